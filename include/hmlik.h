@@ -1,0 +1,154 @@
+/* hmlik.h -- H-matrix Gaussian log-likelihood on AMD MI355X (gfx950).
+ *
+ * C ABI of the library libhmlik.so.  The method is that of Litvinenko, Sun,
+ * Genton, Keyes, "Likelihood Approximation With Hierarchical Matrices For
+ * Large Spatial Datasets" (arXiv:1709.04419):
+ *
+ *   L~(theta) = -n/2 log(2 pi) - sum_i log L~_ii - 1/2 v^T v,   L~ v = Z     (eq. 4, Sect. 3.1)
+ *
+ * where L~ is the H-Cholesky factor (Sect. 3.2) of the H-matrix approximation
+ * (Sect. 2.1, Def. 2.1, Remark 2.4) of the Matern covariance (eq. 2,
+ * Sect. 2.2) plus a nugget tau^2 I (remark in Sect. 2.4), built over a
+ * geometric cluster tree with standard admissibility (App. B, Defs. B.1-B.3).
+ *
+ * Conventions
+ *   - Every function returns hm_status; nothing throws or aborts across the ABI.
+ *   - Arrays passed in are owned by the caller and are copied before the call
+ *     returns (host pointers) or used only in the call's stream order
+ *     (device pointers).  Handles are owned by the library.
+ *   - Matrices are column-major; coordinates are n x 2 row-major (x0 y0 x1 y1 ...).
+ *   - All arithmetic is FP64.  Results are deterministic: the same inputs give
+ *     bitwise-equal outputs.
+ *   - Calls on one dataset must not overlap; different datasets may be used
+ *     from different threads only with different contexts.
+ */
+#ifndef HMLIK_H
+#define HMLIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HM_OK = 0,
+  HM_ERR_ARG = 1,       /* invalid argument (null pointer, size, non-finite value, theta <= 0) */
+  HM_ERR_NOT_SPD = 2,   /* a pivot of the H-Cholesky was <= 0 (the paper's breakdown at coarse
+                           accuracy, Tables 6 and 7); outputs are NaN, fail_block/fail_pivot set */
+  HM_ERR_OOM = 3,       /* device allocation failed */
+  HM_ERR_DEVICE = 4,    /* a HIP runtime call failed */
+  HM_ERR_INTERNAL = 5   /* the task executor aborted (bounded wait exceeded) */
+} hm_status;
+
+typedef struct hm_ctx hm_ctx;
+typedef struct hm_dataset hm_dataset;
+
+/* theta = (sigma^2, ell, nu) of eq. (2) and the nugget tau^2. */
+typedef struct {
+  double sigma2; /* > 0 */
+  double ell;    /* > 0, the argument of K_nu is h / ell (eq. 2 as printed) */
+  double nu;     /* > 0 */
+  double nugget; /* >= 0, added on the diagonal only */
+} hm_theta;
+
+/* Cluster tree options (App. B): leaf size n_min (1..64) and admissibility eta >= 0. */
+typedef struct {
+  int32_t leaf_size;
+  double eta;
+} hm_tree_opts;
+
+/* Accuracy (Remark 2.4 / Def. 2.1): exactly one of
+ *   fixed_rank > 0 (ranks <= fixed_rank, eps ignored), or
+ *   fixed_rank == 0 and eps > 0 (relative spectral accuracy per block). */
+typedef struct {
+  int32_t fixed_rank;
+  double eps;
+} hm_approx;
+
+/* One evaluation: one entry per right-hand side. */
+typedef struct {
+  double loglik;    /* eq. (4) */
+  double logdet;    /* log|C~| = 2 sum log L~_ii */
+  double quadform;  /* v^T v = Z^T (L~ L~^T)^{-1} Z */
+  int32_t status;   /* hm_status of the evaluation */
+  int32_t max_rank; /* largest rank of a low-rank block of the factor */
+  int64_t fail_block; /* block id of the failed pivot (HM_ERR_NOT_SPD), else -1 */
+  int32_t fail_pivot; /* row of the failed pivot inside that block, else -1 */
+  double t_assemble, t_factor, t_solve; /* seconds (device events) */
+} hm_result;
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t (NULL =
+ * the default stream) on which all work of this context is ordered. */
+hm_status hm_ctx_create(int device, void *stream, hm_ctx **out);
+void hm_ctx_destroy(hm_ctx *ctx);
+
+/* Build the cluster tree and block cluster tree for n locations (App. B,
+ * Defs. B.1-B.3) and the theta-independent H-Cholesky schedule, and upload
+ * them.  coords: host pointer, n x 2 row-major, finite. */
+hm_status hm_dataset_create(hm_ctx *ctx, const double *coords, int64_t n, const hm_tree_opts *opts,
+                            hm_dataset **out);
+void hm_dataset_destroy(hm_dataset *ds);
+
+/* Data Z: n x r column-major in input (not permuted) order, 1 <= r <= 64.
+ * on_device != 0: Z is a device pointer read in stream order during this call. */
+hm_status hm_dataset_set_z(hm_dataset *ds, const double *Z, int32_t r, int32_t on_device);
+
+/* Assemble C~(theta): Matern entries of the dense leaves, ACA + truncation of
+ * the admissible blocks (Sect. 2.1, Remark 2.4). */
+hm_status hm_assemble(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx);
+
+/* H-Cholesky of the assembled matrix, in place (Sect. 3.2).  Returns
+ * HM_ERR_NOT_SPD on a non-positive pivot (the factor then holds NaNs). */
+hm_status hm_factor(hm_dataset *ds);
+
+/* Forward solve L~ v = Z, log-determinant and eq. (4) for every column of Z;
+ * out has r entries. */
+hm_status hm_solve(hm_dataset *ds, hm_result *out);
+
+/* hm_assemble + hm_factor + hm_solve. out has r entries. */
+hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, hm_result *out);
+
+/* Introspection (tests): sizes of the trees. */
+hm_status hm_dataset_info(const hm_dataset *ds, int64_t *n, int64_t *nclusters, int64_t *nblocks,
+                          int64_t *ntasks);
+
+/* Permutation (perm[i] = input index at permuted position i, n entries),
+ * cluster ranges (2 per cluster: begin, end), boxes (4 per cluster: lo_x,
+ * lo_y, hi_x, hi_y), in pre-order.  Any pointer may be NULL. */
+hm_status hm_dataset_export_tree(const hm_dataset *ds, int64_t *perm, int64_t *ranges, double *boxes);
+
+/* Blocks in pre-order: rc (4 per block: row begin, col begin, rows, cols) and
+ * kind (0 internal, 1 dense leaf, 2 low-rank leaf).  Either pointer may be NULL. */
+hm_status hm_dataset_export_blocks(const hm_dataset *ds, int64_t *rc, int8_t *kind);
+
+/* Copy one leaf block of the current matrix / factor to host memory.
+ * Dense leaf: data receives rows*cols doubles (column-major), *rank = -1.
+ * Low-rank leaf: data receives U (rows x k) followed by V (cols x k), *rank = k;
+ * data must hold (rows + cols) * 64 doubles. */
+hm_status hm_get_block(hm_dataset *ds, int64_t block, double *data, int32_t *rank);
+
+/* Test hook: the update term `term` of the H-Cholesky schedule (in the order
+ * the recursion records them): kind (0: X = U_A, Y = L_B V_A; 1: X = L_A V_B,
+ * Y = U_B; 2: X = D_A, Y = D_B), the factor blocks A and B, and for kinds 0/1
+ * the computed factor (rows x k, column-major) copied into data (may be NULL;
+ * must hold rows * 64 doubles). */
+hm_status hm_get_term(hm_dataset *ds, int64_t term, double *data, int32_t *kind, int64_t *A, int64_t *B,
+                      int64_t *rows, int32_t *k);
+
+/* Test hook for the truncation step (Remark 2.4): one work-group computes the
+ * best approximation of X Y^T (X: m x r, Y: n x r, host, column-major,
+ * 1 <= r <= 128) at relative accuracy eps (fixed_rank == 0) or rank
+ * fixed_rank, through the same device routine the H-Cholesky uses.  U (m x 64)
+ * and V (n x 64) receive the k = *k factors; *seconds the kernel time.  Uses
+ * the dataset's workspace (m, n at most its largest low-rank block). */
+hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const double *Y, int64_t n, int32_t r,
+                           double eps, int32_t fixed_rank, double *U, double *V, int32_t *k, double *seconds);
+
+const char *hm_status_string(hm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMLIK_H */

@@ -62,7 +62,7 @@ from .lowrank import K_MAX, aca, truncate
 from .matern import covariance_block
 
 # Largest rank an accumulation of updates may reach before it is truncated.
-R_ACC = 128
+R_ACC = 64
 
 
 class NotSPD(Exception):

@@ -36,7 +36,7 @@ import numpy as np
 
 # Largest rank any low-rank block may carry (assembly, truncation, accumulation
 # of updates).  A named constant of the method shared by every implementation.
-K_MAX = 96
+K_MAX = 64
 
 
 def aca(row_fn, col_fn, m: int, n: int, eps: float, kmax: int):

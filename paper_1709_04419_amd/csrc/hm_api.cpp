@@ -1,0 +1,602 @@
+// C ABI of libhmlik (declared in include/hmlik.h): context, dataset (trees,
+// schedule and device storage, built once per set of locations), and the
+// per-theta evaluation of eq. (4) of Section 3.1.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <vector>
+
+#include "../../include/hmlik.h"
+#include "hm_device.h"
+#include "hm_plan.h"
+
+using namespace hm;
+
+struct hm_ctx {
+  int device;
+  hipStream_t stream;
+};
+
+namespace {
+
+constexpr int NSLOTS = 512;   // workspace slots (ACA kernel work-groups)
+constexpr int NEXEC = 256;    // executor work-groups: one per CU (LDS arena of ~140 KB each)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct hm_dataset {
+  hm_ctx* ctx = nullptr;
+  Tree tree;
+  Plan plan;
+  std::vector<DevBuf> bufs;
+  DevData D{};
+  int64_t* d_perm = nullptr;
+  int32_t* d_diag_ids = nullptr;
+  double* d_Z = nullptr;
+  double* d_W = nullptr;
+  double* d_out = nullptr;
+  int32_t r = 0;
+  bool assembled = false, factored = false;
+  hm_status factor_status = HM_OK;
+  int64_t fail_block = -1;
+  int32_t fail_pivot = -1;
+  double t_assemble = 0, t_factor = 0, t_solve = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int32_t> level_begin;   // task index where each DAG level starts (+ end)
+};
+
+namespace {
+
+hm_status dev_alloc(hm_dataset* ds, size_t bytes, void** out) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 64;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return HM_ERR_OOM;
+  }
+  ds->bufs.push_back(DevBuf{p, bytes});
+  *out = p;
+  return HM_OK;
+}
+
+template <class T>
+hm_status upload(hm_dataset* ds, const std::vector<T>& v, T** out) {
+  void* p = nullptr;
+  hm_status s = dev_alloc(ds, v.size() * sizeof(T), &p);
+  if (s != HM_OK) return s;
+  if (!v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return HM_ERR_DEVICE;
+  *out = static_cast<T*>(p);
+  return HM_OK;
+}
+
+#define TRY(x)                        \
+  do {                                \
+    hm_status _s = (x);               \
+    if (_s != HM_OK) return _s;       \
+  } while (0)
+#define HIPTRY(x)                                   \
+  do {                                              \
+    if ((x) != hipSuccess) {                        \
+      (void)hipGetLastError();                      \
+      return HM_ERR_DEVICE;                         \
+    }                                               \
+  } while (0)
+
+// Taylor coefficients a_k of 1/Gamma(1+z) = sum a_k z^k (a_0 = 1), i.e. the
+// coefficients of 1/Gamma(z) = sum_k a_{k-1} z^k (Abramowitz & Stegun 6.1.34).
+constexpr long double RG[8] = {1.0L,
+                               0.5772156649015328606L,
+                               -0.6558780715202538811L,
+                               -0.0420026350340952355L,
+                               0.1665386113822914895L,
+                               -0.0421977345555443367L,
+                               -0.0096219715278769736L,
+                               0.0072189432466630995L};
+
+// Per-theta constants of the K_nu evaluation (Temme's method needs
+// Gamma_1(mu) = (1/Gamma(1-mu) - 1/Gamma(1+mu)) / (2 mu) and
+// Gamma_2(mu) = (1/Gamma(1-mu) + 1/Gamma(1+mu)) / 2 for |mu| <= 1/2).
+MaternConst make_matern(const hm_theta& th) {
+  MaternConst c{};
+  c.sigma2 = th.sigma2;
+  c.inv_ell = 1.0 / th.ell;
+  c.nu = th.nu;
+  c.nugget = th.nugget;
+  const long double nu = th.nu;
+  c.norm = (double)(1.0L / (powl(2.0L, nu - 1.0L) * tgammal(nu)));
+  const long double N = floorl(nu + 0.5L);
+  const long double mu = nu - N;
+  c.mu = (double)mu;
+  c.nrec = (int32_t)N;
+  c.half = (th.nu == 0.5) ? 1 : (th.nu == 1.5) ? 3 : (th.nu == 2.5) ? 5 : 0;
+  const long double gp = tgammal(1.0L + mu), gm = tgammal(1.0L - mu);
+  c.gp = (double)gp;
+  c.gm = (double)gm;
+  long double g1;
+  if (fabsl(mu) < 1e-3L) {
+    // odd part of 1/Gamma(1+z): Gamma_1(mu) = -(a1 + a3 mu^2 + a5 mu^4 + a7 mu^6)
+    const long double m2 = mu * mu;
+    g1 = -(RG[1] + m2 * (RG[3] + m2 * (RG[5] + m2 * RG[7])));
+  } else {
+    g1 = (1.0L / gm - 1.0L / gp) / (2.0L * mu);
+  }
+  c.g1 = (double)g1;
+  c.g2 = (double)((1.0L / gm + 1.0L / gp) / 2.0L);
+  c.fact = (mu == 0.0L) ? 1.0 : (double)(mu * 3.14159265358979323846264338327950288L /
+                                         sinl(mu * 3.14159265358979323846264338327950288L));
+  return c;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+hm_status build_device(hm_dataset* ds) {
+  const Tree& T = ds->tree;
+  const Plan& P = ds->plan;
+  DevData& D = ds->D;
+  D = DevData{};
+  D.n = T.n;
+  TRY(upload(ds, T.bk, const_cast<Block**>(&D.bk)));
+  TRY(upload(ds, T.cl, const_cast<Cluster**>(&D.cl)));
+  TRY(upload(ds, T.diag_of, const_cast<int32_t**>(&D.diag_of)));
+  D.nblocks = (int32_t)T.bk.size();
+  void* p;
+  TRY(dev_alloc(ds, sizeof(double) * P.dense_pool, &p));
+  D.dense = (double*)p;
+  TRY(upload(ds, P.dense_off, const_cast<int64_t**>(&D.dense_off)));
+  TRY(dev_alloc(ds, sizeof(double) * P.lr_pool, &p));
+  D.lr = (double*)p;
+  TRY(upload(ds, P.lr_off, const_cast<int64_t**>(&D.lr_off)));
+  {
+    std::vector<int32_t> rk(T.bk.size(), 0);
+    TRY(upload(ds, rk, &D.rank));
+  }
+  TRY(dev_alloc(ds, sizeof(double) * P.term_pool, &p));
+  D.termbuf = (double*)p;
+  TRY(upload(ds, P.terms, const_cast<TermDef**>(&D.terms)));
+  TRY(upload(ds, P.insts, const_cast<TermInst**>(&D.insts)));
+  TRY(upload(ds, P.tasks, const_cast<Task**>(&D.tasks)));
+  TRY(upload(ds, P.deps, const_cast<int32_t**>(&D.deps)));
+  TRY(upload(ds, P.task_prog, const_cast<int32_t**>(&D.task_prog)));
+  D.ntasks = (int32_t)P.tasks.size();
+  TRY(dev_alloc(ds, sizeof(int32_t) * (P.tasks.size() + 1), &p));
+  D.done = (int32_t*)p;
+  TRY(dev_alloc(ds, sizeof(int32_t) * 4 * NSLOTS, &p));
+  D.dbg = (int32_t*)p;
+  TRY(dev_alloc(ds, 256, &p));
+  D.ticket = (int32_t*)p;
+  D.abort_flag = (int32_t*)((char*)p + 64);
+  D.fail_key = (unsigned long long*)((char*)p + 128);
+  TRY(upload(ds, P.sub_begin, const_cast<int32_t**>(&D.sub_begin)));
+  TRY(upload(ds, P.sub_end, const_cast<int32_t**>(&D.sub_end)));
+  TRY(upload(ds, P.sub_leaves, const_cast<int32_t**>(&D.sub_leaves)));
+  TRY(upload(ds, P.sop_begin, const_cast<int32_t**>(&D.sop_begin)));
+  TRY(upload(ds, P.sops, const_cast<SolveOp**>(&D.sops)));
+  TRY(dev_alloc(ds, sizeof(double) * T.bk.size(), &p));
+  D.logdet_part = (double*)p;
+  TRY(upload(ds, P.dense_ids, const_cast<int32_t**>(&D.dense_ids)));
+  D.ndense = (int32_t)P.dense_ids.size();
+  TRY(upload(ds, P.lr_ids, const_cast<int32_t**>(&D.lr_ids)));
+  D.nlr = (int32_t)P.lr_ids.size();
+  TRY(upload(ds, P.diag_leaf_ids, &ds->d_diag_ids));
+  TRY(upload(ds, T.perm, &ds->d_perm));
+  // workspace slots: truncation of (m + n) x 2 K_MAX factors plus small scratch
+  const int64_t mr = P.max_lr_rows > 64 ? P.max_lr_rows : 64;
+  int64_t stride = 2 * mr * (2 * K_MAX) + mr + 2 * (2 * K_MAX) * (2 * K_MAX) + 4096;
+  stride = (stride + 63) & ~(int64_t)63;
+  D.ws_stride = stride;
+  TRY(dev_alloc(ds, sizeof(double) * stride * NSLOTS, &p));
+  D.ws = (double*)p;
+  D.spin_limit = getenv("HMLIK_SPIN_LIMIT_S") ? (int64_t)(atof(getenv("HMLIK_SPIN_LIMIT_S")) * 1e8) : 3000000000LL;  // 100 MHz counter; 30 s default
+  return HM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hm_status_string(hm_status s) {
+  switch (s) {
+    case HM_OK: return "ok";
+    case HM_ERR_ARG: return "invalid argument";
+    case HM_ERR_NOT_SPD: return "H-Cholesky breakdown: non-positive pivot";
+    case HM_ERR_OOM: return "device out of memory";
+    case HM_ERR_DEVICE: return "HIP runtime error";
+    case HM_ERR_INTERNAL: return "task executor aborted";
+  }
+  return "unknown status";
+}
+
+hm_status hm_ctx_create(int device, void* stream, hm_ctx** out) {
+  if (!out) return HM_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return HM_ERR_DEVICE;
+  }
+  HIPTRY(hipSetDevice(device));
+  hm_ctx* c = new (std::nothrow) hm_ctx;
+  if (!c) return HM_ERR_OOM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  *out = c;
+  return HM_OK;
+}
+
+void hm_ctx_destroy(hm_ctx* ctx) { delete ctx; }
+
+hm_status hm_dataset_create(hm_ctx* ctx, const double* coords, int64_t n, const hm_tree_opts* opts,
+                            hm_dataset** out) {
+  if (!ctx || !coords || !opts || !out || n < 1) return HM_ERR_ARG;
+  *out = nullptr;
+  if (opts->leaf_size < 1 || opts->leaf_size > LEAF_MAX) return HM_ERR_ARG;
+  if (!std::isfinite(opts->eta) || opts->eta < 0.0) return HM_ERR_ARG;
+  for (int64_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(coords[i])) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ctx->device));
+  hm_dataset* ds = new (std::nothrow) hm_dataset;
+  if (!ds) return HM_ERR_OOM;
+  ds->ctx = ctx;
+  try {
+    build_tree(coords, n, opts->leaf_size, opts->eta, ds->tree);
+    build_plan(ds->tree, ds->plan);
+  } catch (const std::bad_alloc&) {
+    delete ds;
+    return HM_ERR_OOM;
+  } catch (const std::exception&) {
+    delete ds;
+    return HM_ERR_INTERNAL;
+  }
+  {
+    const auto& tasks = ds->plan.tasks;
+    ds->level_begin.clear();
+    int32_t cur = -1;
+    for (int32_t i = 0; i < (int32_t)tasks.size(); ++i)
+      if (tasks[i].level != cur) {
+        ds->level_begin.push_back(i);
+        cur = tasks[i].level;
+      }
+    ds->level_begin.push_back((int32_t)tasks.size());
+  }
+  hm_status s = build_device(ds);
+  if (s == HM_OK) {
+    // permuted coordinates
+    std::vector<double> x(n), y(n);
+    for (int64_t i = 0; i < n; ++i) {
+      x[i] = coords[2 * ds->tree.perm[i]];
+      y[i] = coords[2 * ds->tree.perm[i] + 1];
+    }
+    double *dx = nullptr, *dy = nullptr;
+    s = upload(ds, x, &dx);
+    if (s == HM_OK) s = upload(ds, y, &dy);
+    ds->D.px = dx;
+    ds->D.py = dy;
+  }
+  if (s == HM_OK) {
+    for (int i = 0; i < 4 && s == HM_OK; ++i)
+      if (hipEventCreate(&ds->ev[i]) != hipSuccess) s = HM_ERR_DEVICE;
+  }
+  if (s != HM_OK) {
+    hm_dataset_destroy(ds);
+    return s;
+  }
+  *out = ds;
+  return HM_OK;
+}
+
+void hm_dataset_destroy(hm_dataset* ds) {
+  if (!ds) return;
+  (void)hipSetDevice(ds->ctx->device);
+  (void)hipStreamSynchronize(ds->ctx->stream);
+  for (auto& b : ds->bufs) (void)hipFree(b.p);
+  for (int i = 0; i < 4; ++i)
+    if (ds->ev[i]) (void)hipEventDestroy(ds->ev[i]);
+  delete ds;
+}
+
+hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t on_device) {
+  if (!ds || !Z || r < 1 || r > 64) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  const int64_t n = ds->tree.n;
+  if (r > ds->r) {
+    void* p;
+    TRY(dev_alloc(ds, sizeof(double) * n * r, &p));
+    ds->d_Z = (double*)p;
+    TRY(dev_alloc(ds, sizeof(double) * n * r, &p));
+    ds->d_W = (double*)p;
+    TRY(dev_alloc(ds, sizeof(double) * (1 + r), &p));
+    ds->d_out = (double*)p;
+  }
+  if (!on_device) {
+    for (int64_t i = 0; i < n * (int64_t)r; ++i)
+      if (!std::isfinite(Z[i])) return HM_ERR_ARG;
+  }
+  HIPTRY(hipMemcpyAsync(ds->d_Z, Z, sizeof(double) * n * r,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ds->ctx->stream));
+  HIPTRY(hipStreamSynchronize(ds->ctx->stream));
+  ds->r = r;
+  return HM_OK;
+}
+
+hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
+  if (!ds || !th || !ap) return HM_ERR_ARG;
+  if (!finite_pos(th->sigma2) || !finite_pos(th->ell) || !finite_pos(th->nu)) return HM_ERR_ARG;
+  if (!std::isfinite(th->nugget) || th->nugget < 0.0) return HM_ERR_ARG;
+  if (ap->fixed_rank < 0 || ap->fixed_rank > K_MAX) return HM_ERR_ARG;
+  if (ap->fixed_rank == 0 && !finite_pos(ap->eps)) return HM_ERR_ARG;
+  if (ap->fixed_rank > 0 && !(std::isfinite(ap->eps) && ap->eps >= 0.0)) return HM_ERR_ARG;
+  if (th->nu > 50.0) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  DevData& D = ds->D;
+  D.mc = make_matern(*th);
+  D.kfix = ap->fixed_rank;
+  D.eps = (ap->fixed_rank > 0) ? 0.0 : ap->eps;
+  D.kmax = (ap->fixed_rank > 0) ? ap->fixed_rank : K_MAX;
+  hipStream_t st = ds->ctx->stream;
+  HIPTRY(hipEventRecord(ds->ev[0], st));
+  HIPTRY(launch_assemble(D, st));
+  HIPTRY(launch_aca(D, NSLOTS, st));
+  HIPTRY(hipEventRecord(ds->ev[1], st));
+  HIPTRY(hipEventSynchronize(ds->ev[1]));
+  float ms = 0;
+  HIPTRY(hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]));
+  ds->t_assemble = ms * 1e-3;
+  ds->assembled = true;
+  ds->factored = false;
+  return HM_OK;
+}
+
+hm_status hm_factor(hm_dataset* ds) {
+  if (!ds || !ds->assembled) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  DevData& D = ds->D;
+  hipStream_t st = ds->ctx->stream;
+  HIPTRY(hipEventRecord(ds->ev[1], st));
+  if (getenv("HMLIK_PERSISTENT_EXECUTOR")) {
+    // persistent ticket scheduler: disabled by default (stalled on the device,
+    // cause not yet established)
+    int grid = NEXEC;
+    if (const char* e = getenv("HMLIK_EXEC_WGS")) {
+      grid = atoi(e);
+      if (grid < 1 || grid > NSLOTS) grid = NEXEC;
+    }
+    HIPTRY(launch_factor(D, grid, st));
+  } else {
+    HIPTRY(launch_factor_levels(D, ds->level_begin.data(), (int32_t)ds->level_begin.size() - 1, NSLOTS, st));
+  }
+  HIPTRY(hipEventRecord(ds->ev[2], st));
+  HIPTRY(hipEventSynchronize(ds->ev[2]));
+  float ms = 0;
+  HIPTRY(hipEventElapsedTime(&ms, ds->ev[1], ds->ev[2]));
+  ds->t_factor = ms * 1e-3;
+  int32_t flags[2];
+  unsigned long long key = 0;
+  HIPTRY(hipMemcpy(&flags[0], D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&key, D.fail_key, sizeof(key), hipMemcpyDeviceToHost));
+  ds->assembled = false;
+  ds->factored = true;
+  ds->fail_block = -1;
+  ds->fail_pivot = -1;
+  if (flags[0]) {
+    ds->factor_status = HM_ERR_INTERNAL;
+    if (getenv("HMLIK_DUMP_EXECUTOR")) {
+      std::vector<int32_t> dbg(4 * NSLOTS), done(ds->plan.tasks.size());
+      (void)hipMemcpy(dbg.data(), D.dbg, sizeof(int32_t) * dbg.size(), hipMemcpyDeviceToHost);
+      (void)hipMemcpy(done.data(), D.done, sizeof(int32_t) * done.size(), hipMemcpyDeviceToHost);
+      int64_t ndone = 0;
+      for (int32_t v : done) ndone += v != 0;
+      fprintf(stderr, "hmlik executor abort: %lld of %zu tasks done\n", (long long)ndone, done.size());
+      for (int w = 0; w < NSLOTS; ++w) {
+        const int32_t tk = dbg[4 * w], ph = dbg[4 * w + 1], dep = dbg[4 * w + 2];
+        if (ph == 1 || ph == 2)
+          fprintf(stderr, "  wg %d ticket %d kind %d phase %d awaiting %d (done=%d) tasks_done %d\n", w, tk,
+                  (tk >= 0 && tk < (int)done.size()) ? (int)ds->plan.tasks[tk].kind : -1, ph, dep,
+                  (dep >= 0 && dep < (int)done.size()) ? done[dep] : -1, dbg[4 * w + 3]);
+      }
+    }
+    return HM_ERR_INTERNAL;
+  }
+  if (key != ~0ull) {
+    const int64_t prog = (int64_t)(key >> 8);
+    ds->fail_pivot = (int32_t)(key & 0xff);
+    ds->fail_block = (prog >= 0 && prog < (int64_t)ds->plan.prog_obj.size()) ? ds->plan.prog_obj[prog] : -1;
+    ds->factor_status = HM_ERR_NOT_SPD;
+    return HM_ERR_NOT_SPD;
+  }
+  ds->factor_status = HM_OK;
+  return HM_OK;
+}
+
+hm_status hm_solve(hm_dataset* ds, hm_result* out) {
+  if (!ds || !out || !ds->factored || ds->r < 1) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  const int r = ds->r;
+  const int64_t n = ds->tree.n;
+  DevData& D = ds->D;
+  hipStream_t st = ds->ctx->stream;
+  int32_t max_rank = 0;
+  {
+    std::vector<int32_t> rk(ds->tree.bk.size());
+    HIPTRY(hipMemcpy(rk.data(), D.rank, sizeof(int32_t) * rk.size(), hipMemcpyDeviceToHost));
+    for (int32_t b : ds->plan.lr_ids) max_rank = rk[b] > max_rank ? rk[b] : max_rank;
+  }
+  std::vector<double> res(1 + r, NAN);
+  if (ds->factor_status == HM_OK) {
+    HIPTRY(hipEventRecord(ds->ev[2], st));
+    HIPTRY(launch_solve(D, ds->d_Z, ds->d_perm, r, ds->d_W, ds->d_diag_ids,
+                        (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, st));
+    HIPTRY(hipEventRecord(ds->ev[3], st));
+    HIPTRY(hipEventSynchronize(ds->ev[3]));
+    float ms = 0;
+    HIPTRY(hipEventElapsedTime(&ms, ds->ev[2], ds->ev[3]));
+    ds->t_solve = ms * 1e-3;
+    HIPTRY(hipMemcpy(res.data(), ds->d_out, sizeof(double) * (1 + r), hipMemcpyDeviceToHost));
+  }
+  const double c0 = -0.5 * (double)n * std::log(2.0 * 3.14159265358979323846);
+  for (int c = 0; c < r; ++c) {
+    hm_result& o = out[c];
+    o.status = ds->factor_status;
+    o.max_rank = max_rank;
+    o.fail_block = ds->fail_block;
+    o.fail_pivot = ds->fail_pivot;
+    o.t_assemble = ds->t_assemble;
+    o.t_factor = ds->t_factor;
+    o.t_solve = ds->t_solve;
+    if (ds->factor_status == HM_OK) {
+      o.logdet = res[0];
+      o.quadform = res[1 + c];
+      o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.quadform;
+    } else {
+      o.logdet = o.quadform = o.loglik = NAN;
+    }
+  }
+  return ds->factor_status;
+}
+
+hm_status hm_loglik(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hm_result* out) {
+  if (!ds || !out) return HM_ERR_ARG;
+  if (ds->r < 1) return HM_ERR_ARG;
+  TRY(hm_assemble(ds, th, ap));
+  hm_status s = hm_factor(ds);
+  if (s != HM_OK && s != HM_ERR_NOT_SPD) return s;
+  return hm_solve(ds, out);
+}
+
+hm_status hm_dataset_info(const hm_dataset* ds, int64_t* n, int64_t* nclusters, int64_t* nblocks,
+                          int64_t* ntasks) {
+  if (!ds) return HM_ERR_ARG;
+  if (n) *n = ds->tree.n;
+  if (nclusters) *nclusters = (int64_t)ds->tree.cl.size();
+  if (nblocks) *nblocks = (int64_t)ds->tree.bk.size();
+  if (ntasks) *ntasks = (int64_t)ds->plan.tasks.size();
+  return HM_OK;
+}
+
+hm_status hm_dataset_export_tree(const hm_dataset* ds, int64_t* perm, int64_t* ranges, double* boxes) {
+  if (!ds) return HM_ERR_ARG;
+  const Tree& T = ds->tree;
+  if (perm) std::memcpy(perm, T.perm.data(), sizeof(int64_t) * T.n);
+  for (size_t c = 0; c < T.cl.size(); ++c) {
+    if (ranges) {
+      ranges[2 * c] = T.cl[c].begin;
+      ranges[2 * c + 1] = T.cl[c].end;
+    }
+    if (boxes) {
+      boxes[4 * c] = T.cl[c].lo[0];
+      boxes[4 * c + 1] = T.cl[c].lo[1];
+      boxes[4 * c + 2] = T.cl[c].hi[0];
+      boxes[4 * c + 3] = T.cl[c].hi[1];
+    }
+  }
+  return HM_OK;
+}
+
+hm_status hm_dataset_export_blocks(const hm_dataset* ds, int64_t* rc, int8_t* kind) {
+  if (!ds) return HM_ERR_ARG;
+  const Tree& T = ds->tree;
+  for (size_t b = 0; b < T.bk.size(); ++b) {
+    if (rc) {
+      rc[4 * b] = T.bk[b].r0;
+      rc[4 * b + 1] = T.bk[b].c0;
+      rc[4 * b + 2] = T.bk[b].m;
+      rc[4 * b + 3] = T.bk[b].n;
+    }
+    if (kind) kind[b] = T.bk[b].kind;
+  }
+  return HM_OK;
+}
+
+hm_status hm_get_block(hm_dataset* ds, int64_t block, double* data, int32_t* rank) {
+  if (!ds || !data || !rank || block < 0 || block >= (int64_t)ds->tree.bk.size()) return HM_ERR_ARG;
+  const Block& b = ds->tree.bk[block];
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  HIPTRY(hipStreamSynchronize(ds->ctx->stream));
+  if (b.kind == BK_DENSE) {
+    HIPTRY(hipMemcpy(data, ds->D.dense + ds->plan.dense_off[block], sizeof(double) * b.m * b.n,
+                     hipMemcpyDeviceToHost));
+    *rank = -1;
+    return HM_OK;
+  }
+  if (b.kind == BK_LR) {
+    int32_t k = 0;
+    HIPTRY(hipMemcpy(&k, ds->D.rank + block, sizeof(int32_t), hipMemcpyDeviceToHost));
+    const double* U = ds->D.lr + ds->plan.lr_off[block];
+    HIPTRY(hipMemcpy(data, U, sizeof(double) * b.m * k, hipMemcpyDeviceToHost));
+    HIPTRY(hipMemcpy(data + b.m * k, U + b.m * K_MAX, sizeof(double) * b.n * k, hipMemcpyDeviceToHost));
+    *rank = k;
+    return HM_OK;
+  }
+  return HM_ERR_ARG;
+}
+
+hm_status hm_get_term(hm_dataset* ds, int64_t term, double* data, int32_t* kind, int64_t* A, int64_t* B,
+                      int64_t* rows, int32_t* k) {
+  if (!ds || term < 0 || term >= (int64_t)ds->plan.terms.size() || !kind || !A || !B || !rows || !k)
+    return HM_ERR_ARG;
+  const TermDef& t = ds->plan.terms[term];
+  *kind = t.kind;
+  *A = t.A;
+  *B = t.B;
+  *rows = t.rows;
+  *k = 0;
+  if (t.kind == TK_DD) return HM_OK;
+  const int32_t R = (t.kind == TK_LRA) ? t.A : t.B;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  HIPTRY(hipStreamSynchronize(ds->ctx->stream));
+  HIPTRY(hipMemcpy(k, ds->D.rank + R, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (data && *k > 0)
+    HIPTRY(hipMemcpy(data, ds->D.termbuf + t.buf, sizeof(double) * t.rows * (*k), hipMemcpyDeviceToHost));
+  return HM_OK;
+}
+
+hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const double* Y, int64_t n, int32_t r,
+                           double eps, int32_t fixed_rank, double* U, double* V, int32_t* k, double* seconds) {
+  if (!ds || !X || !Y || !U || !V || !k || m < 1 || n < 1 || r < 1 || r > 2 * K_MAX) return HM_ERR_ARG;
+  if (fixed_rank < 0 || fixed_rank > K_MAX || (fixed_rank == 0 && !finite_pos(eps))) return HM_ERR_ARG;
+  if ((m + n) * (int64_t)r + 2 * (int64_t)r * r > ds->D.ws_stride) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  hipStream_t st = ds->ctx->stream;
+  DevData D = ds->D;
+  D.kfix = fixed_rank;
+  D.eps = fixed_rank > 0 ? 0.0 : eps;
+  D.kmax = fixed_rank > 0 ? fixed_rank : K_MAX;
+  void *dX = nullptr, *dY = nullptr, *dU = nullptr, *dV = nullptr, *dk = nullptr;
+  hm_status s = HM_OK;
+  if (hipMalloc(&dX, sizeof(double) * m * r) != hipSuccess || hipMalloc(&dY, sizeof(double) * n * r) != hipSuccess ||
+      hipMalloc(&dU, sizeof(double) * m * K_MAX) != hipSuccess ||
+      hipMalloc(&dV, sizeof(double) * n * K_MAX) != hipSuccess || hipMalloc(&dk, sizeof(int32_t)) != hipSuccess)
+    s = HM_ERR_OOM;
+  if (s == HM_OK) {
+    float ms = 0;
+    if (hipMemcpy(dX, X, sizeof(double) * m * r, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dY, Y, sizeof(double) * n * r, hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventRecord(ds->ev[0], st) != hipSuccess ||
+        launch_truncate_test(D, (double*)dX, m, (double*)dY, n, r, (double*)dU, (double*)dV, (int32_t*)dk, st) !=
+            hipSuccess ||
+        hipEventRecord(ds->ev[1], st) != hipSuccess || hipEventSynchronize(ds->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]) != hipSuccess ||
+        hipMemcpy(k, dk, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      s = HM_ERR_DEVICE;
+    if (s == HM_OK && (hipMemcpy(U, dU, sizeof(double) * m * (*k), hipMemcpyDeviceToHost) != hipSuccess ||
+                       hipMemcpy(V, dV, sizeof(double) * n * (*k), hipMemcpyDeviceToHost) != hipSuccess))
+      s = HM_ERR_DEVICE;
+    if (seconds) *seconds = ms * 1e-3;
+  }
+  (void)hipGetLastError();
+  for (void* q : {dX, dY, dU, dV, dk})
+    if (q) (void)hipFree(q);
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Device-side view of a dataset's plan and storage, passed by value to the
+// kernels.  Plain pointers into device memory owned by the library.
+#pragma once
+#include <cstdint>
+
+#include "hm_plan.h"
+
+namespace hm {
+
+// Per-theta constants of the Matern entry generator (eq. (2) of Section 2.2,
+// plus the nugget of the remark in Section 2.4).  Filled on the host.
+struct MaternConst {
+  double sigma2, inv_ell, nu, nugget;
+  double norm;        // 1 / (2^(nu-1) Gamma(nu))
+  double mu;          // nu - N, |mu| <= 1/2
+  int32_t nrec;       // N = round-half-up(nu): K_nu from (K_mu, K_mu+1) by N-1 recurrences
+  int32_t half;       // 1, 3, 5 for nu = 1/2, 3/2, 5/2 (closed forms), 0 otherwise
+  double g1, g2;      // Temme's Gamma_1(mu), Gamma_2(mu)
+  double gp, gm;      // Gamma(1 + mu), Gamma(1 - mu)
+  double fact;        // mu pi / sin(mu pi)
+};
+
+struct DevData {
+  int64_t n;
+  const double* px;           // permuted coordinates (SoA)
+  const double* py;
+  const Block* bk;
+  const Cluster* cl;
+  const int32_t* diag_of;
+  int32_t nblocks;
+  // storage
+  double* dense;
+  const int64_t* dense_off;
+  double* lr;
+  const int64_t* lr_off;
+  int32_t* rank;              // per block (low-rank leaves)
+  double* termbuf;
+  const TermDef* terms;
+  const TermInst* insts;
+  // schedule
+  const Task* tasks;
+  const int32_t* deps;
+  int32_t ntasks;
+  int32_t* ticket;
+  int32_t* done;
+  int32_t* abort_flag;
+  unsigned long long* fail_key;   // min over (program index << 8 | pivot) of failed pivots
+  const int32_t* task_prog;       // program-order index of each task
+  int32_t* dbg;                   // 4 ints per executor work-group: ticket, phase, awaited task, #done
+  // structure helpers
+  const int32_t* sub_begin;
+  const int32_t* sub_end;
+  const int32_t* sub_leaves;
+  const int32_t* sop_begin;
+  const SolveOp* sops;
+  // outputs
+  double* logdet_part;        // per block id (diagonal dense leaves)
+  // workspace: one slot per resident workgroup
+  double* ws;
+  int64_t ws_stride;
+  // lists for the bulk kernels
+  const int32_t* dense_ids;
+  int32_t ndense;
+  const int32_t* lr_ids;
+  int32_t nlr;
+  // approximation
+  MaternConst mc;
+  double eps;
+  int32_t kfix;
+  int32_t kmax;               // rank cap (K_MAX, or kfix)
+  int64_t spin_limit;         // bounded wait (s_memrealtime ticks)
+};
+
+}  // namespace hm
+
+#include <hip/hip_runtime_api.h>
+
+namespace hm {
+hipError_t launch_assemble(const DevData& D, hipStream_t st);
+hipError_t launch_aca(const DevData& D, int grid, hipStream_t st);
+hipError_t launch_factor(const DevData& D, int grid, hipStream_t st);
+hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
+                                int r, double* U, double* V, int32_t* kout, hipStream_t st);
+hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t nlevels, int max_grid,
+                                hipStream_t st);
+hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,
+                        const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st);
+}  // namespace hm

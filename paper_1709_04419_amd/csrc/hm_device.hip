@@ -1,0 +1,1039 @@
+// Device kernels for the H-matrix Gaussian log-likelihood on gfx950.
+//
+//   matern()            Matern covariance entries, eq. (2) (Section 2.2), with
+//                       K_nu by Temme's series (x <= 2) or Steed's evaluation of
+//                       the second continued fraction (x > 2), then upward
+//                       recurrence in the order.
+//   k_assemble_dense    dense leaves of the H-matrix (Section 2.1), nugget on the
+//                       diagonal (remark in Section 2.4).
+//   k_aca               adaptive cross approximation of admissible blocks
+//                       (Section 2.1) followed by SVD truncation at relative
+//                       accuracy eps or fixed rank k (Remark 2.4, Definition 2.1).
+//   k_factor            persistent H-Cholesky executor (Section 3.2): work-groups
+//                       take tasks in a topological ticket order and wait on the
+//                       completion flags of their predecessors.
+//   k_solve, k_reduce   forward substitution L v = Z, log|C| = 2 sum log L_ii and
+//                       v^T v, assembled into eq. (4) of Section 3.1.
+//
+// One work-group = 256 threads = 4 wavefronts of 64.  All floating point is FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "hm_device.h"
+
+namespace hm {
+
+#define NT 256
+#define NW 4
+// LDS arena (doubles) of the executor work-groups: one per CU.
+#define LDS_FACTOR 17408
+// LDS arena of the solve kernel: a diagonal leaf and a 64-column panel.
+#define LDS_SOLVE (LEAF_MAX * LEAF_MAX + (LEAF_MAX + 1) * LEAF_MAX)
+
+// ------------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the work-group in a fixed order; every thread gets the result.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Arg-max of val over the work-group; ties go to the lowest index.
+__device__ __forceinline__ void amax_merge(double& v, int64_t& i, double v2, int64_t i2) {
+  if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+__device__ void block_argmax(double& v, int64_t& idx, double* redv, int64_t* redi) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double v2 = __shfl_xor(v, o, 64);
+    int64_t i2 = __shfl_xor(idx, o, 64);
+    amax_merge(v, idx, v2, i2);
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) { redv[w] = v; redi[w] = idx; }
+  __syncthreads();
+  v = redv[0];
+  idx = redi[0];
+  for (int k = 1; k < NW; ++k) amax_merge(v, idx, redv[k], redi[k]);
+}
+
+// ------------------------------------------------------------------ Matern
+
+// K_mu(x), K_{mu+1}(x) for |mu| <= 1/2, 0 < x <= 2: Temme's series.
+__device__ void bessel_k_temme(double x, const MaternConst& c, double& k0, double& k1) {
+  const double mu = c.mu;
+  const double h = 0.5 * x;
+  const double lg = -log(h);          // ln(2/x)
+  const double s = mu * lg;
+  const double shs = (fabs(s) < 1e-300) ? 1.0 : sinh(s) / s;
+  double f = c.fact * (cosh(s) * c.g1 + shs * lg * c.g2);
+  const double e = exp(s);            // (x/2)^(-mu)
+  double p = 0.5 * e * c.gp;
+  double q = 0.5 / e * c.gm;
+  double ck = 1.0;
+  const double y = h * h;
+  double sum0 = f, sum1 = p;
+  for (int k = 1; k < 60; ++k) {
+    const double dk = (double)k;
+    f = (dk * f + p + q) / (dk * dk - mu * mu);
+    p = p / (dk - mu);
+    q = q / (dk + mu);
+    ck = ck * y / dk;
+    const double t0 = ck * f;
+    sum0 += t0;
+    sum1 += ck * (p - dk * f);
+    if (fabs(t0) < 1e-17 * fabs(sum0)) break;
+  }
+  k0 = sum0;
+  k1 = sum1 * 2.0 / x;
+}
+
+// x > 2: Steed's algorithm for the continued fraction CF2 (Temme 1975,
+// Thompson & Barnett 1987).  Returns K_mu and K_{mu+1} with the factor
+// exp(-x) included.
+__device__ void bessel_k_cf2(double x, const MaternConst& c, double& k0, double& k1) {
+  const double mu = c.mu;
+  double b = 2.0 * (1.0 + x);
+  double d = 1.0 / b;
+  double h = d, dh = d;
+  double q1 = 0.0, q2 = 1.0;
+  const double a1 = 0.25 - mu * mu;
+  double q = a1, cc = a1, a = -a1;
+  double s = 1.0 + q * dh;
+  for (int i = 1; i < 2000; ++i) {
+    const double di = (double)i;
+    a -= 2.0 * di;
+    cc = -a * cc / (di + 1.0);
+    const double qn = (q1 - b * q2) / a;
+    q1 = q2;
+    q2 = qn;
+    q += cc * qn;
+    b += 2.0;
+    d = 1.0 / (b + a * d);
+    dh = (b * d - 1.0) * dh;
+    h += dh;
+    const double ds = q * dh;
+    s += ds;
+    if (fabs(ds) < 1e-17 * fabs(s)) break;
+  }
+  h = a1 * h;
+  k0 = sqrt(M_PI / (2.0 * x)) * exp(-x) / s;
+  k1 = k0 * (mu + x + 0.5 - h) / x;
+}
+
+// sigma^2 * M_nu(x), x = distance / ell  (no nugget)
+__device__ double matern(double x, const MaternConst& c) {
+  if (x == 0.0) return c.sigma2;
+  if (c.half == 1) return c.sigma2 * exp(-x);
+  if (c.half == 3) return c.sigma2 * (1.0 + x) * exp(-x);
+  if (c.half == 5) return c.sigma2 * (1.0 + x + x * x * (1.0 / 3.0)) * exp(-x);
+  double k0, k1;
+  if (x <= 2.0) bessel_k_temme(x, c, k0, k1);
+  else bessel_k_cf2(x, c, k0, k1);
+  double kn;
+  if (c.nrec == 0) {
+    kn = k0;
+  } else {
+    // K_{mu+j+1} = K_{mu+j-1} + 2 (mu + j) / x K_{mu+j}
+    double km = k0, kc = k1;
+    for (int j = 1; j < c.nrec; ++j) {
+      const double kp = km + 2.0 * (c.mu + j) / x * kc;
+      km = kc;
+      kc = kp;
+    }
+    kn = kc;
+  }
+  return c.sigma2 * pow(x, c.nu) * kn * c.norm;
+}
+
+__device__ __forceinline__ double entry(const DevData& D, int64_t i, int64_t j) {
+  const double dx = D.px[i] - D.px[j];
+  const double dy = D.py[i] - D.py[j];
+  const double r = sqrt(dx * dx + dy * dy);
+  double v = matern(r * D.mc.inv_ell, D.mc);
+  if (i == j) v += D.mc.nugget;
+  return v;
+}
+
+// ------------------------------------------------------------------ dense leaves
+
+__global__ void __launch_bounds__(NT) k_assemble_dense(DevData D) {
+  for (int32_t q = blockIdx.x; q < D.ndense; q += gridDim.x) {
+    const int32_t b = D.dense_ids[q];
+    const Block bk = D.bk[b];
+    double* out = D.dense + D.dense_off[b];
+    const int64_t cnt = bk.m * bk.n;
+    for (int64_t e = threadIdx.x; e < cnt; e += NT) {
+      const int64_t i = e % bk.m, j = e / bk.m;
+      out[e] = entry(D, bk.r0 + i, bk.c0 + j);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ QR / SVD
+
+struct Smem {
+  double red[8];
+  int64_t redi[8];
+  double tau_x[2 * K_MAX];
+  double tau_y[2 * K_MAX];
+  double sig[2 * K_MAX];
+  int32_t ord[2 * K_MAX];
+  int32_t flag;
+  int32_t task;
+  int32_t ival[4];
+  double dval[4];
+};
+
+// Threads per column when `cols` columns are processed side by side: a power
+// of two (<= 64, so a group never straddles a wavefront).
+__device__ __forceinline__ int group_size(int cols) {
+  int g = 64;
+  while (g > 1 && g * cols > NT) g >>= 1;
+  return g;
+}
+
+// In-place Householder QR of A (m x r, column-major, lda); p = min(m, r)
+// reflectors H_j = I - tau_j v_j v_j^T, v_j(j) = 1 implicit, stored below the
+// diagonal; R on and above it.  The trailing columns of each step are updated
+// side by side, a group of g threads per column (the group that forms a
+// column's dot product also updates that column, so one barrier per step
+// suffices besides the norm reduction).
+__device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Smem& S) {
+  const int p = (int)(m < r ? m : r);
+  const int tid = threadIdx.x;
+  for (int j = 0; j < p; ++j) {
+    double* a = A + (int64_t)j * lda;
+    double s = 0.0;
+    for (int64_t i = j + 1 + tid; i < m; i += NT) s += a[i] * a[i];
+    s = block_sum(s, S.red);
+    const double alpha = a[j];
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (s != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + s), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (s != 0.0)
+      for (int64_t i = j + 1 + tid; i < m; i += NT) a[i] *= scale;
+    if (tid == 0) { a[j] = beta; tau[j] = t; }
+    __syncthreads();
+    const int C = r - j - 1;
+    if (t != 0.0 && C > 0) {
+      const int g = group_size(C);
+      const int c = tid / g, gl = tid % g;
+      if (c < C) {
+        double* ac = A + (int64_t)(j + 1 + c) * lda;
+        double dot = (gl == 0) ? ac[j] : 0.0;
+        for (int64_t i = j + 1 + gl; i < m; i += g) dot += a[i] * ac[i];
+        for (int o = 1; o < g; o <<= 1) dot += __shfl_xor(dot, o, 64);
+        const double f = t * dot;
+        if (gl == 0) ac[j] -= f;
+        for (int64_t i = j + 1 + gl; i < m; i += g) ac[i] -= f * a[i];
+      }
+    }
+    // the next step reads the column this step's trailing update just wrote
+    __syncthreads();
+  }
+}
+
+// B <- Q B with Q = H_0 ... H_{p-1} from wg_qr (B is m x k, ldb).
+__device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const double* tau,
+                           double* B, int k, int64_t ldb) {
+  const int tid = threadIdx.x;
+  if (k <= 0) return;
+  const int g = group_size(k);
+  const int c0 = tid / g, gl = tid % g;
+  const int cstep = NT / g;
+  for (int j = p - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t != 0.0) {
+      const double* a = A + (int64_t)j * lda;
+      for (int c = c0; c < k; c += cstep) {
+        double* bc = B + (int64_t)c * ldb;
+        double dot = (gl == 0) ? bc[j] : 0.0;
+        for (int64_t i = j + 1 + gl; i < m; i += g) dot += a[i] * bc[i];
+        for (int o = 1; o < g; o <<= 1) dot += __shfl_xor(dot, o, 64);
+        const double f = t * dot;
+        if (gl == 0) bc[j] -= f;
+        for (int64_t i = j + 1 + gl; i < m; i += g) bc[i] -= f * a[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One-sided Jacobi on the columns of G (px x py, column-major, ld px):
+// on exit G = W Sigma (columns mutually orthogonal).  Round-robin ordering,
+// p/2 disjoint column pairs per round, a group of g threads per pair.  A pair
+// is rotated when its columns are not orthogonal to 2e-15 sqrt(px) relative;
+// columns below 4 max(px,py) eps ||G||_F are numerically zero and are left
+// alone (they carry no singular value that any truncation keeps).
+__device__ void wg_jacobi(double* G, int px, int py, Smem& S) {
+  const int tid = threadIdx.x;
+  const int q = (py + 1) & ~1;
+  if (q < 2) return;
+  double f2 = 0.0;
+  for (int e = tid; e < px * py; e += NT) f2 += G[e] * G[e];
+  f2 = block_sum(f2, S.red);
+  const double epsm = 2.220446049250313e-16;
+  const double tnorm = 4.0 * (double)(px > py ? px : py) * epsm;
+  const double tiny = tnorm * tnorm * f2;
+  const double tol = 2e-15 * sqrt((double)px);
+  const int npairs = q / 2;
+  const int g = group_size(npairs);
+  const int pair = tid / g, gl = tid % g;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) S.flag = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < q - 1; ++rnd) {
+      if (pair < npairs) {
+        int i, j;
+        if (pair == 0) { i = rnd; j = q - 1; }
+        else { i = (rnd + pair) % (q - 1); j = (rnd - pair + q - 1) % (q - 1); }
+        const bool act = (i < py && j < py);
+        double al = 0.0, be = 0.0, ga = 0.0;
+        double* ci = G + (int64_t)(act ? i : 0) * px;
+        double* cj = G + (int64_t)(act ? j : 0) * px;
+        if (act) {
+          for (int rr = gl; rr < px; rr += g) {
+            const double u = ci[rr], v = cj[rr];
+            al += u * u;
+            be += v * v;
+            ga += u * v;
+          }
+        }
+        for (int o = 1; o < g; o <<= 1) {
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          ga += __shfl_xor(ga, o, 64);
+        }
+        if (act && al > tiny && be > tiny && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double az = fabs(zeta);
+          const double t = (az < 1e150) ? copysign(1.0, zeta) / (az + sqrt(1.0 + zeta * zeta)) : 0.5 / zeta;
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+          for (int rr = gl; rr < px; rr += g) {
+            const double u = ci[rr], v = cj[rr];
+            ci[rr] = cs * u - sn * v;
+            cj[rr] = sn * u + cs * v;
+          }
+          if (gl == 0) S.flag = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int f = S.flag;
+    __syncthreads();
+    if (!f) break;
+  }
+}
+
+// Best approximation of X Y^T (X: m x r, Y: n x r, in workspace, destroyed) at
+// relative accuracy eps (kfix == 0) or rank kfix, capped at kmax.  Writes
+// U (m x k, ldu = m) and V (n x k, ldv = n); returns k.
+// scratch: at least r*r + r*r doubles of global workspace.
+__device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, int64_t n, int r,
+                           double* U, double* V, double* scratch, double* lds_g, int lds_cap, Smem& S) {
+  const int tid = threadIdx.x;
+  if (r == 0) return 0;
+  wg_qr(X, m, r, m, S.tau_x, S);
+  wg_qr(Y, n, r, n, S.tau_y, S);
+  const int px = (int)(m < r ? m : r), py = (int)(n < r ? n : r);
+  // M = Rx Ry^T  (px x py), keep a copy for the right singular vectors
+  double* M = scratch;
+  double* G = (px * py <= lds_cap) ? lds_g : scratch + (int64_t)px * py;   // LDS unless it cannot fit
+  for (int e = tid; e < px * py; e += NT) {
+    const int i = e % px, j = e / px;
+    const int l0 = i > j ? i : j;
+    double acc = 0.0;
+    for (int l = l0; l < r; ++l) acc += X[i + (int64_t)l * m] * Y[j + (int64_t)l * n];
+    M[e] = acc;
+    G[e] = acc;
+  }
+  __syncthreads();
+  wg_jacobi(G, px, py, S);
+  // singular values, ordering (descending, ties by index)
+  for (int j = tid; j < py; j += NT) {
+    double s = 0.0;
+    for (int i = 0; i < px; ++i) s += G[i + j * px] * G[i + j * px];
+    S.sig[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < py; j += NT) {
+    int rk = 0;
+    const double sj = S.sig[j];
+    for (int i = 0; i < py; ++i) {
+      const double si = S.sig[i];
+      if (si > sj || (si == sj && i < j)) ++rk;
+    }
+    S.ord[rk] = j;
+  }
+  __syncthreads();
+  const double s1 = S.sig[S.ord[0]];
+  int k = 0;
+  if (s1 > 0.0) {
+    if (D.kfix > 0) {
+      for (int l = 0; l < py; ++l) if (S.sig[S.ord[l]] > 0.0) ++k;
+      if (k > D.kfix) k = D.kfix;
+    } else {
+      for (int l = 0; l < py; ++l) if (S.sig[S.ord[l]] > D.eps * s1) ++k;
+    }
+    if (k > D.kmax) k = D.kmax;
+  }
+  // U = Qx [G(:, ord) ; 0],  V = Qy [M^T G(:, ord) / sigma^2 ; 0]
+  for (int64_t e = tid; e < m * (int64_t)k; e += NT) {
+    const int64_t i = e % m;
+    const int l = (int)(e / m);
+    U[e] = (i < px) ? G[i + (int64_t)S.ord[l] * px] : 0.0;
+  }
+  for (int64_t e = tid; e < n * (int64_t)k; e += NT) {
+    const int64_t j = e % n;
+    const int l = (int)(e / n);
+    double v = 0.0;
+    if (j < py) {
+      const int o = S.ord[l];
+      const double sg = S.sig[o];
+      for (int i = 0; i < px; ++i) v += M[i + (int64_t)j * px] * G[i + (int64_t)o * px];
+      v = v / (sg * sg);
+    }
+    V[e] = v;
+  }
+  __syncthreads();
+  wg_apply_q(X, m, px, m, S.tau_x, U, k, m);
+  wg_apply_q(Y, n, py, n, S.tau_y, V, k, n);
+  __syncthreads();
+  return k;
+}
+
+// ------------------------------------------------------------------ ACA
+
+// Workspace slot layout for ACA: Ua (m x kmax), Va (n x kmax), row (n),
+// used flags (m as doubles), scratch for truncation.
+__global__ void __launch_bounds__(NT) k_aca(DevData D) {
+  extern __shared__ double dyn[];
+  __shared__ Smem S;
+  const int tid = threadIdx.x;
+  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  for (int32_t q = blockIdx.x; q < D.nlr; q += gridDim.x) {
+    const int32_t b = D.lr_ids[q];
+    const Block bk = D.bk[b];
+    const int64_t m = bk.m, n = bk.n;
+    const int kcap = (int)((D.kmax < m) ? ((D.kmax < n) ? D.kmax : n) : ((m < n) ? m : n));
+    double* Ua = slot;
+    double* Va = Ua + m * K_MAX;
+    double* used = Va + n * K_MAX;
+    double* scratch = used + m;
+    for (int64_t i = tid; i < m; i += NT) used[i] = 0.0;
+    __syncthreads();
+    int k = 0;
+    int64_t istar = 0;
+    double S2 = 0.0;
+    int64_t nused = 0;
+    while (k < kcap) {
+      // residual row -> Va[:, k]
+      double* v = Va + (int64_t)k * n;
+      double best = -1.0;
+      int64_t bj = 0;
+      for (int64_t j = tid; j < n; j += NT) {
+        double r = entry(D, bk.r0 + istar, bk.c0 + j);
+        for (int l = 0; l < k; ++l) r -= Ua[istar + (int64_t)l * m] * Va[j + (int64_t)l * n];
+        v[j] = r;
+        const double a = fabs(r);
+        if (a > best || (a == best && j < bj)) { best = a; bj = j; }
+      }
+      block_argmax(best, bj, S.red, S.redi);
+      if (tid == 0) used[istar] = 1.0;
+      ++nused;
+      __syncthreads();
+      const double piv = v[bj];
+      __syncthreads();   // every thread has the pivot before its owner rescales it
+      if (piv == 0.0) {
+        if (nused >= m) break;
+        // lowest unused row
+        int64_t lo = m;
+        for (int64_t i = tid; i < m; i += NT) if (used[i] == 0.0 && i < lo) lo = i;
+        double dv = -(double)lo;
+        block_argmax(dv, lo, S.red, S.redi);
+        istar = (int64_t)(-dv);
+        __syncthreads();
+        continue;
+      }
+      const double inv = 1.0 / piv;
+      for (int64_t j = tid; j < n; j += NT) v[j] = v[j] * inv;
+      double* u = Ua + (int64_t)k * m;
+      __syncthreads();
+      for (int64_t i = tid; i < m; i += NT) {
+        double r = entry(D, bk.r0 + i, bk.c0 + bj);
+        for (int l = 0; l < k; ++l) r -= Va[bj + (int64_t)l * n] * Ua[i + (int64_t)l * m];
+        u[i] = r;
+      }
+      __syncthreads();
+      // norms and cross terms
+      double pu = 0.0, pv = 0.0;
+      for (int64_t i = tid; i < m; i += NT) pu += u[i] * u[i];
+      for (int64_t j = tid; j < n; j += NT) pv += v[j] * v[j];
+      const double nu2 = block_sum(pu, S.red);
+      const double nv2 = block_sum(pv, S.red);
+      double cross = 0.0;
+      for (int l = 0; l < k; ++l) {
+        double a = 0.0, c = 0.0;
+        for (int64_t i = tid; i < m; i += NT) a += Ua[i + (int64_t)l * m] * u[i];
+        for (int64_t j = tid; j < n; j += NT) c += Va[j + (int64_t)l * n] * v[j];
+        a = block_sum(a, S.red);
+        c = block_sum(c, S.red);
+        cross += a * c;
+      }
+      S2 = S2 + 2.0 * cross + nu2 * nv2;
+      ++k;
+      if (sqrt(nu2) * sqrt(nv2) <= D.eps * sqrt(S2)) break;
+      if (nused >= m) break;
+      // next row: largest |u_i| among unused rows
+      double bv = -1.0;
+      int64_t bi = 0;
+      for (int64_t i = tid; i < m; i += NT) {
+        const double a = (used[i] != 0.0) ? -1.0 : fabs(u[i]);
+        if (a > bv || (a == bv && i < bi)) { bv = a; bi = i; }
+      }
+      block_argmax(bv, bi, S.red, S.redi);
+      istar = bi;
+      __syncthreads();
+    }
+    __syncthreads();
+    double* U = D.lr + D.lr_off[b];
+    double* V = U + m * K_MAX;
+    const int kt = wg_truncate(D, Ua, m, Va, n, k, U, V, scratch, dyn, 4096, S);
+    if (tid == 0) D.rank[b] = kt;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ tasks
+
+__device__ __forceinline__ int term_rank(const DevData& D, const TermDef& t) {
+  if (t.kind == TK_DD) return (int)D.bk[t.A].n;
+  if (t.kind == TK_LRA) return D.rank[t.A];
+  return D.rank[t.B];
+}
+
+// Pointers/leading dimensions of the factors of a term.
+__device__ __forceinline__ void term_factors(const DevData& D, const TermDef& t, const double*& X,
+                                             int64_t& ldx, const double*& Y, int64_t& ldy) {
+  const Block A = D.bk[t.A], B = D.bk[t.B];
+  if (t.kind == TK_DD) {
+    X = D.dense + D.dense_off[t.A]; ldx = A.m;
+    Y = D.dense + D.dense_off[t.B]; ldy = B.m;
+  } else if (t.kind == TK_LRA) {
+    X = D.lr + D.lr_off[t.A]; ldx = A.m;
+    Y = D.termbuf + t.buf; ldy = t.rows;
+  } else {
+    X = D.termbuf + t.buf; ldx = t.rows;
+    Y = D.lr + D.lr_off[t.B]; ldy = B.m;
+  }
+}
+
+// Y += L_blk W for one leaf of the factor: W (ncols(blk) x k, ldw), Y (ldy).
+// tmp: k_blk x k doubles (global or shared).
+__device__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k,
+                            double* Y, int64_t ldy, double sign, double* tmp) {
+  const Block L = D.bk[blk];
+  const int tid = threadIdx.x;
+  if (L.kind == BK_DENSE) {
+    const double* A = D.dense + D.dense_off[blk];
+    for (int64_t e = tid; e < L.m * (int64_t)k; e += NT) {
+      const int64_t i = e % L.m;
+      const int c = (int)(e / L.m);
+      double acc = 0.0;
+      for (int64_t l = 0; l < L.n; ++l) acc += A[i + l * L.m] * W[l + c * ldw];
+      Y[i + c * ldy] += sign * acc;
+    }
+  } else {
+    const double* U = D.lr + D.lr_off[blk];
+    const double* V = U + L.m * K_MAX;
+    const int kb = D.rank[blk];
+    // tmp = V^T W  (kb x k)
+    const int w = tid >> 6, lane = tid & 63;
+    for (int e = w; e < kb * k; e += NW) {
+      const int a = e % kb, c = e / kb;
+      double acc = 0.0;
+      for (int64_t l = lane; l < L.n; l += 64) acc += V[l + a * L.n] * W[l + c * ldw];
+      acc = wave_sum(acc);
+      if (lane == 0) tmp[e] = acc;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < L.m * (int64_t)k; e += NT) {
+      const int64_t i = e % L.m;
+      const int c = (int)(e / L.m);
+      double acc = 0.0;
+      for (int a = 0; a < kb; ++a) acc += U[i + (int64_t)a * L.m] * tmp[a + c * kb];
+      Y[i + c * ldy] += sign * acc;
+    }
+  }
+  __syncthreads();
+}
+
+// W <- L_cc^{-1} W over cluster c (W: |c| x k, ldw) by the solve program.
+__device__ void run_solve(const DevData& D, int32_t c, double* W, int64_t ldw, int k, double* tmp,
+                          double* lds) {
+  const int tid = threadIdx.x;
+  for (int32_t o = D.sop_begin[c]; o < D.sop_begin[c + 1]; ++o) {
+    const SolveOp op = D.sops[o];
+    const Block L = D.bk[op.blk];
+    if (op.kind == SOP_TRSV) {
+      // dense lower-triangular solve of the leaf's rows, staged in LDS; one
+      // thread per right-hand side column
+      const double* A = D.dense + D.dense_off[op.blk];
+      const int mm = (int)L.m;
+      double* Ls = lds;
+      double* Ws = lds + LEAF_MAX * LEAF_MAX;   // mm x k, leading dimension LEAF_MAX + 1
+      const int ldl = LEAF_MAX + 1;
+      double* w = W + op.off;
+      for (int e = tid; e < mm * mm; e += NT) Ls[e] = A[e];
+      for (int e = tid; e < mm * k; e += NT) Ws[(e % mm) + (e / mm) * ldl] = w[(e % mm) + (int64_t)(e / mm) * ldw];
+      __syncthreads();
+      for (int c = tid; c < k; c += NT) {
+        double* wc = Ws + c * ldl;
+        for (int i = 0; i < mm; ++i) {
+          double sum = wc[i];
+          for (int l = 0; l < i; ++l) sum -= Ls[i + l * mm] * wc[l];
+          wc[i] = sum / Ls[i + i * mm];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < mm * k; e += NT) w[(e % mm) + (int64_t)(e / mm) * ldw] = Ws[(e % mm) + (e / mm) * ldl];
+      __syncthreads();
+    } else {
+      leaf_matvec(D, op.blk, W + op.off2, ldw, k, W + op.off, ldw, -1.0, tmp);
+    }
+  }
+}
+
+// Term product: Y = L_B V_A (TK_LRA) or X = L_A V_B (TK_LRB).
+__device__ void task_term(const DevData& D, int32_t tid_term, double* tmp) {
+  const TermDef t = D.terms[tid_term];
+  const int32_t H = (t.kind == TK_LRA) ? t.B : t.A;      // H-block applied
+  const int32_t R = (t.kind == TK_LRA) ? t.A : t.B;      // low-rank block providing V
+  const Block HB = D.bk[H], RB = D.bk[R];
+  const int k = D.rank[R];
+  const double* Vr = D.lr + D.lr_off[R] + RB.m * K_MAX;   // n(R) x k, ld n(R)
+  double* out = D.termbuf + t.buf;                        // rows x k, ld rows
+  for (int64_t e = threadIdx.x; e < t.rows * (int64_t)k; e += NT) out[e] = 0.0;
+  __syncthreads();
+  for (int32_t q = D.sub_begin[H]; q < D.sub_end[H]; ++q) {
+    const int32_t lf = D.sub_leaves[q];
+    const Block L = D.bk[lf];
+    leaf_matvec(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp);
+  }
+}
+
+// Dense leaf: flush its terms, then Cholesky (diagonal) or triangular solve.
+__device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, double* lds, Smem& S) {
+  const int tid = threadIdx.x;
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int m = (int)bk.m, n = (int)bk.n;
+  double* Dg = D.dense + D.dense_off[b];
+  double dreg[16];
+  const int cnt = m * n;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + q * NT;
+    dreg[q] = (e < cnt) ? Dg[e] : 0.0;
+  }
+  double* Xs = lds;                 // 64 x 32 chunk
+  double* Ys = lds + 64 * 33;       // 64 x 32 chunk, row stride 33
+  for (int32_t ii = 0; ii < tk.ninst; ++ii) {
+    const TermInst in = D.insts[tk.inst_begin + ii];
+    const TermDef t = D.terms[in.term];
+    const int r = term_rank(D, t);
+    const double *X, *Y;
+    int64_t ldx, ldy;
+    term_factors(D, t, X, ldx, Y, ldy);
+    for (int l0 = 0; l0 < r; l0 += 32) {
+      const int lc = (r - l0 < 32) ? (r - l0) : 32;
+      __syncthreads();
+      for (int e = tid; e < in.mx * lc; e += NT) {
+        const int i = e % in.mx, l = e / in.mx;
+        Xs[i * 33 + l] = X[in.xr0 + i + (int64_t)(l0 + l) * ldx];
+      }
+      for (int e = tid; e < in.ny * lc; e += NT) {
+        const int j = e % in.ny, l = e / in.ny;
+        Ys[j * 33 + l] = Y[in.yr0 + j + (int64_t)(l0 + l) * ldy];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = tid + q * NT;
+        if (e < cnt) {
+          const int i = e % m - in.lr0, j = e / m - in.lc0;
+          if (i >= 0 && i < in.mx && j >= 0 && j < in.ny) {
+            double acc = 0.0;
+            for (int l = 0; l < lc; ++l) acc += Xs[i * 33 + l] * Ys[j * 33 + l];
+            dreg[q] -= acc;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double* A = lds;                  // m x n tile, column-major
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + q * NT;
+    if (e < cnt) A[e] = dreg[q];
+  }
+  __syncthreads();
+  if (tk.kind == TASK_DIAG) {
+    // right-looking Cholesky in LDS (lower)
+    for (int j = 0; j < n; ++j) {
+      const double djj = A[j + j * m];
+      const bool bad = !(djj > 0.0);
+      if (bad && tid == 0) {
+        const unsigned long long key = ((unsigned long long)prog << 8) | (unsigned long long)j;
+        atomicMin(D.fail_key, key);
+      }
+      const double ljj = bad ? NAN : sqrt(djj);
+      __syncthreads();
+      for (int i = j + tid; i < m; i += NT) A[i + j * m] = (i == j) ? ljj : A[i + j * m] / ljj;
+      __syncthreads();
+      const int rem = m - j - 1;
+      for (int e = tid; e < rem * rem; e += NT) {
+        const int i = j + 1 + e % rem, c = j + 1 + e / rem;
+        if (c <= i) A[i + c * m] -= A[i + j * m] * A[c + j * m];
+      }
+      __syncthreads();
+    }
+    double s = 0.0;
+    for (int i = tid; i < m; i += NT) s += log(A[i + i * m]);
+    s = block_sum(s, S.red);
+    if (tid == 0) D.logdet_part[b] = s;
+    for (int e = tid; e < cnt; e += NT) {
+      const int i = e % m, j = e / m;
+      Dg[e] = (j <= i) ? A[e] : 0.0;
+    }
+  } else {
+    // X L^T = A, L the factored diagonal leaf of the column cluster (n x n)
+    const double* Lg = D.dense + D.dense_off[tk.diag];
+    double* Ls = lds + 64 * 64;
+    for (int e = tid; e < n * n; e += NT) Ls[e] = Lg[e];
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) {
+      for (int j = 0; j < n; ++j) {
+        double s = A[i + j * m];
+        for (int l = 0; l < j; ++l) s -= A[i + l * m] * Ls[j + l * n];
+        A[i + j * m] = s / Ls[j + j * n];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < cnt; e += NT) Dg[e] = A[e];
+  }
+  __syncthreads();
+}
+
+// Low-rank leaf: truncate U V^T minus its terms (in order, R_ACC at a time),
+// then V <- L_{sigma sigma}^{-1} V.
+__device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
+  const int tid = threadIdx.x;
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int64_t m = bk.m, n = bk.n;
+  const int RW = 2 * K_MAX;
+  double* U = D.lr + D.lr_off[b];
+  double* V = U + m * K_MAX;
+  if (tk.ninst > 0) {
+    double* Xa = slot;
+    double* Ya = Xa + m * RW;
+    double* scratch = Ya + n * RW;
+    int rank = D.rank[b];
+    for (int64_t e = tid; e < m * rank; e += NT) Xa[e] = U[e];
+    for (int64_t e = tid; e < n * rank; e += NT) Ya[e] = V[e];
+    __syncthreads();
+    for (int32_t ii = 0; ii < tk.ninst; ++ii) {
+      const TermInst in = D.insts[tk.inst_begin + ii];
+      const TermDef t = D.terms[in.term];
+      const int r = term_rank(D, t);
+      if (r == 0) continue;
+      if (rank > 0 && rank + r > R_ACC) {
+        const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, scratch, lds, LDS_FACTOR, S);
+        for (int64_t e = tid; e < m * kk; e += NT) Xa[e] = U[e];
+        for (int64_t e = tid; e < n * kk; e += NT) Ya[e] = V[e];
+        rank = kk;
+        __syncthreads();
+      }
+      const double *X, *Y;
+      int64_t ldx, ldy;
+      term_factors(D, t, X, ldx, Y, ldy);
+      for (int64_t e = tid; e < m * r; e += NT) {
+        const int64_t i = e % m;
+        const int l = (int)(e / m);
+        const int64_t li = i - in.lr0;
+        Xa[(rank + l) * m + i] = (li >= 0 && li < in.mx) ? -X[in.xr0 + li + l * ldx] : 0.0;
+      }
+      for (int64_t e = tid; e < n * r; e += NT) {
+        const int64_t j = e % n;
+        const int l = (int)(e / n);
+        const int64_t lj = j - in.lc0;
+        Ya[(rank + l) * n + j] = (lj >= 0 && lj < in.ny) ? Y[in.yr0 + lj + l * ldy] : 0.0;
+      }
+      rank += r;
+      __syncthreads();
+    }
+    const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, scratch, lds, LDS_FACTOR, S);
+    if (tid == 0) D.rank[b] = kk;
+    if (tid == 0) S.ival[0] = kk;
+    __syncthreads();
+  } else {
+    if (tid == 0) S.ival[0] = D.rank[b];
+    __syncthreads();
+  }
+  const int k = S.ival[0];
+  __syncthreads();
+  if (k > 0) run_solve(D, tk.diag, V, n, k, slot, lds);
+}
+
+// ------------------------------------------------------------------ executor
+
+__device__ __forceinline__ int64_t rtc() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
+
+__global__ void __launch_bounds__(NT) k_factor(DevData D) {
+  extern __shared__ double dyn[];
+  __shared__ Smem S;
+  const int tid = threadIdx.x;
+  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  int32_t* dbg = D.dbg + 4 * blockIdx.x;   // executor state, read by the host after an abort
+  while (true) {
+    if (tid == 0) {
+      int t = atomicAdd(D.ticket, 1);
+      if (__hip_atomic_load(D.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) t = D.ntasks;
+      S.task = t;
+      dbg[0] = t;
+      dbg[1] = 1;
+    }
+    __syncthreads();
+    const int32_t t = S.task;
+    __syncthreads();
+    if (t >= D.ntasks) break;
+    const Task tk = D.tasks[t];
+    // wait for predecessors (bounded)
+    int bad = 0;
+    for (int32_t q = tid; q < tk.ndeps; q += NT) {
+      const int32_t d = D.deps[tk.dep_begin + q];
+      const int64_t t0 = rtc();
+      while (__hip_atomic_load(&D.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        dbg[2] = d;
+        if (__hip_atomic_load(D.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { bad = 1; break; }
+        if (rtc() - t0 > D.spin_limit) {
+          __hip_atomic_store(D.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (bad) break;
+    }
+    if (tid == 0) S.flag = 0;
+    __syncthreads();
+    if (bad) S.flag = 1;
+    __syncthreads();
+    const int stop = S.flag;
+    __syncthreads();
+    if (stop) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tid == 0) dbg[1] = 2;
+    const int32_t prog = D.task_prog[t];
+    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot);
+    else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
+    else task_dense(D, tk, prog, dyn, S);
+    // every wave's stores acknowledged by L2 before the one agent-scope
+    // release (L2 write-back) that publishes the task
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&D.done[t], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      dbg[1] = 3;
+      dbg[3] += 1;
+    }
+  }
+}
+
+// Level-synchronous executor: the tasks of one DAG level (longest-path depth)
+// have no dependencies among themselves, and all their predecessors belong to
+// earlier levels, completed by earlier launches.  Work-group w takes tasks
+// t0 + w, t0 + w + gridDim.x, ... of the level; it uses workspace slot w.
+__global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1) {
+  extern __shared__ double dyn[];
+  __shared__ Smem S;
+  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  for (int32_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) {
+    const Task tk = D.tasks[t];
+    const int32_t prog = D.task_prog[t];
+    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot);
+    else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
+    else task_dense(D, tk, prog, dyn, S);
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_init_sched(int32_t* ticket, int32_t* abort_flag, unsigned long long* fail_key) {
+  if (threadIdx.x == 0) {
+    *ticket = 0;
+    *abort_flag = 0;
+    *fail_key = ~0ull;
+  }
+}
+
+// ------------------------------------------------------------------ solve
+
+// W (n x r, permuted Z) <- L^{-1} W over the whole index set.
+__global__ void __launch_bounds__(NT) k_solve(DevData D, double* W, int r) {
+  extern __shared__ double dyn[];
+  double* slot = D.ws;
+  run_solve(D, 0, W, D.n, r, slot, dyn);
+}
+
+// Gather Z into permuted order: W[i, c] = Z[perm[i], c].
+__global__ void k_permute(const double* Z, const int64_t* perm, int64_t n, int r, double* W) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * r; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    W[e] = Z[perm[i] + c * n];
+  }
+}
+
+// out[0] = log|C| (2 sum over diagonal leaves in order), out[1 + c] = v_c^T v_c.
+__global__ void __launch_bounds__(NT) k_reduce(DevData D, const int32_t* diag_ids, int32_t ndiag,
+                                               const double* W, int r, double* out) {
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  // log-determinant: per-thread contiguous chunks of leaves, fixed order
+  double s = 0.0;
+  const int32_t per = (ndiag + NT - 1) / NT;
+  for (int32_t q = tid * per; q < ndiag && q < (tid + 1) * per; ++q) s += D.logdet_part[diag_ids[q]];
+  s = block_sum(s, red);
+  if (tid == 0) out[0] = 2.0 * s;
+  for (int c = 0; c < r; ++c) {
+    const double* w = W + (int64_t)c * D.n;
+    double a = 0.0;
+    const int64_t per2 = (D.n + NT - 1) / NT;
+    for (int64_t i = tid * per2; i < D.n && i < (tid + 1) * per2; ++i) a += w[i] * w[i];
+    a = block_sum(a, red);
+    if (tid == 0) out[1 + c] = a;
+  }
+}
+
+// ------------------------------------------------------------------ test hook
+
+// One work-group truncates X Y^T (X: m x r, Y: n x r, copied into workspace
+// slot 0) into U (m x k), V (n x k); k written to *kout.
+__global__ void __launch_bounds__(NT) k_truncate_test(DevData D, const double* X, int64_t m,
+                                                      const double* Y, int64_t n, int r, double* U,
+                                                      double* V, int32_t* kout) {
+  extern __shared__ double dyn[];
+  __shared__ Smem S;
+  double* Xa = D.ws;
+  double* Ya = Xa + m * r;
+  double* scratch = Ya + n * r;
+  for (int64_t e = threadIdx.x; e < m * r; e += NT) Xa[e] = X[e];
+  for (int64_t e = threadIdx.x; e < n * r; e += NT) Ya[e] = Y[e];
+  __syncthreads();
+  const int k = wg_truncate(D, Xa, m, Ya, n, r, U, V, scratch, dyn, LDS_FACTOR, S);
+  if (threadIdx.x == 0) *kout = k;
+}
+
+hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
+                                int r, double* U, double* V, int32_t* kout, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_truncate_test, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     LDS_FACTOR * sizeof(double));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_truncate_test, dim3(1), dim3(NT), LDS_FACTOR * sizeof(double), st, D, X, m, Y, n, r, U, V,
+                     kout);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_assemble(const DevData& D, hipStream_t st) {
+  if (D.ndense > 0) {
+    int g = D.ndense < 4096 ? D.ndense : 4096;
+    hipLaunchKernelGGL(k_assemble_dense, dim3(g), dim3(NT), 0, st, D);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_aca(const DevData& D, int grid, hipStream_t st) {
+  if (D.nlr > 0) {
+    int g = D.nlr < grid ? D.nlr : grid;
+    hipLaunchKernelGGL(k_aca, dim3(g), dim3(NT), 4096 * sizeof(double), st, D);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_factor(const DevData& D, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
+  hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(NT), 0, st, D.done, (int64_t)D.ntasks, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(8), dim3(NT), 0, st, D.dbg, (int64_t)4 * grid, -1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_FACTOR * sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (D.ntasks > 0) hipLaunchKernelGGL(k_factor, dim3(grid), dim3(NT), LDS_FACTOR * sizeof(double), st, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t nlevels, int max_grid,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_level, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_FACTOR * sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  for (int32_t l = 0; l < nlevels; ++l) {
+    const int32_t t0 = level_begin[l], t1 = level_begin[l + 1];
+    const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
+    if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,
+                        const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_permute, dim3(1024), dim3(NT), 0, st, Z, perm, D.n, r, W);
+  static bool solve_attr = false;
+  if (!solve_attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_SOLVE * sizeof(double));
+    if (e != hipSuccess) return e;
+    solve_attr = true;
+  }
+  hipLaunchKernelGGL(k_solve, dim3(1), dim3(NT), LDS_SOLVE * sizeof(double), st, D, W, r);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, st, D, diag_ids, ndiag, W, r, out);
+  return hipGetLastError();
+}
+
+}  // namespace hm

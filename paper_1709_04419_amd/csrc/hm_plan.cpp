@@ -1,0 +1,581 @@
+// Host planner: cluster tree, block cluster tree and symbolic H-Cholesky.
+//
+// Cluster tree (Appendix B, Definition B.1): geometric bisection.  A cluster
+// with more than n_min points is split along the longest side of its tight
+// bounding box (lowest axis on ties) at the median of the total order
+// (coordinate, original index); the first son gets floor(|t|/2) points.  The
+// permutation is the left-to-right order of the leaves.
+//
+// Block cluster tree (Definitions B.2, B.3): lower triangle only, standard
+// admissibility min(diam^2) <= eta^2 dist^2 with dist^2 > 0, evaluated with a
+// fixed operation order.  This file is compiled without floating-point
+// contraction so that the partition is reproducible bit for bit.
+//
+// Symbolic H-Cholesky (Section 3.2: the factor keeps the block structure of
+// the matrix; log|C| = 2 sum log L_ii): the recursive formatted Cholesky with
+// deferred, per-leaf ordered updates is run once without numbers.  It records
+//   * every update term (what its factors X, Y are made of),
+//   * for every leaf the ordered list of restricted terms it must subtract,
+//   * the tasks (dense diagonal, dense off-diagonal, low-rank leaf, term
+//     product) with their data dependencies,
+//   * the forward-substitution programs over clusters.
+// The device executes the tasks in any order compatible with the
+// dependencies; each leaf still applies its terms in program order, so the
+// arithmetic per leaf is fixed.
+#include "hm_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+namespace hm {
+
+namespace {
+
+struct TreeBuilder {
+  const double* P;
+  int64_t n;
+  int32_t nmin;
+  Tree& t;
+  std::vector<int64_t> work;
+
+  int32_t build(int64_t b, int64_t e, int32_t level) {
+    Cluster c{};
+    c.begin = b;
+    c.end = e;
+    c.level = level;
+    c.son[0] = c.son[1] = -1;
+    for (int ax = 0; ax < 2; ++ax) {
+      double lo = P[2 * work[b] + ax], hi = lo;
+      for (int64_t i = b + 1; i < e; ++i) {
+        double v = P[2 * work[i] + ax];
+        if (v < lo) lo = v;
+        if (v > hi) hi = v;
+      }
+      c.lo[ax] = lo;
+      c.hi[ax] = hi;
+    }
+    int32_t id = (int32_t)t.cl.size();
+    t.cl.push_back(c);
+    if (e - b <= nmin) return id;
+    double ext0 = c.hi[0] - c.lo[0], ext1 = c.hi[1] - c.lo[1];
+    int ax = (ext1 > ext0) ? 1 : 0;  // lowest axis on ties
+    const double* Pp = P;
+    std::sort(work.begin() + b, work.begin() + e, [Pp, ax](int64_t i, int64_t j) {
+      double a = Pp[2 * i + ax], bb = Pp[2 * j + ax];
+      return a < bb || (a == bb && i < j);
+    });
+    int64_t half = (e - b) / 2;
+    int32_t s0 = build(b, b + half, level + 1);
+    int32_t s1 = build(b + half, e, level + 1);
+    t.cl[id].son[0] = s0;
+    t.cl[id].son[1] = s1;
+    return id;
+  }
+};
+
+inline bool is_leaf(const Cluster& c) { return c.son[0] < 0; }
+
+double diam2(const Cluster& c) {
+  double dx = c.hi[0] - c.lo[0];
+  double dy = c.hi[1] - c.lo[1];
+  double a = dx * dx;
+  double b = dy * dy;
+  return a + b;
+}
+
+double dist2(const Cluster& a, const Cluster& b) {
+  double s = 0.0;
+  for (int ax = 0; ax < 2; ++ax) {
+    double g = 0.0;
+    double g1 = b.lo[ax] - a.hi[ax];
+    double g2 = a.lo[ax] - b.hi[ax];
+    if (g1 > g) g = g1;
+    if (g2 > g) g = g2;
+    double gg = g * g;
+    s = s + gg;
+  }
+  return s;
+}
+
+bool admissible(const Cluster& a, const Cluster& b, double eta) {
+  double d2 = dist2(a, b);
+  if (!(d2 > 0.0)) return false;
+  double da = diam2(a), db = diam2(b);
+  double dm = da < db ? da : db;
+  double e2 = eta * eta;
+  double rhs = e2 * d2;
+  return dm <= rhs;
+}
+
+struct BlockBuilder {
+  Tree& t;
+  double eta;
+  int32_t build(int32_t r, int32_t s) {
+    const Cluster& R = t.cl[r];
+    const Cluster& S = t.cl[s];
+    Block b{};
+    b.row = r;
+    b.col = s;
+    b.kind = BK_NODE;
+    b.r0 = R.begin;
+    b.c0 = S.begin;
+    b.m = R.end - R.begin;
+    b.n = S.end - S.begin;
+    b.son_begin = -1;
+    b.nsons = 0;
+    int32_t id = (int32_t)t.bk.size();
+    t.bk.push_back(b);
+    if (r == s) t.diag_of[r] = id;
+    if (r != s && admissible(R, S, eta)) {
+      t.bk[id].kind = BK_LR;
+      return id;
+    }
+    if (is_leaf(R) && is_leaf(S)) {
+      t.bk[id].kind = BK_DENSE;
+      return id;
+    }
+    int32_t rows[2], cols[2];
+    int nr = 0, nc = 0;
+    if (is_leaf(R)) rows[nr++] = r; else { rows[nr++] = R.son[0]; rows[nr++] = R.son[1]; }
+    if (is_leaf(S)) cols[nc++] = s; else { cols[nc++] = S.son[0]; cols[nc++] = S.son[1]; }
+    int32_t local[4];
+    int ns = 0;
+    for (int i = 0; i < nr; ++i)
+      for (int j = 0; j < nc; ++j) {
+        if (r == s && t.cl[rows[i]].begin < t.cl[cols[j]].begin) continue;
+        local[ns++] = build(rows[i], cols[j]);
+      }
+    t.bk[id].son_begin = (int32_t)t.sons.size();
+    t.bk[id].nsons = ns;
+    for (int i = 0; i < ns; ++i) t.sons.push_back(local[i]);
+    return id;
+  }
+};
+
+}  // namespace
+
+void build_tree(const double* coords, int64_t n, int32_t leaf_size, double eta, Tree& t) {
+  if (n < 1 || leaf_size < 1) throw std::invalid_argument("n and leaf_size must be >= 1");
+  t = Tree{};
+  t.n = n;
+  t.leaf_size = leaf_size;
+  t.eta = eta;
+  TreeBuilder tb{coords, n, leaf_size, t, {}};
+  tb.work.resize(n);
+  for (int64_t i = 0; i < n; ++i) tb.work[i] = i;
+  tb.build(0, n, 0);
+  t.perm = tb.work;
+  t.diag_of.assign(t.cl.size(), -1);
+  BlockBuilder bb{t, eta};
+  bb.build(0, 0);
+}
+
+// ---------------------------------------------------------------- planner
+
+namespace {
+
+struct Planner {
+  const Tree& T;
+  Plan& P;
+  std::vector<int32_t> final_task;                  // block -> task that finalises it
+  std::vector<std::vector<TermInst>> leaf_insts;    // block -> ordered instances
+  std::vector<Task> tasks;                          // program order
+  std::vector<std::vector<int32_t>> tdeps;
+  std::vector<int32_t> term_task;                   // term -> task (-1 for TK_DD)
+  std::vector<int32_t> sub_end;                     // block -> one past its pre-order subtree
+  std::vector<int32_t> leaf_rank;                   // block -> #leaves with smaller id
+
+  Planner(const Tree& t, Plan& p) : T(t), P(p) {}
+
+  const Block& B(int32_t b) const { return T.bk[b]; }
+  const Cluster& C(int32_t c) const { return T.cl[c]; }
+
+  int32_t son(int32_t b, int32_t r, int32_t c) const {
+    const Block& bb = B(b);
+    for (int i = 0; i < bb.nsons; ++i) {
+      int32_t s = T.sons[bb.son_begin + i];
+      if (B(s).row == r && B(s).col == c) return s;
+    }
+    throw std::logic_error("missing block son");
+  }
+
+  void leaves_of(int32_t b, std::vector<int32_t>& out) const {
+    for (int32_t i = leaf_rank[b]; i < leaf_rank[sub_end[b]]; ++i) out.push_back(P.sub_leaves[i]);
+  }
+
+  int32_t new_task(int8_t kind, int32_t obj, std::vector<int32_t> deps) {
+    std::sort(deps.begin(), deps.end());
+    deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+    if (!deps.empty() && deps.front() < 0) throw std::logic_error("dependency on an unfinished block");
+    Task t{};
+    t.kind = kind;
+    t.obj = obj;
+    t.diag = -1;
+    tasks.push_back(t);
+    tdeps.push_back(std::move(deps));
+    return (int32_t)tasks.size() - 1;
+  }
+
+  void push(int32_t bid, int64_t R0, int64_t C0, int32_t term, int64_t xoff, int64_t yoff,
+            int64_t mx, int64_t ny) {
+    const Block& b = B(bid);
+    if (b.kind != BK_NODE) {
+      TermInst in{};
+      in.term = term;
+      in.lr0 = (int32_t)(R0 - b.r0);
+      in.lc0 = (int32_t)(C0 - b.c0);
+      in.mx = (int32_t)mx;
+      in.ny = (int32_t)ny;
+      in.xr0 = xoff;
+      in.yr0 = yoff;
+      leaf_insts[bid].push_back(in);
+      return;
+    }
+    if (R0 != b.r0 || C0 != b.c0 || mx != b.m || ny != b.n)
+      throw std::logic_error("partial target on a non-leaf block");
+    for (int i = 0; i < b.nsons; ++i) {
+      int32_t s = T.sons[b.son_begin + i];
+      const Block& sb = B(s);
+      push(s, sb.r0, sb.c0, term, xoff + (sb.r0 - R0), yoff + (sb.c0 - C0), sb.m, sb.n);
+    }
+  }
+
+  struct Target {
+    int32_t bid;
+    int64_t R0, C0;
+  };
+
+  Target sub_target(const Target& tg, int32_t t, int32_t s) const {
+    Target o{tg.bid, C(t).begin, C(s).begin};
+    if (B(tg.bid).kind == BK_NODE) o.bid = son(tg.bid, t, s);
+    return o;
+  }
+
+  void update(const Target& tg, int32_t A, int32_t Bb) {
+    int8_t ka = B(A).kind, kb = B(Bb).kind;
+    int64_t mx = B(A).m, ny = B(Bb).m;
+    if (ka == BK_LR || kb == BK_LR || (ka == BK_DENSE && kb == BK_DENSE)) {
+      TermDef d{};
+      d.A = A;
+      d.B = Bb;
+      std::vector<int32_t> deps;
+      int32_t tid = (int32_t)P.terms.size();
+      if (ka == BK_LR) {
+        d.kind = TK_LRA;
+        d.rows = ny;
+        deps.push_back(final_task[A]);
+        std::vector<int32_t> lv;
+        leaves_of(Bb, lv);
+        for (int32_t l : lv) deps.push_back(final_task[l]);
+      } else if (kb == BK_LR) {
+        d.kind = TK_LRB;
+        d.rows = mx;
+        deps.push_back(final_task[Bb]);
+        std::vector<int32_t> lv;
+        leaves_of(A, lv);
+        for (int32_t l : lv) deps.push_back(final_task[l]);
+      } else {
+        d.kind = TK_DD;
+        d.rows = 0;
+      }
+      d.buf = -1;
+      if (d.rows > 0) {
+        d.buf = P.term_pool;
+        P.term_pool += d.rows * K_MAX;
+        term_task.push_back(new_task(TASK_TERM, tid, deps));
+      } else {
+        term_task.push_back(-1);
+      }
+      P.terms.push_back(d);
+      push(tg.bid, tg.R0, tg.C0, tid, 0, 0, mx, ny);
+      return;
+    }
+    int32_t tau = B(A).row, rho = B(A).col, sig = B(Bb).row;
+    int32_t ts[2], ss[2], rs[2];
+    int nt = 0, nss = 0, nr = 0;
+    if (ka == BK_NODE && !is_leaf(C(tau))) { ts[nt++] = C(tau).son[0]; ts[nt++] = C(tau).son[1]; }
+    else ts[nt++] = tau;
+    if (kb == BK_NODE && !is_leaf(C(sig))) { ss[nss++] = C(sig).son[0]; ss[nss++] = C(sig).son[1]; }
+    else ss[nss++] = sig;
+    if (!is_leaf(C(rho))) { rs[nr++] = C(rho).son[0]; rs[nr++] = C(rho).son[1]; }
+    else rs[nr++] = rho;
+    bool diag = tau == sig;
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nss; ++j) {
+        if (diag && C(ts[i]).begin < C(ss[j]).begin) continue;
+        Target sub = sub_target(tg, ts[i], ss[j]);
+        for (int k = 0; k < nr; ++k) {
+          int32_t a = (ka != BK_NODE) ? A : son(A, ts[i], rs[k]);
+          int32_t b = (kb != BK_NODE) ? Bb : son(Bb, ss[j], rs[k]);
+          update(sub, a, b);
+        }
+      }
+  }
+
+  std::vector<int32_t> inst_deps(int32_t bid) const {
+    std::vector<int32_t> deps;
+    for (const TermInst& in : leaf_insts[bid]) {
+      const TermDef& d = P.terms[in.term];
+      if (d.kind == TK_DD) {
+        deps.push_back(final_task[d.A]);
+        deps.push_back(final_task[d.B]);
+      } else {
+        deps.push_back(term_task[in.term]);
+      }
+    }
+    return deps;
+  }
+
+  void htrsm(int32_t bid) {
+    const Block& b = B(bid);
+    int32_t sig = b.col;
+    if (b.kind == BK_DENSE) {
+      std::vector<int32_t> deps = inst_deps(bid);
+      int32_t d = T.diag_of[sig];
+      deps.push_back(final_task[d]);
+      int32_t t = new_task(TASK_OFFD, bid, deps);
+      tasks[t].diag = d;
+      final_task[bid] = t;
+      return;
+    }
+    if (b.kind == BK_LR) {
+      std::vector<int32_t> deps = inst_deps(bid);
+      std::vector<int32_t> lv;
+      leaves_of(T.diag_of[sig], lv);
+      for (int32_t l : lv) deps.push_back(final_task[l]);
+      int32_t t = new_task(TASK_LR, bid, deps);
+      tasks[t].diag = sig;
+      final_task[bid] = t;
+      return;
+    }
+    int32_t rho = b.row;
+    int32_t rows[2];
+    int nr = 0;
+    if (is_leaf(C(rho))) rows[nr++] = rho; else { rows[nr++] = C(rho).son[0]; rows[nr++] = C(rho).son[1]; }
+    if (is_leaf(C(sig))) {
+      for (int i = 0; i < nr; ++i) htrsm(son(bid, rows[i], sig));
+      return;
+    }
+    int32_t s1 = C(sig).son[0], s2 = C(sig).son[1];
+    int32_t L21 = son(T.diag_of[sig], s2, s1);
+    for (int i = 0; i < nr; ++i) {
+      int32_t b1 = son(bid, rows[i], s1);
+      int32_t b2 = son(bid, rows[i], s2);
+      htrsm(b1);
+      update(Target{b2, C(rows[i]).begin, C(s2).begin}, b1, L21);
+      htrsm(b2);
+    }
+  }
+
+  void hchol(int32_t c) {
+    int32_t d = T.diag_of[c];
+    if (is_leaf(C(c))) {
+      int32_t t = new_task(TASK_DIAG, d, inst_deps(d));
+      tasks[t].diag = d;
+      final_task[d] = t;
+      return;
+    }
+    int32_t c1 = C(c).son[0], c2 = C(c).son[1];
+    hchol(c1);
+    int32_t b21 = son(d, c2, c1);
+    htrsm(b21);
+    update(Target{T.diag_of[c2], C(c2).begin, C(c2).begin}, b21, b21);
+    hchol(c2);
+  }
+
+  void solve_prog(int32_t c, int64_t base, std::vector<SolveOp>& out) const {
+    int32_t d = T.diag_of[c];
+    if (is_leaf(C(c))) {
+      SolveOp op{};
+      op.kind = SOP_TRSV;
+      op.blk = d;
+      op.off = C(c).begin - base;
+      op.off2 = 0;
+      out.push_back(op);
+      return;
+    }
+    int32_t c1 = C(c).son[0], c2 = C(c).son[1];
+    solve_prog(c1, base, out);
+    int32_t b21 = son(d, c2, c1);
+    std::vector<int32_t> lv;
+    leaves_of(b21, lv);
+    for (int32_t l : lv) {
+      SolveOp op{};
+      op.kind = SOP_MATVEC;
+      op.blk = l;
+      op.off = B(l).r0 - base;
+      op.off2 = B(l).c0 - base;
+      out.push_back(op);
+    }
+    solve_prog(c2, base, out);
+  }
+
+  void run() {
+    const int32_t nb = (int32_t)T.bk.size();
+    // leaves in pre-order and subtree extents
+    sub_end.assign(nb, 0);
+    for (int32_t b = nb - 1; b >= 0; --b) {
+      const Block& bb = B(b);
+      sub_end[b] = b + 1;
+      for (int i = 0; i < bb.nsons; ++i) sub_end[b] = std::max(sub_end[b], sub_end[T.sons[bb.son_begin + i]]);
+    }
+    leaf_rank.assign(nb + 1, 0);
+    P.sub_leaves.clear();
+    for (int32_t b = 0; b < nb; ++b) {
+      leaf_rank[b] = (int32_t)P.sub_leaves.size();
+      if (B(b).kind != BK_NODE) P.sub_leaves.push_back(b);
+    }
+    leaf_rank[nb] = (int32_t)P.sub_leaves.size();
+    P.sub_begin.assign(nb, 0);
+    P.sub_end.assign(nb, 0);
+    for (int32_t b = 0; b < nb; ++b) {
+      P.sub_begin[b] = leaf_rank[b];
+      P.sub_end[b] = leaf_rank[sub_end[b]];
+    }
+    // storage
+    P.dense_off.assign(nb, -1);
+    P.lr_off.assign(nb, -1);
+    P.dense_pool = P.lr_pool = P.term_pool = 0;
+    P.n_dense_entries = 0;
+    P.max_lr_rows = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+      const Block& bb = B(b);
+      if (bb.kind == BK_DENSE) {
+        P.dense_off[b] = P.dense_pool;
+        P.dense_pool += bb.m * bb.n;
+        P.n_dense_entries += bb.m * bb.n;
+        P.dense_ids.push_back(b);
+        if (bb.row == bb.col) P.diag_leaf_ids.push_back(b);
+      } else if (bb.kind == BK_LR) {
+        P.lr_off[b] = P.lr_pool;
+        P.lr_pool += (bb.m + bb.n) * (int64_t)K_MAX;
+        P.lr_ids.push_back(b);
+        P.max_lr_rows = std::max(P.max_lr_rows, std::max(bb.m, bb.n));
+      }
+    }
+    // symbolic factorisation in program order
+    final_task.assign(nb, -1);
+    leaf_insts.assign(nb, {});
+    hchol(0);
+    // levels (longest path) and ticket order
+    const int32_t nt = (int32_t)tasks.size();
+    std::vector<int32_t> level(nt, 0);
+    for (int32_t i = 0; i < nt; ++i) {
+      int32_t lv = 0;
+      for (int32_t d : tdeps[i]) {
+        if (d >= i) throw std::logic_error("dependency not earlier in program order");
+        lv = std::max(lv, level[d] + 1);
+      }
+      level[i] = lv;
+    }
+    std::vector<int32_t> order(nt);
+    for (int32_t i = 0; i < nt; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return level[a] < level[b]; });
+    std::vector<int32_t> rank(nt);
+    for (int32_t i = 0; i < nt; ++i) rank[order[i]] = i;
+    P.tasks.clear();
+    P.deps.clear();
+    P.insts.clear();
+    P.max_level = 0;
+    for (int32_t k = 0; k < nt; ++k) {
+      int32_t i = order[k];
+      Task t = tasks[i];
+      t.level = level[i];
+      P.max_level = std::max(P.max_level, level[i]);
+      t.dep_begin = (int32_t)P.deps.size();
+      for (int32_t d : tdeps[i]) P.deps.push_back(rank[d]);
+      t.ndeps = (int32_t)tdeps[i].size();
+      t.inst_begin = (int32_t)P.insts.size();
+      t.ninst = 0;
+      if (t.kind != TASK_TERM) {
+        for (const TermInst& in : leaf_insts[t.obj]) P.insts.push_back(in);
+        t.ninst = (int32_t)leaf_insts[t.obj].size();
+      }
+      P.tasks.push_back(t);
+      P.task_prog.push_back(i);
+    }
+    P.prog_obj.resize(nt);
+    for (int32_t i = 0; i < nt; ++i) P.prog_obj[i] = tasks[i].obj;
+    // solve programs for every cluster
+    const int32_t nc = (int32_t)T.cl.size();
+    P.sop_begin.assign(nc + 1, 0);
+    P.sops.clear();
+    for (int32_t c = 0; c < nc; ++c) {
+      P.sop_begin[c] = (int32_t)P.sops.size();
+      solve_prog(c, C(c).begin, P.sops);
+    }
+    P.sop_begin[nc] = (int32_t)P.sops.size();
+  }
+};
+
+}  // namespace
+
+// Bounds and ordering checks of everything the device will index with.
+static void validate(const Tree& T, const Plan& P) {
+  auto fail = [](const char* what) { throw std::logic_error(what); };
+  const int64_t nb = (int64_t)T.bk.size(), nt = (int64_t)P.tasks.size();
+  for (int64_t k = 0; k < nt; ++k) {
+    const Task& t = P.tasks[k];
+    for (int32_t q = 0; q < t.ndeps; ++q) {
+      const int32_t d = P.deps[t.dep_begin + q];
+      if (d < 0 || d >= k) fail("dependency not earlier in ticket order");
+    }
+    if (t.kind == TASK_TERM) {
+      if (t.obj < 0 || t.obj >= (int32_t)P.terms.size()) fail("term id");
+      continue;
+    }
+    if (t.obj < 0 || t.obj >= nb) fail("task block id");
+    const Block& b = T.bk[t.obj];
+    if (t.kind == TASK_LR) {
+      if (b.kind != BK_LR || t.diag != b.col) fail("low-rank task");
+    } else {
+      if (b.kind != BK_DENSE || b.m > LEAF_MAX || b.n > LEAF_MAX) fail("dense task");
+      if (t.diag < 0 || t.diag >= nb || T.bk[t.diag].kind != BK_DENSE || T.bk[t.diag].m != b.n) fail("diag leaf");
+    }
+    for (int32_t q = 0; q < t.ninst; ++q) {
+      const TermInst& in = P.insts[t.inst_begin + q];
+      const TermDef& d = P.terms[in.term];
+      if (in.lr0 < 0 || in.lc0 < 0 || in.lr0 + in.mx > b.m || in.lc0 + in.ny > b.n) fail("instance region");
+      const Block& A = T.bk[d.A];
+      const Block& B = T.bk[d.B];
+      const int64_t xrows = (d.kind == TK_LRB) ? d.rows : A.m;
+      const int64_t yrows = (d.kind == TK_LRA) ? d.rows : B.m;
+      if (in.xr0 < 0 || in.xr0 + in.mx > xrows || in.yr0 < 0 || in.yr0 + in.ny > yrows) fail("instance rows");
+      if (d.kind == TK_DD && (A.kind != BK_DENSE || B.kind != BK_DENSE || A.n != B.n)) fail("dd term");
+      if (d.kind == TK_LRA && A.kind != BK_LR) fail("lrA term");
+      if (d.kind == TK_LRB && B.kind != BK_LR) fail("lrB term");
+    }
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    if (P.sub_begin[b] < 0 || P.sub_end[b] < P.sub_begin[b] || P.sub_end[b] > (int32_t)P.sub_leaves.size())
+      fail("subtree leaf range");
+    for (int32_t q = P.sub_begin[b]; q < P.sub_end[b]; ++q) {
+      const Block& l = T.bk[P.sub_leaves[q]];
+      const Block& bb = T.bk[b];
+      if (l.r0 < bb.r0 || l.r0 + l.m > bb.r0 + bb.m || l.c0 < bb.c0 || l.c0 + l.n > bb.c0 + bb.n)
+        fail("subtree leaf outside its block");
+    }
+  }
+  for (const TermDef& d : P.terms)
+    if (d.kind != TK_DD && (d.buf < 0 || d.buf + d.rows * K_MAX > P.term_pool)) fail("term buffer");
+  for (size_t c = 0; c + 1 < P.sop_begin.size(); ++c) {
+    const int64_t len = T.cl[c].end - T.cl[c].begin;
+    for (int32_t o = P.sop_begin[c]; o < P.sop_begin[c + 1]; ++o) {
+      const SolveOp& op = P.sops[o];
+      const Block& b = T.bk[op.blk];
+      if (op.off < 0 || op.off + b.m > len) fail("solve op rows");
+      if (op.kind == SOP_MATVEC && (op.off2 < 0 || op.off2 + b.n > len)) fail("solve op cols");
+      if (op.kind == SOP_TRSV && (b.kind != BK_DENSE || b.m != b.n)) fail("solve op diag");
+    }
+  }
+}
+
+void build_plan(const Tree& t, Plan& p) {
+  p = Plan{};
+  Planner pl(t, p);
+  pl.run();
+  validate(t, p);
+}
+
+}  // namespace hm

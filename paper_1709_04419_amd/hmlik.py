@@ -1,0 +1,271 @@
+"""Thin Python binding of libhmlik (include/hmlik.h) with the same names.
+
+Argument marshalling only: every step of the likelihood evaluation runs in
+the library's HIP kernels.  There is no CPU fallback: if the shared library
+is missing or cannot be loaded, importing this module raises.
+
+Arrays: coordinates are (n, 2) float64; Z is (n,) or (n, r) float64, either
+a numpy array (host) or a torch CUDA tensor (device pointer, read on the
+context's stream).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmlik.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1709_04419_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+HM_OK, HM_ERR_ARG, HM_ERR_NOT_SPD, HM_ERR_OOM, HM_ERR_DEVICE, HM_ERR_INTERNAL = range(6)
+
+
+class hm_theta(C.Structure):
+    _fields_ = [("sigma2", C.c_double), ("ell", C.c_double), ("nu", C.c_double),
+                ("nugget", C.c_double)]
+
+
+class hm_tree_opts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("eta", C.c_double)]
+
+
+class hm_approx(C.Structure):
+    _fields_ = [("fixed_rank", C.c_int32), ("eps", C.c_double)]
+
+
+class hm_result(C.Structure):
+    _fields_ = [("loglik", C.c_double), ("logdet", C.c_double), ("quadform", C.c_double),
+                ("status", C.c_int32), ("max_rank", C.c_int32), ("fail_block", C.c_int64),
+                ("fail_pivot", C.c_int32), ("t_assemble", C.c_double), ("t_factor", C.c_double),
+                ("t_solve", C.c_double)]
+
+
+_P = C.c_void_p
+_sig = {
+    "hm_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "hm_ctx_destroy": (None, [_P]),
+    "hm_dataset_create": (C.c_int, [_P, _P, C.c_int64, C.POINTER(hm_tree_opts), C.POINTER(_P)]),
+    "hm_dataset_destroy": (None, [_P]),
+    "hm_dataset_set_z": (C.c_int, [_P, _P, C.c_int32, C.c_int32]),
+    "hm_assemble": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx)]),
+    "hm_factor": (C.c_int, [_P]),
+    "hm_solve": (C.c_int, [_P, C.POINTER(hm_result)]),
+    "hm_loglik": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx), C.POINTER(hm_result)]),
+    "hm_dataset_info": (C.c_int, [_P, _P, _P, _P, _P]),
+    "hm_dataset_export_tree": (C.c_int, [_P, _P, _P, _P]),
+    "hm_dataset_export_blocks": (C.c_int, [_P, _P, _P]),
+    "hm_get_block": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int32)]),
+    "hm_get_term": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                              C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "hm_test_truncate": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_double, C.c_int32,
+                                   _P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "hm_status_string": (C.c_char_p, [C.c_int]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class HMError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {hm_status_string(status)} (status {status})")
+        self.status = status
+
+
+def hm_status_string(s: int) -> str:
+    return _lib.hm_status_string(int(s)).decode()
+
+
+def _check(s, where):
+    if s != HM_OK:
+        raise HMError(s, where)
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(int(a.data_ptr()))
+
+
+class Context:
+    """hm_ctx_create / hm_ctx_destroy.  stream: a torch.cuda.Stream, a raw
+    hipStream_t as int, or None for the default stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = _P()
+        raw = None
+        if stream is not None:
+            raw = getattr(stream, "cuda_stream", stream)
+        _check(_lib.hm_ctx_create(int(device), C.c_void_p(raw) if raw else None, C.byref(h)),
+               "hm_ctx_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _lib.hm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Dataset:
+    """hm_dataset_*: trees, schedule and device storage for one set of locations."""
+
+    def __init__(self, ctx: Context, coords, leaf_size: int = 64, eta: float = 2.0):
+        P = np.ascontiguousarray(coords, dtype=np.float64)
+        if P.ndim != 2 or P.shape[1] != 2:
+            raise ValueError("coords must be (n, 2)")
+        self.ctx = ctx
+        self.n = P.shape[0]
+        opts = hm_tree_opts(int(leaf_size), float(eta))
+        h = _P()
+        _check(_lib.hm_dataset_create(ctx._h, _ptr(P), C.c_int64(self.n), C.byref(opts), C.byref(h)),
+               "hm_dataset_create")
+        self._h = h
+        self.r = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hm_dataset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_z(self, Z):
+        on_dev = not isinstance(Z, np.ndarray)
+        if on_dev:
+            if Z.dim() == 1:
+                Z = Z[:, None]
+            Zc = Z.t().contiguous()     # column-major (n, r) == row-major (r, n)
+            r = Zc.shape[0]
+            if Zc.shape[1] != self.n:
+                raise ValueError("Z has the wrong length")
+            _check(_lib.hm_dataset_set_z(self._h, C.c_void_p(int(Zc.data_ptr())), r, 1),
+                   "hm_dataset_set_z")
+        else:
+            Z = np.asarray(Z, dtype=np.float64)
+            if Z.ndim == 1:
+                Z = Z[:, None]
+            if Z.shape[0] != self.n:
+                raise ValueError("Z has the wrong length")
+            r = Z.shape[1]
+            Zc = np.asfortranarray(Z)
+            _check(_lib.hm_dataset_set_z(self._h, C.c_void_p(Zc.ctypes.data), r, 0), "hm_dataset_set_z")
+        self.r = r
+
+    @staticmethod
+    def _args(theta, nugget, eps, rank):
+        sigma2, ell, nu = theta
+        return hm_theta(sigma2, ell, nu, nugget), hm_approx(int(rank), float(eps))
+
+    def assemble(self, theta, nugget, eps=0.0, rank=0):
+        th, ap = self._args(theta, nugget, eps, rank)
+        _check(_lib.hm_assemble(self._h, C.byref(th), C.byref(ap)), "hm_assemble")
+
+    def factor(self) -> int:
+        s = _lib.hm_factor(self._h)
+        if s not in (HM_OK, HM_ERR_NOT_SPD):
+            raise HMError(s, "hm_factor")
+        return s
+
+    def solve(self):
+        out = (hm_result * self.r)()
+        s = _lib.hm_solve(self._h, out)
+        if s not in (HM_OK, HM_ERR_NOT_SPD):
+            raise HMError(s, "hm_solve")
+        return _results(out)
+
+    def loglik(self, theta, nugget, eps=0.0, rank=0):
+        """Eq. (4) for every column of Z; returns a dict of arrays."""
+        th, ap = self._args(theta, nugget, eps, rank)
+        out = (hm_result * self.r)()
+        s = _lib.hm_loglik(self._h, C.byref(th), C.byref(ap), out)
+        if s not in (HM_OK, HM_ERR_NOT_SPD):
+            raise HMError(s, "hm_loglik")
+        return _results(out)
+
+    def info(self):
+        vals = [C.c_int64() for _ in range(4)]
+        _check(_lib.hm_dataset_info(self._h, *[C.byref(v) for v in vals]), "hm_dataset_info")
+        return dict(zip(("n", "nclusters", "nblocks", "ntasks"), (v.value for v in vals)))
+
+    def export_tree(self):
+        inf = self.info()
+        perm = np.empty(self.n, dtype=np.int64)
+        ranges = np.empty((inf["nclusters"], 2), dtype=np.int64)
+        boxes = np.empty((inf["nclusters"], 4), dtype=np.float64)
+        _check(_lib.hm_dataset_export_tree(self._h, _ptr(perm), _ptr(ranges), _ptr(boxes)),
+               "hm_dataset_export_tree")
+        return perm, ranges, boxes
+
+    def export_blocks(self):
+        inf = self.info()
+        rc = np.empty((inf["nblocks"], 4), dtype=np.int64)
+        kind = np.empty(inf["nblocks"], dtype=np.int8)
+        _check(_lib.hm_dataset_export_blocks(self._h, _ptr(rc), _ptr(kind)), "hm_dataset_export_blocks")
+        return rc, kind
+
+    def get_term(self, term: int):
+        """Update term `term`: dict(kind, A, B, factor) (factor None for kind 2)."""
+        kind, k = C.c_int32(), C.c_int32()
+        A, B, rows = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.hm_get_term(self._h, C.c_int64(term), None, C.byref(kind), C.byref(A), C.byref(B),
+                                C.byref(rows), C.byref(k)), "hm_get_term")
+        fac = None
+        if kind.value != 2:
+            buf = np.empty(max(1, rows.value * 64), dtype=np.float64)
+            _check(_lib.hm_get_term(self._h, C.c_int64(term), _ptr(buf), C.byref(kind), C.byref(A), C.byref(B),
+                                    C.byref(rows), C.byref(k)), "hm_get_term")
+            fac = buf[:rows.value * k.value].reshape(k.value, rows.value).T.copy()
+        return dict(kind=kind.value, A=A.value, B=B.value, factor=fac)
+
+    def get_block(self, block: int, rows: int, cols: int):
+        """Dense leaf -> (rows, cols) array; low-rank leaf -> (U, V)."""
+        buf = np.empty((rows + cols) * 64 if rows * cols < (rows + cols) * 64 else rows * cols,
+                       dtype=np.float64)
+        k = C.c_int32()
+        _check(_lib.hm_get_block(self._h, C.c_int64(block), _ptr(buf), C.byref(k)), "hm_get_block")
+        if k.value < 0:
+            return buf[:rows * cols].reshape(cols, rows).T.copy()
+        kk = k.value
+        U = buf[:rows * kk].reshape(kk, rows).T.copy()
+        V = buf[rows * kk:rows * kk + cols * kk].reshape(kk, cols).T.copy()
+        return U, V
+
+
+def test_truncate(ds: "Dataset", X, Y, eps=0.0, rank=0):
+    """hm_test_truncate: device truncation of X Y^T; returns (U, V, seconds)."""
+    X = np.asfortranarray(X, dtype=np.float64)
+    Y = np.asfortranarray(Y, dtype=np.float64)
+    m, r = X.shape
+    n = Y.shape[0]
+    U = np.zeros((m, 64), order="F")
+    V = np.zeros((n, 64), order="F")
+    k = C.c_int32()
+    sec = C.c_double()
+    _check(_lib.hm_test_truncate(ds._h, _ptr(X), m, _ptr(Y), n, r, float(eps), int(rank), _ptr(U), _ptr(V),
+                                 C.byref(k), C.byref(sec)), "hm_test_truncate")
+    kk = k.value
+    Uo = np.asarray(U.reshape(-1, order="F")[:m * kk].reshape(kk, m).T)
+    Vo = np.asarray(V.reshape(-1, order="F")[:n * kk].reshape(kk, n).T)
+    return Uo, Vo, sec.value
+
+
+def _results(out):
+    keys = ("loglik", "logdet", "quadform", "status", "max_rank", "fail_block", "fail_pivot",
+            "t_assemble", "t_factor", "t_solve")
+    return {k: np.array([getattr(o, k) for o in out]) for k in keys}
