@@ -129,6 +129,12 @@ hm_status hm_dataset_export_blocks(const hm_dataset *ds, int64_t *rc, int8_t *ki
  * data must hold (rows + cols) * 64 doubles. */
 hm_status hm_get_block(hm_dataset *ds, int64_t block, double *data, int32_t *rank);
 
+/* Algorithmic floating-point operations of the last hm_factor (dense leaf
+ * Cholesky / triangular solves / update products, low-rank products, QR and
+ * SVD recompressions, forward substitutions), counted by the device from the
+ * actual sizes and ranks.  Used for roofline fractions. */
+hm_status hm_factor_flops(hm_dataset *ds, double *flops);
+
 /* Test hook: the update term `term` of the H-Cholesky schedule (in the order
  * the recursion records them): kind (0: X = U_A, Y = L_B V_A; 1: X = L_A V_B,
  * Y = U_B; 2: X = D_A, Y = D_B), the factor blocks A and B, and for kinds 0/1

@@ -197,6 +197,12 @@ hm_status build_device(hm_dataset* ds) {
   D.ws_stride = stride;
   TRY(dev_alloc(ds, sizeof(double) * stride * NSLOTS, &p));
   D.ws = (double*)p;
+  TRY(dev_alloc(ds, sizeof(double) * (P.tasks.size() + 1), &p));
+  D.task_flops = (double*)p;
+  if (getenv("HMLIK_TASK_TIMES")) {
+    TRY(dev_alloc(ds, sizeof(int64_t) * 2 * (P.tasks.size() + 1), &p));
+    D.task_times = (int64_t*)p;
+  }
   D.spin_limit = getenv("HMLIK_SPIN_LIMIT_S") ? (int64_t)(atof(getenv("HMLIK_SPIN_LIMIT_S")) * 1e8) : 3000000000LL;  // 100 MHz counter; 30 s default
   return HM_OK;
 }
@@ -384,6 +390,21 @@ hm_status hm_factor(hm_dataset* ds) {
   unsigned long long key = 0;
   HIPTRY(hipMemcpy(&flags[0], D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(&key, D.fail_key, sizeof(key), hipMemcpyDeviceToHost));
+  if (D.task_times) {
+    const char* path = getenv("HMLIK_TASK_TIMES");
+    std::vector<int64_t> tt(2 * ds->plan.tasks.size());
+    if (hipMemcpy(tt.data(), D.task_times, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+      if (FILE* f = fopen(path, "w")) {
+        fprintf(f, "task kind obj level ninst start end\n");
+        for (size_t i = 0; i < ds->plan.tasks.size(); ++i) {
+          const Task& t = ds->plan.tasks[i];
+          fprintf(f, "%zu %d %d %d %d %lld %lld\n", i, (int)t.kind, t.obj, t.level, t.ninst, (long long)tt[2 * i],
+                  (long long)tt[2 * i + 1]);
+        }
+        fclose(f);
+      }
+    }
+  }
   ds->assembled = false;
   ds->factored = true;
   ds->fail_block = -1;
@@ -538,6 +559,19 @@ hm_status hm_get_block(hm_dataset* ds, int64_t block, double* data, int32_t* ran
     return HM_OK;
   }
   return HM_ERR_ARG;
+}
+
+hm_status hm_factor_flops(hm_dataset* ds, double* flops) {
+  if (!ds || !flops || !ds->factored) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  HIPTRY(hipStreamSynchronize(ds->ctx->stream));
+  std::vector<double> f(ds->plan.tasks.size());
+  if (!f.empty())
+    HIPTRY(hipMemcpy(f.data(), ds->D.task_flops, sizeof(double) * f.size(), hipMemcpyDeviceToHost));
+  double s = 0.0;
+  for (double v : f) s += v;
+  *flops = s;
+  return HM_OK;
 }
 
 hm_status hm_get_term(hm_dataset* ds, int64_t term, double* data, int32_t* kind, int64_t* A, int64_t* B,

@@ -47,6 +47,8 @@ struct DevData {
   unsigned long long* fail_key;   // min over (program index << 8 | pivot) of failed pivots
   const int32_t* task_prog;       // program-order index of each task
   int32_t* dbg;                   // 4 ints per executor work-group: ticket, phase, awaited task, #done
+  int64_t* task_times;            // optional: start/end real-time stamps per task (nullptr: off)
+  double* task_flops;             // algorithmic flops of each factorization task
   // structure helpers
   const int32_t* sub_begin;
   const int32_t* sub_end;

@@ -197,6 +197,7 @@ struct Smem {
   int32_t task;
   int32_t ival[4];
   double dval[4];
+  double flops;     // algorithmic flop count of the current task (thread 0 accumulates)
 };
 
 // Threads per column when `cols` columns are processed side by side: a power
@@ -216,6 +217,8 @@ __device__ __forceinline__ int group_size(int cols) {
 __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Smem& S) {
   const int p = (int)(m < r ? m : r);
   const int tid = threadIdx.x;
+  if (tid == 0)
+    for (int j = 0; j < p; ++j) S.flops += 2.0 * (m - j) + 4.0 * (double)(m - j) * (r - j - 1);
   for (int j = 0; j < p; ++j) {
     double* a = A + (int64_t)j * lda;
     double s = 0.0;
@@ -340,6 +343,7 @@ __device__ void wg_jacobi(double* G, int px, int py, Smem& S) {
       __syncthreads();
     }
     const int f = S.flag;
+    if (tid == 0) S.flops += 12.0 * (double)px * npairs * (q - 1);
     __syncthreads();
     if (!f) break;
   }
@@ -416,6 +420,12 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
     V[e] = v;
   }
   __syncthreads();
+  if (tid == 0) {
+    double f = 2.0 * px * py * r + 2.0 * (double)n * k * px;   // core product, right vectors
+    for (int j = 0; j < px; ++j) f += 4.0 * (double)(m - j) * k;
+    for (int j = 0; j < py; ++j) f += 4.0 * (double)(n - j) * k;
+    S.flops += f;
+  }
   wg_apply_q(X, m, px, m, S.tau_x, U, k, m);
   wg_apply_q(Y, n, py, n, S.tau_y, V, k, n);
   __syncthreads();
@@ -551,9 +561,11 @@ __device__ __forceinline__ void term_factors(const DevData& D, const TermDef& t,
 // Y += L_blk W for one leaf of the factor: W (ncols(blk) x k, ldw), Y (ldy).
 // tmp: k_blk x k doubles (global or shared).
 __device__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k,
-                            double* Y, int64_t ldy, double sign, double* tmp) {
+                            double* Y, int64_t ldy, double sign, double* tmp, Smem& S) {
   const Block L = D.bk[blk];
   const int tid = threadIdx.x;
+  if (tid == 0)
+    S.flops += (L.kind == BK_DENSE) ? 2.0 * L.m * L.n * k : 2.0 * (double)(L.m + L.n) * D.rank[blk] * k;
   if (L.kind == BK_DENSE) {
     const double* A = D.dense + D.dense_off[blk];
     for (int64_t e = tid; e < L.m * (int64_t)k; e += NT) {
@@ -590,7 +602,7 @@ __device__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int6
 
 // W <- L_cc^{-1} W over cluster c (W: |c| x k, ldw) by the solve program.
 __device__ void run_solve(const DevData& D, int32_t c, double* W, int64_t ldw, int k, double* tmp,
-                          double* lds) {
+                          double* lds, Smem& S) {
   const int tid = threadIdx.x;
   for (int32_t o = D.sop_begin[c]; o < D.sop_begin[c + 1]; ++o) {
     const SolveOp op = D.sops[o];
@@ -604,6 +616,7 @@ __device__ void run_solve(const DevData& D, int32_t c, double* W, int64_t ldw, i
       double* Ws = lds + LEAF_MAX * LEAF_MAX;   // mm x k, leading dimension LEAF_MAX + 1
       const int ldl = LEAF_MAX + 1;
       double* w = W + op.off;
+      if (tid == 0) S.flops += (double)mm * mm * k;
       for (int e = tid; e < mm * mm; e += NT) Ls[e] = A[e];
       for (int e = tid; e < mm * k; e += NT) Ws[(e % mm) + (e / mm) * ldl] = w[(e % mm) + (int64_t)(e / mm) * ldw];
       __syncthreads();
@@ -619,13 +632,13 @@ __device__ void run_solve(const DevData& D, int32_t c, double* W, int64_t ldw, i
       for (int e = tid; e < mm * k; e += NT) w[(e % mm) + (int64_t)(e / mm) * ldw] = Ws[(e % mm) + (e / mm) * ldl];
       __syncthreads();
     } else {
-      leaf_matvec(D, op.blk, W + op.off2, ldw, k, W + op.off, ldw, -1.0, tmp);
+      leaf_matvec(D, op.blk, W + op.off2, ldw, k, W + op.off, ldw, -1.0, tmp, S);
     }
   }
 }
 
 // Term product: Y = L_B V_A (TK_LRA) or X = L_A V_B (TK_LRB).
-__device__ void task_term(const DevData& D, int32_t tid_term, double* tmp) {
+__device__ void task_term(const DevData& D, int32_t tid_term, double* tmp, Smem& S) {
   const TermDef t = D.terms[tid_term];
   const int32_t H = (t.kind == TK_LRA) ? t.B : t.A;      // H-block applied
   const int32_t R = (t.kind == TK_LRA) ? t.A : t.B;      // low-rank block providing V
@@ -638,7 +651,7 @@ __device__ void task_term(const DevData& D, int32_t tid_term, double* tmp) {
   for (int32_t q = D.sub_begin[H]; q < D.sub_end[H]; ++q) {
     const int32_t lf = D.sub_leaves[q];
     const Block L = D.bk[lf];
-    leaf_matvec(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp);
+    leaf_matvec(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp, S);
   }
 }
 
@@ -665,6 +678,7 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
     const double *X, *Y;
     int64_t ldx, ldy;
     term_factors(D, t, X, ldx, Y, ldy);
+    if (tid == 0) S.flops += 2.0 * in.mx * in.ny * r;
     for (int l0 = 0; l0 < r; l0 += 32) {
       const int lc = (r - l0 < 32) ? (r - l0) : 32;
       __syncthreads();
@@ -699,6 +713,7 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
     if (e < cnt) A[e] = dreg[q];
   }
   __syncthreads();
+  if (tid == 0) S.flops += (tk.kind == TASK_DIAG) ? (double)m * m * m / 3.0 : (double)m * n * n;
   if (tk.kind == TASK_DIAG) {
     // right-looking Cholesky in LDS (lower)
     for (int j = 0; j < n; ++j) {
@@ -804,7 +819,7 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   }
   const int k = S.ival[0];
   __syncthreads();
-  if (k > 0) run_solve(D, tk.diag, V, n, k, slot, lds);
+  if (k > 0) run_solve(D, tk.diag, V, n, k, slot, lds, S);
 }
 
 // ------------------------------------------------------------------ executor
@@ -857,7 +872,7 @@ __global__ void __launch_bounds__(NT) k_factor(DevData D) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (tid == 0) dbg[1] = 2;
     const int32_t prog = D.task_prog[t];
-    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot);
+    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
     else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
     else task_dense(D, tk, prog, dyn, S);
     // every wave's stores acknowledged by L2 before the one agent-scope
@@ -884,10 +899,18 @@ __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1)
   for (int32_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) {
     const Task tk = D.tasks[t];
     const int32_t prog = D.task_prog[t];
-    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot);
+    int64_t ts = 0;
+    if (threadIdx.x == 0) S.flops = 0.0;
+    if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
+    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
     else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
     else task_dense(D, tk, prog, dyn, S);
     __syncthreads();
+    if (D.task_times && threadIdx.x == 0) {
+      D.task_times[2 * t] = ts;
+      D.task_times[2 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
+    }
+    if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
   }
 }
 
@@ -908,8 +931,9 @@ __global__ void k_init_sched(int32_t* ticket, int32_t* abort_flag, unsigned long
 // W (n x r, permuted Z) <- L^{-1} W over the whole index set.
 __global__ void __launch_bounds__(NT) k_solve(DevData D, double* W, int r) {
   extern __shared__ double dyn[];
+  __shared__ Smem S;
   double* slot = D.ws;
-  run_solve(D, 0, W, D.n, r, slot, dyn);
+  run_solve(D, 0, W, D.n, r, slot, dyn, S);
 }
 
 // Gather Z into permuted order: W[i, c] = Z[perm[i], c].

@@ -60,6 +60,7 @@ _sig = {
     "hm_dataset_export_tree": (C.c_int, [_P, _P, _P, _P]),
     "hm_dataset_export_blocks": (C.c_int, [_P, _P, _P]),
     "hm_get_block": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int32)]),
+    "hm_factor_flops": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "hm_get_term": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "hm_test_truncate": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_double, C.c_int32,
@@ -218,6 +219,12 @@ class Dataset:
         kind = np.empty(inf["nblocks"], dtype=np.int8)
         _check(_lib.hm_dataset_export_blocks(self._h, _ptr(rc), _ptr(kind)), "hm_dataset_export_blocks")
         return rc, kind
+
+    def factor_flops(self) -> float:
+        """hm_factor_flops: algorithmic flops of the last factorization."""
+        f = C.c_double()
+        _check(_lib.hm_factor_flops(self._h, C.byref(f)), "hm_factor_flops")
+        return f.value
 
     def get_term(self, term: int):
         """Update term `term`: dict(kind, A, B, factor) (factor None for kind 2)."""
