@@ -34,7 +34,12 @@ Cholesky with deferred updates:
 
   FLUSH(b) applies b's terms in order:
                 dense   -> D -= X Y^T per term
-                lowrank -> the product [U, -X_1, ...][V, Y_1, ...]^T is truncated
+                lowrank, both clusters leaves (a block of at most n_min x n_min)
+                        -> the updated block U V^T - sum X Y^T is formed exactly
+                           and replaced by its best approximation at accuracy eps
+                           (or rank k): one truncated SVD (lowrank.truncate_dense)
+                lowrank, otherwise
+                        -> the product [U, -X_1, ...][V, Y_1, ...]^T is truncated
                            (lowrank.truncate); the accumulation is truncated early
                            whenever its rank would exceed R_ACC.
 
@@ -58,7 +63,7 @@ import scipy.linalg
 from scipy.linalg import lapack
 
 from .htree import DENSE, LOWRANK, NODE, BlockTree, ClusterTree
-from .lowrank import K_MAX, aca, truncate
+from .lowrank import K_MAX, aca, truncate, truncate_dense
 from .matern import covariance_block
 
 # Largest rank an accumulation of updates may reach before it is truncated.
@@ -246,6 +251,15 @@ class HLikelihood:
             return
         m = self.rng_r[bid][1] - self.rng_r[bid][0]
         n = self.rng_c[bid][1] - self.rng_c[bid][0]
+        C = self.tree.clusters
+        b = self.bt.blocks[bid]
+        if C[b.row].is_leaf and C[b.col].is_leaf:
+            D = self.U[bid] @ self.V[bid].T
+            for (r0, c0, X, Y) in terms:
+                D[r0:r0 + X.shape[0], c0:c0 + Y.shape[0]] -= X @ Y.T
+            self.stats.flush_terms.append(len(terms))
+            self.U[bid], self.V[bid] = truncate_dense(D, self.eps, self.kfix)
+            return
         Xs, Ys = [self.U[bid]], [self.V[bid]]
         rank = self.U[bid].shape[1]
         peak = rank

@@ -22,6 +22,9 @@ recompression:
        k' is also capped by K_MAX;
        U = Qx W[:, :k'] S[:k'],  V = Qy Z[:, :k'].
 
+  TRUNCATE_DENSE(D) for an explicit (small) block: the same rank rule applied
+       to the SVD D = W S Z^T;  U = W[:, :k'] S[:k'],  V = Z[:, :k'].
+
 The same eps is used for assembly and for the truncations inside the
 H-Cholesky (Tables 6 and 7 quote a single eps for both).
 
@@ -84,6 +87,25 @@ def aca(row_fn, col_fn, m: int, n: int, eps: float, kmax: int):
     return np.stack(Us, axis=1), np.stack(Vs, axis=1)
 
 
+def _keep(s, eps, kfix):
+    if s.size == 0 or s[0] == 0.0:
+        return 0
+    if kfix > 0:
+        k = min(kfix, int(np.count_nonzero(s > 0.0)))
+    else:
+        k = int(np.count_nonzero(s > eps * s[0]))
+    return min(k, K_MAX)
+
+
+def truncate_dense(D: np.ndarray, eps: float, kfix: int):
+    """Best approximation of an explicit block D at relative accuracy eps
+    (kfix == 0) or rank kfix, capped at K_MAX.  Returns (U, V)."""
+    m, n = D.shape
+    W, s, Zt = np.linalg.svd(D)
+    k = _keep(s, eps, kfix)
+    return W[:, :k] * s[:k], Zt[:k, :].T.copy()
+
+
 def truncate(X: np.ndarray, Y: np.ndarray, eps: float, kfix: int):
     """Best approximation of X Y^T at relative accuracy eps (kfix == 0) or
     rank kfix (kfix > 0), capped at K_MAX.  Returns (U, V)."""
@@ -94,13 +116,9 @@ def truncate(X: np.ndarray, Y: np.ndarray, eps: float, kfix: int):
     Qx, Rx = np.linalg.qr(X, mode="reduced")
     Qy, Ry = np.linalg.qr(Y, mode="reduced")
     W, s, Zt = np.linalg.svd(Rx @ Ry.T)
-    if s.size == 0 or s[0] == 0.0:
+    k = _keep(s, eps, kfix)
+    if k == 0:
         return np.zeros((m, 0)), np.zeros((n, 0))
-    if kfix > 0:
-        k = min(kfix, int(np.count_nonzero(s > 0.0)))
-    else:
-        k = int(np.count_nonzero(s > eps * s[0]))
-    k = min(k, K_MAX)
     U = Qx @ (W[:, :k] * s[:k])
     V = Qy @ Zt[:k, :].T
     return U, V

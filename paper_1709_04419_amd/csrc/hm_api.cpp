@@ -200,7 +200,7 @@ hm_status build_device(hm_dataset* ds) {
   TRY(dev_alloc(ds, sizeof(double) * (P.tasks.size() + 1), &p));
   D.task_flops = (double*)p;
   if (getenv("HMLIK_TASK_TIMES")) {
-    TRY(dev_alloc(ds, sizeof(int64_t) * 2 * (P.tasks.size() + 1), &p));
+    TRY(dev_alloc(ds, sizeof(int64_t) * 6 * (P.tasks.size() + 1), &p));
     D.task_times = (int64_t*)p;
   }
   D.spin_limit = getenv("HMLIK_SPIN_LIMIT_S") ? (int64_t)(atof(getenv("HMLIK_SPIN_LIMIT_S")) * 1e8) : 3000000000LL;  // 100 MHz counter; 30 s default
@@ -392,14 +392,15 @@ hm_status hm_factor(hm_dataset* ds) {
   HIPTRY(hipMemcpy(&key, D.fail_key, sizeof(key), hipMemcpyDeviceToHost));
   if (D.task_times) {
     const char* path = getenv("HMLIK_TASK_TIMES");
-    std::vector<int64_t> tt(2 * ds->plan.tasks.size());
+    std::vector<int64_t> tt(6 * ds->plan.tasks.size());
     if (hipMemcpy(tt.data(), D.task_times, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost) == hipSuccess) {
       if (FILE* f = fopen(path, "w")) {
-        fprintf(f, "task kind obj level ninst start end\n");
+        fprintf(f, "task kind obj level ninst start end qr svd apply solve\n");
         for (size_t i = 0; i < ds->plan.tasks.size(); ++i) {
           const Task& t = ds->plan.tasks[i];
-          fprintf(f, "%zu %d %d %d %d %lld %lld\n", i, (int)t.kind, t.obj, t.level, t.ninst, (long long)tt[2 * i],
-                  (long long)tt[2 * i + 1]);
+          fprintf(f, "%zu %d %d %d %d %lld %lld %lld %lld %lld %lld\n", i, (int)t.kind, t.obj, t.level, t.ninst,
+                  (long long)tt[6 * i], (long long)tt[6 * i + 1], (long long)tt[6 * i + 2], (long long)tt[6 * i + 3],
+                  (long long)tt[6 * i + 4], (long long)tt[6 * i + 5]);
         }
         fclose(f);
       }
@@ -605,18 +606,20 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
   D.kfix = fixed_rank;
   D.eps = fixed_rank > 0 ? 0.0 : eps;
   D.kmax = fixed_rank > 0 ? fixed_rank : K_MAX;
-  void *dX = nullptr, *dY = nullptr, *dU = nullptr, *dV = nullptr, *dk = nullptr;
+  void *dX = nullptr, *dY = nullptr, *dU = nullptr, *dV = nullptr, *dk = nullptr, *dph = nullptr;
   hm_status s = HM_OK;
   if (hipMalloc(&dX, sizeof(double) * m * r) != hipSuccess || hipMalloc(&dY, sizeof(double) * n * r) != hipSuccess ||
       hipMalloc(&dU, sizeof(double) * m * K_MAX) != hipSuccess ||
-      hipMalloc(&dV, sizeof(double) * n * K_MAX) != hipSuccess || hipMalloc(&dk, sizeof(int32_t)) != hipSuccess)
+      hipMalloc(&dV, sizeof(double) * n * K_MAX) != hipSuccess || hipMalloc(&dk, sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&dph, sizeof(int64_t) * 4) != hipSuccess)
     s = HM_ERR_OOM;
   if (s == HM_OK) {
     float ms = 0;
     if (hipMemcpy(dX, X, sizeof(double) * m * r, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dY, Y, sizeof(double) * n * r, hipMemcpyHostToDevice) != hipSuccess ||
         hipEventRecord(ds->ev[0], st) != hipSuccess ||
-        launch_truncate_test(D, (double*)dX, m, (double*)dY, n, r, (double*)dU, (double*)dV, (int32_t*)dk, st) !=
+        launch_truncate_test(D, (double*)dX, m, (double*)dY, n, r, (double*)dU, (double*)dV, (int32_t*)dk,
+                             (int64_t*)dph, st) !=
             hipSuccess ||
         hipEventRecord(ds->ev[1], st) != hipSuccess || hipEventSynchronize(ds->ev[1]) != hipSuccess ||
         hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]) != hipSuccess ||
@@ -625,10 +628,15 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
     if (s == HM_OK && (hipMemcpy(U, dU, sizeof(double) * m * (*k), hipMemcpyDeviceToHost) != hipSuccess ||
                        hipMemcpy(V, dV, sizeof(double) * n * (*k), hipMemcpyDeviceToHost) != hipSuccess))
       s = HM_ERR_DEVICE;
-    if (seconds) *seconds = ms * 1e-3;
+    if (seconds) {
+      int64_t ph[3] = {0, 0, 0};
+      (void)hipMemcpy(ph, dph, sizeof(ph), hipMemcpyDeviceToHost);
+      seconds[0] = ms * 1e-3;
+      for (int q = 0; q < 3; ++q) seconds[1 + q] = ph[q] * 1e-8;   // 100 MHz clock
+    }
   }
   (void)hipGetLastError();
-  for (void* q : {dX, dY, dU, dV, dk})
+  for (void* q : {dX, dY, dU, dV, dk, dph})
     if (q) (void)hipFree(q);
   return s;
 }

@@ -82,7 +82,7 @@ hipError_t launch_assemble(const DevData& D, hipStream_t st);
 hipError_t launch_aca(const DevData& D, int grid, hipStream_t st);
 hipError_t launch_factor(const DevData& D, int grid, hipStream_t st);
 hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
-                                int r, double* U, double* V, int32_t* kout, hipStream_t st);
+                                int r, double* U, double* V, int32_t* kout, int64_t* phases, hipStream_t st);
 hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t nlevels, int max_grid,
                                 hipStream_t st);
 hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,

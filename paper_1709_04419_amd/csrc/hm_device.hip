@@ -27,6 +27,7 @@ namespace hm {
 
 #define NT 256
 #define NW 4
+__device__ __forceinline__ int64_t clk() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
 // LDS arena (doubles) of the executor work-groups: one per CU.
 #define LDS_FACTOR 17408
 // LDS arena of the solve kernel: a diagonal leaf and a 64-column panel.
@@ -198,6 +199,7 @@ struct Smem {
   int32_t ival[4];
   double dval[4];
   double flops;     // algorithmic flop count of the current task (thread 0 accumulates)
+  int64_t ph[4];    // per-task phase clocks (QR, SVD, Q application, solve) when timing is on
 };
 
 // Threads per column when `cols` columns are processed side by side: a power
@@ -210,49 +212,116 @@ __device__ __forceinline__ int group_size(int cols) {
 
 // In-place Householder QR of A (m x r, column-major, lda); p = min(m, r)
 // reflectors H_j = I - tau_j v_j v_j^T, v_j(j) = 1 implicit, stored below the
-// diagonal; R on and above it.  The trailing columns of each step are updated
-// side by side, a group of g threads per column (the group that forms a
-// column's dot product also updates that column, so one barrier per step
-// suffices besides the norm reduction).
+// diagonal; R on and above it.
+//
+// One pass and one barrier per step: the trailing columns are processed side
+// by side, a group of g threads per column, and every group forms both its
+// column's dot product with the (still unscaled) pivot column and, redundantly,
+// the pivot column's norm over the same rows, so the reflector is known to
+// every group without a block-wide reduction.  The pivot column itself is
+// scaled into v_j at the start of the next step (nobody reads it then).
 __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Smem& S) {
   const int p = (int)(m < r ? m : r);
   const int tid = threadIdx.x;
   if (tid == 0)
     for (int j = 0; j < p; ++j) S.flops += 2.0 * (m - j) + 4.0 * (double)(m - j) * (r - j - 1);
+  double prev_scale = 0.0, prev_beta = 0.0;
   for (int j = 0; j < p; ++j) {
-    double* a = A + (int64_t)j * lda;
-    double s = 0.0;
-    for (int64_t i = j + 1 + tid; i < m; i += NT) s += a[i] * a[i];
-    s = block_sum(s, S.red);
-    const double alpha = a[j];
-    double t = 0.0, beta = alpha, scale = 0.0;
-    if (s != 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + s), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+    if (j > 0) {
+      // deferred: column j-1 becomes v_{j-1}, its diagonal R_{j-1,j-1}
+      double* ap = A + (int64_t)(j - 1) * lda;
+      if (prev_scale != 0.0)
+        for (int64_t i = j + tid; i < m; i += NT) ap[i] *= prev_scale;
+      if (tid == 0) ap[j - 1] = prev_beta;
     }
-    __syncthreads();
-    if (s != 0.0)
-      for (int64_t i = j + 1 + tid; i < m; i += NT) a[i] *= scale;
-    if (tid == 0) { a[j] = beta; tau[j] = t; }
-    __syncthreads();
+    const double* a = A + (int64_t)j * lda;
+    const double alpha = a[j];
     const int C = r - j - 1;
-    if (t != 0.0 && C > 0) {
+    double s = 0.0, t = 0.0, beta = alpha, scale = 0.0;
+    if (C > 0) {
       const int g = group_size(C);
       const int c = tid / g, gl = tid % g;
+      // the first C groups own a trailing column each; the remaining (idle)
+      // groups only form the pivot norm, over the same row partition
+      double* ac = A + (int64_t)(j + 1 + (c < C ? c : 0)) * lda;
+      double dot = 0.0, nrm = 0.0, acj = 0.0;
+      // four rows in flight per iteration; the partial sums are combined in
+      // a fixed order, identical in every group
+      const int64_t i0 = j + 1 + gl;
+      const int64_t g4 = 4 * (int64_t)g;
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
       if (c < C) {
-        double* ac = A + (int64_t)(j + 1 + c) * lda;
-        double dot = (gl == 0) ? ac[j] : 0.0;
-        for (int64_t i = j + 1 + gl; i < m; i += g) dot += a[i] * ac[i];
-        for (int o = 1; o < g; o <<= 1) dot += __shfl_xor(dot, o, 64);
-        const double f = t * dot;
-        if (gl == 0) ac[j] -= f;
-        for (int64_t i = j + 1 + gl; i < m; i += g) ac[i] -= f * a[i];
+        acj = ac[j];
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int64_t i = i0;
+        for (; i + 3 * g < m; i += g4) {
+          const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+          const double y0 = ac[i], y1 = ac[i + g], y2 = ac[i + 2 * g], y3 = ac[i + 3 * g];
+          n0 += x0 * x0; n1 += x1 * x1; n2 += x2 * x2; n3 += x3 * x3;
+          d0 += x0 * y0; d1 += x1 * y1; d2 += x2 * y2; d3 += x3 * y3;
+        }
+        for (; i < m; i += g) {
+          const double x = a[i];
+          n0 += x * x;
+          d0 += x * ac[i];
+        }
+        dot = (d0 + d1) + (d2 + d3);
+      } else {
+        int64_t i = i0;
+        for (; i + 3 * g < m; i += g4) {
+          const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+          n0 += x0 * x0; n1 += x1 * x1; n2 += x2 * x2; n3 += x3 * x3;
+        }
+        for (; i < m; i += g) n0 += a[i] * a[i];
+      }
+      nrm = (n0 + n1) + (n2 + n3);
+      for (int o = 1; o < g; o <<= 1) {
+        nrm += __shfl_xor(nrm, o, 64);
+        dot += __shfl_xor(dot, o, 64);
+      }
+      s = nrm;
+      if (s != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        if (c < C) {
+          const double f = t * (acj + scale * dot);
+          const double fs = f * scale;
+          if (gl == 0) ac[j] -= f;
+          int64_t i = i0;
+          for (; i + 3 * g < m; i += g4) {
+            const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+            const double y0 = ac[i], y1 = ac[i + g], y2 = ac[i + 2 * g], y3 = ac[i + 3 * g];
+            ac[i] = y0 - fs * x0;
+            ac[i + g] = y1 - fs * x1;
+            ac[i + 2 * g] = y2 - fs * x2;
+            ac[i + 3 * g] = y3 - fs * x3;
+          }
+          for (; i < m; i += g) ac[i] -= fs * a[i];
+        }
+      }
+    } else {
+      double part = 0.0;
+      for (int64_t i = j + 1 + tid; i < m; i += NT) part += a[i] * a[i];
+      s = block_sum(part, S.red);
+      if (s != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + s), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
       }
     }
-    // the next step reads the column this step's trailing update just wrote
+    if (tid == 0) tau[j] = t;
+    prev_scale = (s != 0.0) ? scale : 0.0;
+    prev_beta = beta;
     __syncthreads();
   }
+  if (p > 0) {
+    double* ap = A + (int64_t)(p - 1) * lda;
+    if (prev_scale != 0.0)
+      for (int64_t i = p + tid; i < m; i += NT) ap[i] *= prev_scale;
+    if (tid == 0) ap[p - 1] = prev_beta;
+  }
+  __syncthreads();
 }
 
 // B <- Q B with Q = H_0 ... H_{p-1} from wg_qr (B is m x k, ldb).
@@ -269,12 +338,31 @@ __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const
       const double* a = A + (int64_t)j * lda;
       for (int c = c0; c < k; c += cstep) {
         double* bc = B + (int64_t)c * ldb;
-        double dot = (gl == 0) ? bc[j] : 0.0;
-        for (int64_t i = j + 1 + gl; i < m; i += g) dot += a[i] * bc[i];
+        const int64_t i0 = j + 1 + gl;
+        const int64_t g4 = 4 * (int64_t)g;
+        double d0 = (gl == 0) ? bc[j] : 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int64_t i = i0;
+        for (; i + 3 * g < m; i += g4) {
+          d0 += a[i] * bc[i];
+          d1 += a[i + g] * bc[i + g];
+          d2 += a[i + 2 * g] * bc[i + 2 * g];
+          d3 += a[i + 3 * g] * bc[i + 3 * g];
+        }
+        for (; i < m; i += g) d0 += a[i] * bc[i];
+        double dot = (d0 + d1) + (d2 + d3);
         for (int o = 1; o < g; o <<= 1) dot += __shfl_xor(dot, o, 64);
         const double f = t * dot;
         if (gl == 0) bc[j] -= f;
-        for (int64_t i = j + 1 + gl; i < m; i += g) bc[i] -= f * a[i];
+        i = i0;
+        for (; i + 3 * g < m; i += g4) {
+          const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+          const double y0 = bc[i], y1 = bc[i + g], y2 = bc[i + 2 * g], y3 = bc[i + 3 * g];
+          bc[i] = y0 - f * x0;
+          bc[i + g] = y1 - f * x1;
+          bc[i + 2 * g] = y2 - f * x2;
+          bc[i + 3 * g] = y3 - f * x3;
+        }
+        for (; i < m; i += g) bc[i] -= f * a[i];
       }
     }
     __syncthreads();
@@ -287,12 +375,12 @@ __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const
 // is rotated when its columns are not orthogonal to 2e-15 sqrt(px) relative;
 // columns below 4 max(px,py) eps ||G||_F are numerically zero and are left
 // alone (they carry no singular value that any truncation keeps).
-__device__ void wg_jacobi(double* G, int px, int py, Smem& S) {
+__device__ void wg_jacobi(double* G, int px, int py, int ldg, Smem& S) {
   const int tid = threadIdx.x;
   const int q = (py + 1) & ~1;
   if (q < 2) return;
   double f2 = 0.0;
-  for (int e = tid; e < px * py; e += NT) f2 += G[e] * G[e];
+  for (int e = tid; e < px * py; e += NT) f2 += G[(e % px) + (e / px) * ldg] * G[(e % px) + (e / px) * ldg];
   f2 = block_sum(f2, S.red);
   const double epsm = 2.220446049250313e-16;
   const double tnorm = 4.0 * (double)(px > py ? px : py) * epsm;
@@ -311,8 +399,8 @@ __device__ void wg_jacobi(double* G, int px, int py, Smem& S) {
         else { i = (rnd + pair) % (q - 1); j = (rnd - pair + q - 1) % (q - 1); }
         const bool act = (i < py && j < py);
         double al = 0.0, be = 0.0, ga = 0.0;
-        double* ci = G + (int64_t)(act ? i : 0) * px;
-        double* cj = G + (int64_t)(act ? j : 0) * px;
+        double* ci = G + (int64_t)(act ? i : 0) * ldg;
+        double* cj = G + (int64_t)(act ? j : 0) * ldg;
         if (act) {
           for (int rr = gl; rr < px; rr += g) {
             const double u = ci[rr], v = cj[rr];
@@ -349,34 +437,77 @@ __device__ void wg_jacobi(double* G, int px, int py, Smem& S) {
   }
 }
 
+__device__ __forceinline__ int64_t odd_ld(int64_t rows) { return rows | 1; }
+
+// B <- Q B (wg_apply_q) with the reflectors and B staged through LDS when both
+// fit (odd leading dimensions against bank conflicts).
+__device__ void wg_apply_q_staged(const double* A, int64_t m, int p, const double* tau, double* B, int k,
+                                  double* lds, int lds_cap) {
+  const int tid = threadIdx.x;
+  if (k <= 0) return;
+  const int64_t ld = odd_ld(m);
+  if (ld * (p + k) <= lds_cap) {
+    double* As = lds;
+    double* Bs = lds + ld * p;
+    for (int64_t e = tid; e < m * p; e += NT) As[(e % m) + (e / m) * ld] = A[e];
+    for (int64_t e = tid; e < m * k; e += NT) Bs[(e % m) + (e / m) * ld] = B[e];
+    __syncthreads();
+    wg_apply_q(As, m, p, ld, tau, Bs, k, ld);
+    for (int64_t e = tid; e < m * k; e += NT) B[e] = Bs[(e % m) + (e / m) * ld];
+    __syncthreads();
+  } else {
+    wg_apply_q(A, m, p, m, tau, B, k, m);
+  }
+}
+
 // Best approximation of X Y^T (X: m x r, Y: n x r, in workspace, destroyed) at
-// relative accuracy eps (kfix == 0) or rank kfix, capped at kmax.  Writes
+// relative accuracy eps (kfix == 0) or rank kfix, capped at kmax: Householder
+// QR of both factors, one-sided Jacobi SVD of the small core Rx Ry^T, then the
+// kept singular vectors mapped back through the reflectors.  Writes
 // U (m x k, ldu = m) and V (n x k, ldv = n); returns k.
-// scratch: at least r*r + r*r doubles of global workspace.
+// scratch: at least 2 r^2 doubles of global workspace.
 __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, int64_t n, int r,
                            double* U, double* V, double* scratch, double* lds_g, int lds_cap, Smem& S) {
   const int tid = threadIdx.x;
   if (r == 0) return 0;
-  wg_qr(X, m, r, m, S.tau_x, S);
-  wg_qr(Y, n, r, n, S.tau_y, S);
+  int64_t c0 = (tid == 0) ? clk() : 0;
+  // QR of each factor, staged through LDS when it fits (copy in, factor, copy back)
+  for (int side = 0; side < 2; ++side) {
+    double* A = side ? Y : X;
+    const int64_t rows = side ? n : m;
+    double* tau = side ? S.tau_y : S.tau_x;
+    const int64_t ld = odd_ld(rows);
+    if (ld * (int64_t)r <= lds_cap) {
+      for (int64_t e = tid; e < rows * r; e += NT) lds_g[(e % rows) + (e / rows) * ld] = A[e];
+      __syncthreads();
+      wg_qr(lds_g, rows, r, ld, tau, S);
+      for (int64_t e = tid; e < rows * r; e += NT) A[e] = lds_g[(e % rows) + (e / rows) * ld];
+      __syncthreads();
+    } else {
+      wg_qr(A, rows, r, rows, tau, S);
+    }
+  }
   const int px = (int)(m < r ? m : r), py = (int)(n < r ? n : r);
   // M = Rx Ry^T  (px x py), keep a copy for the right singular vectors
   double* M = scratch;
-  double* G = (px * py <= lds_cap) ? lds_g : scratch + (int64_t)px * py;   // LDS unless it cannot fit
+  const int gld = (int)odd_ld(px);
+  double* G = ((int64_t)gld * py <= lds_cap) ? lds_g : scratch + (int64_t)px * py;
   for (int e = tid; e < px * py; e += NT) {
     const int i = e % px, j = e / px;
     const int l0 = i > j ? i : j;
     double acc = 0.0;
     for (int l = l0; l < r; ++l) acc += X[i + (int64_t)l * m] * Y[j + (int64_t)l * n];
     M[e] = acc;
-    G[e] = acc;
+    G[i + j * gld] = acc;
   }
   __syncthreads();
-  wg_jacobi(G, px, py, S);
+  if (tid == 0) { const int64_t c1 = clk(); S.ph[0] += c1 - c0; c0 = c1; }
+  wg_jacobi(G, px, py, gld, S);
+  if (tid == 0) { const int64_t c1 = clk(); S.ph[1] += c1 - c0; c0 = c1; }
   // singular values, ordering (descending, ties by index)
   for (int j = tid; j < py; j += NT) {
     double s = 0.0;
-    for (int i = 0; i < px; ++i) s += G[i + j * px] * G[i + j * px];
+    for (int i = 0; i < px; ++i) s += G[i + j * gld] * G[i + j * gld];
     S.sig[j] = sqrt(s);
   }
   __syncthreads();
@@ -405,7 +536,7 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
   for (int64_t e = tid; e < m * (int64_t)k; e += NT) {
     const int64_t i = e % m;
     const int l = (int)(e / m);
-    U[e] = (i < px) ? G[i + (int64_t)S.ord[l] * px] : 0.0;
+    U[e] = (i < px) ? G[i + (int64_t)S.ord[l] * gld] : 0.0;
   }
   for (int64_t e = tid; e < n * (int64_t)k; e += NT) {
     const int64_t j = e % n;
@@ -414,7 +545,7 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
     if (j < py) {
       const int o = S.ord[l];
       const double sg = S.sig[o];
-      for (int i = 0; i < px; ++i) v += M[i + (int64_t)j * px] * G[i + (int64_t)o * px];
+      for (int i = 0; i < px; ++i) v += M[i + (int64_t)j * px] * G[i + (int64_t)o * gld];
       v = v / (sg * sg);
     }
     V[e] = v;
@@ -426,9 +557,10 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
     for (int j = 0; j < py; ++j) f += 4.0 * (double)(n - j) * k;
     S.flops += f;
   }
-  wg_apply_q(X, m, px, m, S.tau_x, U, k, m);
-  wg_apply_q(Y, n, py, n, S.tau_y, V, k, n);
+  wg_apply_q_staged(X, m, px, S.tau_x, U, k, lds_g, lds_cap);
+  wg_apply_q_staged(Y, n, py, S.tau_y, V, k, lds_g, lds_cap);
   __syncthreads();
+  if (tid == 0) S.ph[2] += clk() - c0;
   return k;
 }
 
@@ -655,21 +787,14 @@ __device__ void task_term(const DevData& D, int32_t tid_term, double* tmp, Smem&
   }
 }
 
-// Dense leaf: flush its terms, then Cholesky (diagonal) or triangular solve.
-__device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, double* lds, Smem& S) {
+// Subtracts a leaf's restricted update terms, in order, from an m x n tile
+// held in registers (entry e = tid + q NT of the column-major tile in
+// dreg[q]).  Term factors are staged through LDS 32 columns at a time.
+__device__ void apply_terms(const DevData& D, const Task& tk, int m, int n, double (&dreg)[16], double* lds,
+                            Smem& S) {
   const int tid = threadIdx.x;
-  const int32_t b = tk.obj;
-  const Block bk = D.bk[b];
-  const int m = (int)bk.m, n = (int)bk.n;
-  double* Dg = D.dense + D.dense_off[b];
-  double dreg[16];
   const int cnt = m * n;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + q * NT;
-    dreg[q] = (e < cnt) ? Dg[e] : 0.0;
-  }
-  double* Xs = lds;                 // 64 x 32 chunk
+  double* Xs = lds;                 // 64 x 32 chunk, row stride 33
   double* Ys = lds + 64 * 33;       // 64 x 32 chunk, row stride 33
   for (int32_t ii = 0; ii < tk.ninst; ++ii) {
     const TermInst in = D.insts[tk.inst_begin + ii];
@@ -705,6 +830,23 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
       }
     }
   }
+}
+
+// Dense leaf: flush its terms, then Cholesky (diagonal) or triangular solve.
+__device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, double* lds, Smem& S) {
+  const int tid = threadIdx.x;
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int m = (int)bk.m, n = (int)bk.n;
+  double* Dg = D.dense + D.dense_off[b];
+  double dreg[16];
+  const int cnt = m * n;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + q * NT;
+    dreg[q] = (e < cnt) ? Dg[e] : 0.0;
+  }
+  apply_terms(D, tk, m, n, dreg, lds, S);
   __syncthreads();
   double* A = lds;                  // m x n tile, column-major
 #pragma unroll
@@ -761,6 +903,94 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
   __syncthreads();
 }
 
+// Low-rank leaf whose row and column clusters are both leaves (at most
+// n_min x n_min): the updated block U V^T - sum X Y^T is formed exactly in
+// registers and replaced by its truncated SVD (one-sided Jacobi on the tile).
+// Returns the new rank (also written to D.rank).
+__device__ int lr_dense_flush(const DevData& D, const Task& tk, double* lds, Smem& S) {
+  const int tid = threadIdx.x;
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int m = (int)bk.m, n = (int)bk.n;
+  double* U = D.lr + D.lr_off[b];
+  double* V = U + (int64_t)m * K_MAX;
+  const int k0 = D.rank[b];
+  const int cnt = m * n;
+  double dreg[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + q * NT;
+    double acc = 0.0;
+    if (e < cnt) {
+      const int i = e % m, j = e / m;
+      for (int l = 0; l < k0; ++l) acc += U[i + l * m] * V[j + l * n];
+    }
+    dreg[q] = acc;
+  }
+  if (tid == 0) S.flops += 2.0 * m * n * k0;
+  apply_terms(D, tk, m, n, dreg, lds, S);
+  __syncthreads();
+  const int ld = m | 1;
+  double* A0 = lds;                 // the updated block, kept for the right vectors
+  double* G = lds + ld * n;         // Jacobi working copy
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + q * NT;
+    if (e < cnt) {
+      const int i = e % m, j = e / m;
+      A0[i + j * ld] = dreg[q];
+      G[i + j * ld] = dreg[q];
+    }
+  }
+  __syncthreads();
+  wg_jacobi(G, m, n, ld, S);
+  for (int j = tid; j < n; j += NT) {
+    double sq = 0.0;
+    for (int i = 0; i < m; ++i) sq += G[i + j * ld] * G[i + j * ld];
+    S.sig[j] = sqrt(sq);
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += NT) {
+    int rk = 0;
+    const double sj = S.sig[j];
+    for (int i = 0; i < n; ++i) {
+      const double si = S.sig[i];
+      if (si > sj || (si == sj && i < j)) ++rk;
+    }
+    S.ord[rk] = j;
+  }
+  __syncthreads();
+  const double s1 = S.sig[S.ord[0]];
+  int k = 0;
+  if (s1 > 0.0) {
+    if (D.kfix > 0) {
+      for (int l = 0; l < n; ++l) if (S.sig[S.ord[l]] > 0.0) ++k;
+      if (k > D.kfix) k = D.kfix;
+    } else {
+      for (int l = 0; l < n; ++l) if (S.sig[S.ord[l]] > D.eps * s1) ++k;
+    }
+    if (k > D.kmax) k = D.kmax;
+  }
+  for (int e = tid; e < m * k; e += NT) {
+    const int i = e % m, l = e / m;
+    U[i + l * m] = G[i + S.ord[l] * ld];
+  }
+  for (int e = tid; e < n * k; e += NT) {
+    const int j = e % n, l = e / n;
+    const int o = S.ord[l];
+    const double sg = S.sig[o];
+    double v = 0.0;
+    for (int i = 0; i < m; ++i) v += A0[i + j * ld] * G[i + o * ld];
+    V[j + l * n] = v / (sg * sg);
+  }
+  if (tid == 0) {
+    S.flops += 2.0 * (double)n * m * k;
+    D.rank[b] = k;
+  }
+  __syncthreads();
+  return k;
+}
+
 // Low-rank leaf: truncate U V^T minus its terms (in order, R_ACC at a time),
 // then V <- L_{sigma sigma}^{-1} V.
 __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
@@ -771,7 +1001,12 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   const int RW = 2 * K_MAX;
   double* U = D.lr + D.lr_off[b];
   double* V = U + m * K_MAX;
-  if (tk.ninst > 0) {
+  const bool leafpair = D.cl[bk.row].son[0] < 0 && D.cl[bk.col].son[0] < 0;
+  if (tk.ninst > 0 && leafpair) {
+    const int kk = lr_dense_flush(D, tk, lds, S);
+    if (tid == 0) S.ival[0] = kk;
+    __syncthreads();
+  } else if (tk.ninst > 0) {
     double* Xa = slot;
     double* Ya = Xa + m * RW;
     double* scratch = Ya + n * RW;
@@ -819,7 +1054,9 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   }
   const int k = S.ival[0];
   __syncthreads();
+  int64_t c0 = (tid == 0) ? clk() : 0;
   if (k > 0) run_solve(D, tk.diag, V, n, k, slot, lds, S);
+  if (tid == 0) S.ph[3] += clk() - c0;
 }
 
 // ------------------------------------------------------------------ executor
@@ -900,15 +1137,16 @@ __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1)
     const Task tk = D.tasks[t];
     const int32_t prog = D.task_prog[t];
     int64_t ts = 0;
-    if (threadIdx.x == 0) S.flops = 0.0;
+    if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = 0; }
     if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
     if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
     else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
     else task_dense(D, tk, prog, dyn, S);
     __syncthreads();
     if (D.task_times && threadIdx.x == 0) {
-      D.task_times[2 * t] = ts;
-      D.task_times[2 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
+      D.task_times[6 * t] = ts;
+      D.task_times[6 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
+      for (int q = 0; q < 4; ++q) D.task_times[6 * t + 2 + q] = S.ph[q];
     }
     if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
   }
@@ -971,7 +1209,7 @@ __global__ void __launch_bounds__(NT) k_reduce(DevData D, const int32_t* diag_id
 // slot 0) into U (m x k), V (n x k); k written to *kout.
 __global__ void __launch_bounds__(NT) k_truncate_test(DevData D, const double* X, int64_t m,
                                                       const double* Y, int64_t n, int r, double* U,
-                                                      double* V, int32_t* kout) {
+                                                      double* V, int32_t* kout, int64_t* phases) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
   double* Xa = D.ws;
@@ -979,18 +1217,22 @@ __global__ void __launch_bounds__(NT) k_truncate_test(DevData D, const double* X
   double* scratch = Ya + n * r;
   for (int64_t e = threadIdx.x; e < m * r; e += NT) Xa[e] = X[e];
   for (int64_t e = threadIdx.x; e < n * r; e += NT) Ya[e] = Y[e];
+  if (threadIdx.x == 0) S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = 0;
   __syncthreads();
   const int k = wg_truncate(D, Xa, m, Ya, n, r, U, V, scratch, dyn, LDS_FACTOR, S);
-  if (threadIdx.x == 0) *kout = k;
+  if (threadIdx.x == 0) {
+    *kout = k;
+    for (int q = 0; q < 3; ++q) phases[q] = S.ph[q];
+  }
 }
 
 hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
-                                int r, double* U, double* V, int32_t* kout, hipStream_t st) {
+                                int r, double* U, double* V, int32_t* kout, int64_t* phases, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute((const void*)k_truncate_test, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      LDS_FACTOR * sizeof(double));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_truncate_test, dim3(1), dim3(NT), LDS_FACTOR * sizeof(double), st, D, X, m, Y, n, r, U, V,
-                     kout);
+                     kout, phases);
   return hipGetLastError();
 }
 

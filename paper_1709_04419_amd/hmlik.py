@@ -64,7 +64,7 @@ _sig = {
     "hm_get_term": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "hm_test_truncate": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_double, C.c_int32,
-                                   _P, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+                                   _P, _P, C.POINTER(C.c_int32), _P]),
     "hm_status_string": (C.c_char_p, [C.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -255,7 +255,7 @@ class Dataset:
 
 
 def test_truncate(ds: "Dataset", X, Y, eps=0.0, rank=0):
-    """hm_test_truncate: device truncation of X Y^T; returns (U, V, seconds)."""
+    """hm_test_truncate: device truncation of X Y^T; returns (U, V, [total, qr, svd, back] seconds)."""
     X = np.asfortranarray(X, dtype=np.float64)
     Y = np.asfortranarray(Y, dtype=np.float64)
     m, r = X.shape
@@ -263,13 +263,13 @@ def test_truncate(ds: "Dataset", X, Y, eps=0.0, rank=0):
     U = np.zeros((m, 64), order="F")
     V = np.zeros((n, 64), order="F")
     k = C.c_int32()
-    sec = C.c_double()
+    sec = (C.c_double * 4)()
     _check(_lib.hm_test_truncate(ds._h, _ptr(X), m, _ptr(Y), n, r, float(eps), int(rank), _ptr(U), _ptr(V),
-                                 C.byref(k), C.byref(sec)), "hm_test_truncate")
+                                 C.byref(k), sec), "hm_test_truncate")
     kk = k.value
     Uo = np.asarray(U.reshape(-1, order="F")[:m * kk].reshape(kk, m).T)
     Vo = np.asarray(V.reshape(-1, order="F")[:n * kk].reshape(kk, n).T)
-    return Uo, Vo, sec.value
+    return Uo, Vo, list(sec)
 
 
 def _results(out):

@@ -87,3 +87,19 @@ def test_truncate_fixed_rank_and_cap():
 def test_truncate_zero():
     U, V = truncate(np.zeros((5, 2)), np.ones((4, 2)), 1e-8, 0)
     assert U.shape == (5, 0) and V.shape == (4, 0)
+
+
+@pytest.mark.parametrize("eps,k", [(1e-6, 0), (1e-12, 0), (0.0, 5)])
+def test_truncate_dense_eckart_young(eps, k):
+    from oracle.lowrank import truncate_dense
+    rng = np.random.default_rng(3)
+    D = rng.standard_normal((40, 30)) @ np.diag(np.logspace(0, -14, 30)) @ rng.standard_normal((30, 33))
+    U, V = truncate_dense(D, eps, k)
+    sv = np.linalg.svd(D, compute_uv=False)
+    kk = k if k else int(np.count_nonzero(sv > eps * sv[0]))
+    assert U.shape[1] == kk
+    assert np.linalg.norm(D - U @ V.T, 2) <= sv[kk] * (1 + 1e-6) + 1e-14 * sv[0]
+    # same best approximation as the factored truncation of D = D * I
+    from oracle.lowrank import truncate
+    U2, V2 = truncate(D, np.eye(33), eps, k)
+    assert np.allclose(U @ V.T, U2 @ V2.T, atol=1e-12 * sv[0])
