@@ -34,7 +34,7 @@ Cholesky with deferred updates:
 
   FLUSH(b) applies b's terms in order:
                 dense   -> D -= X Y^T per term
-                lowrank, both clusters leaves (a block of at most n_min x n_min)
+                lowrank, both clusters of at most DENSE_FLUSH * n_min points
                         -> the updated block U V^T - sum X Y^T is formed exactly
                            and replaced by its best approximation at accuracy eps
                            (or rank k): one truncated SVD (lowrank.truncate_dense)
@@ -49,7 +49,7 @@ diagonal leaves in permuted order.
 
 Parity pins (tests/test_oracle_hchol.py): with no admissible blocks (eta = 0)
 the method is an exact blocked Cholesky and must equal the dense oracle to
-rounding ("the full rank gives an exact representation", Section 1); at tiny
+rounding (a full-rank block is represented exactly, Section 1); at tiny
 eps it converges to the dense value; Theorem 1's bound holds against the
 dense oracle at several eps; ||C~ - L~ L~^T|| / ||C~|| = O(eps).
 """
@@ -68,6 +68,12 @@ from .matern import covariance_block
 
 # Largest rank an accumulation of updates may reach before it is truncated.
 R_ACC = 64
+# A low-rank block whose row and column clusters both hold at most
+# DENSE_FLUSH * n_min points takes its pending updates on the explicit matrix
+# (it is no larger than a 4 x 4 array of dense leaves) and is truncated once:
+# the best approximation of the exact sum (Remark 2.4's truncation applied to
+# the formatted sum as a whole).
+DENSE_FLUSH = 4
 
 
 class NotSPD(Exception):
@@ -93,6 +99,7 @@ class HLikelihood:
     def __init__(self, P, n_min=32, eta=2.0):
         self.P = np.asarray(P, dtype=np.float64)
         self.n = len(self.P)
+        self.n_min = n_min
         self.tree = ClusterTree(self.P, n_min)
         self.bt = BlockTree(self.tree, eta)
         self.perm = self.tree.perm
@@ -253,7 +260,7 @@ class HLikelihood:
         n = self.rng_c[bid][1] - self.rng_c[bid][0]
         C = self.tree.clusters
         b = self.bt.blocks[bid]
-        if C[b.row].is_leaf and C[b.col].is_leaf:
+        if max(m, n) <= DENSE_FLUSH * self.n_min:
             D = self.U[bid] @ self.V[bid].T
             for (r0, c0, X, Y) in terms:
                 D[r0:r0 + X.shape[0], c0:c0 + Y.shape[0]] -= X @ Y.T

@@ -3,6 +3,7 @@
 // per-theta evaluation of eq. (4) of Section 3.1.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -190,9 +191,14 @@ hm_status build_device(hm_dataset* ds) {
   D.nlr = (int32_t)P.lr_ids.size();
   TRY(upload(ds, P.diag_leaf_ids, &ds->d_diag_ids));
   TRY(upload(ds, T.perm, &ds->d_perm));
-  // workspace slots: truncation of (m + n) x 2 K_MAX factors plus small scratch
+  // workspace slots: truncation of (m + n) x 2 K_MAX factors plus small
+  // scratch, or an explicit block of at most dflush x dflush with the
+  // transposed triangular factor of its pivoted QR
   const int64_t mr = P.max_lr_rows > 64 ? P.max_lr_rows : 64;
-  int64_t stride = 2 * mr * (2 * K_MAX) + mr + 2 * (2 * K_MAX) * (2 * K_MAX) + 4096;
+  D.dflush = DENSE_FLUSH * T.leaf_size;
+  const int64_t df = D.dflush;
+  int64_t stride = 2 * mr * (2 * K_MAX) + mr + 2 * (2 * K_MAX + 1) * (2 * K_MAX) + 4096;
+  if (stride < df * df + (df + 1) * df + 64) stride = df * df + (df + 1) * df + 64;
   stride = (stride + 63) & ~(int64_t)63;
   D.ws_stride = stride;
   TRY(dev_alloc(ds, sizeof(double) * stride * NSLOTS, &p));
@@ -200,7 +206,7 @@ hm_status build_device(hm_dataset* ds) {
   TRY(dev_alloc(ds, sizeof(double) * (P.tasks.size() + 1), &p));
   D.task_flops = (double*)p;
   if (getenv("HMLIK_TASK_TIMES")) {
-    TRY(dev_alloc(ds, sizeof(int64_t) * 6 * (P.tasks.size() + 1), &p));
+    TRY(dev_alloc(ds, sizeof(int64_t) * 7 * (P.tasks.size() + 1), &p));
     D.task_times = (int64_t*)p;
   }
   D.spin_limit = getenv("HMLIK_SPIN_LIMIT_S") ? (int64_t)(atof(getenv("HMLIK_SPIN_LIMIT_S")) * 1e8) : 3000000000LL;  // 100 MHz counter; 30 s default
@@ -379,7 +385,24 @@ hm_status hm_factor(hm_dataset* ds) {
     }
     HIPTRY(launch_factor(D, grid, st));
   } else {
-    HIPTRY(launch_factor_levels(D, ds->level_begin.data(), (int32_t)ds->level_begin.size() - 1, NSLOTS, st));
+    const int32_t nlev = (int32_t)ds->level_begin.size() - 1;
+    // HMLIK_PROGRESS=<levels>: synchronise every <levels> levels and report
+    // progress on stderr (for long factorisations; costs a sync per chunk)
+    int32_t chunk = nlev;
+    if (const char* e = getenv("HMLIK_PROGRESS")) chunk = std::max(1, atoi(e));
+    for (int32_t l0 = 0; l0 < nlev; l0 += chunk) {
+      const int32_t l1 = std::min(nlev, l0 + chunk);
+      HIPTRY(launch_factor_levels(D, ds->level_begin.data(), l0, l1, l0 == 0, NSLOTS, st));
+      if (l1 < nlev) {
+        HIPTRY(hipStreamSynchronize(st));
+        HIPTRY(hipEventRecord(ds->ev[2], st));
+        HIPTRY(hipEventSynchronize(ds->ev[2]));
+        float ms = 0;
+        HIPTRY(hipEventElapsedTime(&ms, ds->ev[1], ds->ev[2]));
+        fprintf(stderr, "hmlik factor: level %d of %d, task %d of %d, %.1f s\n", l1, nlev, ds->level_begin[l1],
+                ds->level_begin[nlev], ms * 1e-3);
+      }
+    }
   }
   HIPTRY(hipEventRecord(ds->ev[2], st));
   HIPTRY(hipEventSynchronize(ds->ev[2]));
@@ -392,15 +415,15 @@ hm_status hm_factor(hm_dataset* ds) {
   HIPTRY(hipMemcpy(&key, D.fail_key, sizeof(key), hipMemcpyDeviceToHost));
   if (D.task_times) {
     const char* path = getenv("HMLIK_TASK_TIMES");
-    std::vector<int64_t> tt(6 * ds->plan.tasks.size());
+    std::vector<int64_t> tt(7 * ds->plan.tasks.size());
     if (hipMemcpy(tt.data(), D.task_times, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost) == hipSuccess) {
       if (FILE* f = fopen(path, "w")) {
-        fprintf(f, "task kind obj level ninst start end qr svd apply solve\n");
+        fprintf(f, "task kind obj level ninst start end qr svd apply solve form\n");
         for (size_t i = 0; i < ds->plan.tasks.size(); ++i) {
           const Task& t = ds->plan.tasks[i];
-          fprintf(f, "%zu %d %d %d %d %lld %lld %lld %lld %lld %lld\n", i, (int)t.kind, t.obj, t.level, t.ninst,
-                  (long long)tt[6 * i], (long long)tt[6 * i + 1], (long long)tt[6 * i + 2], (long long)tt[6 * i + 3],
-                  (long long)tt[6 * i + 4], (long long)tt[6 * i + 5]);
+          fprintf(f, "%zu %d %d %d %d", i, (int)t.kind, t.obj, t.level, t.ninst);
+          for (int q = 0; q < 7; ++q) fprintf(f, " %lld", (long long)tt[7 * i + q]);
+          fprintf(f, "\n");
         }
         fclose(f);
       }
@@ -599,7 +622,7 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
                            double eps, int32_t fixed_rank, double* U, double* V, int32_t* k, double* seconds) {
   if (!ds || !X || !Y || !U || !V || !k || m < 1 || n < 1 || r < 1 || r > 2 * K_MAX) return HM_ERR_ARG;
   if (fixed_rank < 0 || fixed_rank > K_MAX || (fixed_rank == 0 && !finite_pos(eps))) return HM_ERR_ARG;
-  if ((m + n) * (int64_t)r + 2 * (int64_t)r * r > ds->D.ws_stride) return HM_ERR_ARG;
+  if ((m + n) * (int64_t)r + 2 * (int64_t)(r + 1) * r + 64 > ds->D.ws_stride) return HM_ERR_ARG;
   HIPTRY(hipSetDevice(ds->ctx->device));
   hipStream_t st = ds->ctx->stream;
   DevData D = ds->D;

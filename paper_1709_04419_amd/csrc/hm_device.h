@@ -70,6 +70,7 @@ struct DevData {
   double eps;
   int32_t kfix;
   int32_t kmax;               // rank cap (K_MAX, or kfix)
+  int32_t dflush;             // low-rank blocks of at most dflush x dflush take their updates explicitly
   int64_t spin_limit;         // bounded wait (s_memrealtime ticks)
 };
 
@@ -83,8 +84,10 @@ hipError_t launch_aca(const DevData& D, int grid, hipStream_t st);
 hipError_t launch_factor(const DevData& D, int grid, hipStream_t st);
 hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
                                 int r, double* U, double* V, int32_t* kout, int64_t* phases, hipStream_t st);
-hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t nlevels, int max_grid,
-                                hipStream_t st);
+// Launches levels [l0, l1) of the task DAG, one kernel per level; `init`
+// clears the breakdown flags first (the first chunk of a factorisation).
+hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, bool init,
+                                int max_grid, hipStream_t st);
 hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,
                         const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st);
 }  // namespace hm

@@ -25,8 +25,17 @@
 
 namespace hm {
 
-#define NT 256
-#define NW 4
+// Threads per work-group (4 wavefronts, one per SIMD: one work-group per CU,
+// as the executor's LDS arena takes most of the CU's LDS anyway).
+#ifndef HM_NT
+#define HM_NT 256
+#endif
+#define NT HM_NT
+#define NW (NT / 64)
+// Register tile of a dense leaf: entry e = tid + q NT, q < NQ.
+#define NQ ((LEAF_MAX * LEAF_MAX + NT - 1) / NT)
+// Most columns of a matrix that is truncated in explicit form.
+#define CMAX (4 * LEAF_MAX)
 __device__ __forceinline__ int64_t clk() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
 // LDS arena (doubles) of the executor work-groups: one per CU.
 #define LDS_FACTOR 17408
@@ -48,7 +57,15 @@ __device__ double block_sum(double v, double* red) {
   __syncthreads();
   if (l == 0) red[w] = v;
   __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+  // pairwise over the wavefronts, fixed order
+  double t[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) t[k] = red[k];
+#pragma unroll
+  for (int h = 1; h < NW; h <<= 1)
+#pragma unroll
+    for (int k = 0; k + h < NW; k += 2 * h) t[k] += t[k + h];
+  return t[0];
 }
 
 // Arg-max of val over the work-group; ties go to the lowest index.
@@ -188,18 +205,21 @@ __global__ void __launch_bounds__(NT) k_assemble_dense(DevData D) {
 // ------------------------------------------------------------------ QR / SVD
 
 struct Smem {
-  double red[8];
-  int64_t redi[8];
+  double red[NW];
+  int64_t redi[NW];
   double tau_x[2 * K_MAX];
   double tau_y[2 * K_MAX];
-  double sig[2 * K_MAX];
-  int32_t ord[2 * K_MAX];
+  double sig[CMAX];
+  int32_t ord[CMAX];
+  double cn[2][CMAX];      // pivoted QR: partial column norms^2 (by column), by step parity
+  int32_t pos[2][CMAX];    // pivoted QR: column at each position, by step parity
+  double tau_p[CMAX];      // pivoted QR: reflector coefficients
   int32_t flag;
   int32_t task;
   int32_t ival[4];
   double dval[4];
   double flops;     // algorithmic flop count of the current task (thread 0 accumulates)
-  int64_t ph[4];    // per-task phase clocks (QR, SVD, Q application, solve) when timing is on
+  int64_t ph[5];    // per-task phase clocks (QR, SVD, Q application, solve, explicit formation)
 };
 
 // Threads per column when `cols` columns are processed side by side: a power
@@ -324,9 +344,10 @@ __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Sme
   __syncthreads();
 }
 
-// B <- Q B with Q = H_0 ... H_{p-1} from wg_qr (B is m x k, ldb).
+// B <- Q B with Q = H_0 ... H_{p-1} from wg_qr (B is m x k, ldb).  With a
+// column map, reflector j is stored in column pos[j] of A (wg_cpqr).
 __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const double* tau,
-                           double* B, int k, int64_t ldb) {
+                           double* B, int k, int64_t ldb, const int32_t* pos = nullptr) {
   const int tid = threadIdx.x;
   if (k <= 0) return;
   const int g = group_size(k);
@@ -335,7 +356,7 @@ __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const
   for (int j = p - 1; j >= 0; --j) {
     const double t = tau[j];
     if (t != 0.0) {
-      const double* a = A + (int64_t)j * lda;
+      const double* a = A + (int64_t)(pos ? pos[j] : j) * lda;
       for (int c = c0; c < k; c += cstep) {
         double* bc = B + (int64_t)c * ldb;
         const int64_t i0 = j + 1 + gl;
@@ -460,12 +481,277 @@ __device__ void wg_apply_q_staged(const double* A, int64_t m, int p, const doubl
   }
 }
 
+// Householder QR with column pivoting of A (m x n, column-major, lda, n <=
+// CMAX), in place and without moving columns.  Step j takes, among the columns
+// not yet chosen, the one of largest norm below row j (ties: lowest position in
+// the current order) and eliminates it below row j.  The factorisation stops
+// before step j once that norm is at most tolrel ||A||_F (tolrel = 0: only at
+// an exactly zero remainder).  Returns the number of steps r.  On return
+// S.pos[r & 1][q] is the column at position q; reflector j (v_j(j) = 1
+// implicit) lies below row j of column pos[j], with S.tau_p[j]; and
+// R(i, q) = A(i, pos[q]) for i <= q, i < r.  The discarded remainder (rows >= r
+// of the columns at positions >= r) has Frobenius norm at most
+// sqrt(n - r) tolrel ||A||_F.
+//
+// One fused pass and one barrier per step, as in wg_qr: a group of g threads
+// per trailing column forms its dot product with the pivot column, the pivot
+// column's norm (redundantly, same rows and order in every group), applies the
+// reflector and forms the column's new norm below row j.  The pivot order and
+// the norms are double-buffered by step parity, so that a step only reads the
+// copies written before the previous barrier.
+__device__ int wg_cpqr(double* A, int m, int n, int64_t lda, double tolrel, Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int p = m < n ? m : n;
+  for (int c = wv; c < n; c += NW) {
+    const double* ac = A + (int64_t)c * lda;
+    double v = 0.0;
+    for (int i = lane; i < m; i += 64) v += ac[i] * ac[i];
+    v = wave_sum(v);
+    if (lane == 0) S.cn[0][c] = v;
+  }
+  for (int c = tid; c < n; c += NT) S.pos[0][c] = c;
+  __syncthreads();
+  const double f2 = block_sum(tid < n ? S.cn[0][tid] : 0.0, S.red);
+  const double thr = tolrel * tolrel * f2;
+  double prev_scale = 0.0, prev_beta = 0.0;
+  int prev_col = 0;
+  int r = p;
+  double flops = 0.0;
+  for (int j = 0; j < p; ++j) {
+    const int cur = j & 1, nxt = cur ^ 1;
+    const int32_t* pos = S.pos[cur];
+    const double* cn = S.cn[cur];
+    // pivot: each wavefront scans positions j..n-1 and reduces the same way
+    double best = -1.0;
+    int bq = n;
+    for (int q = j + lane; q < n; q += 64) {
+      const double v = cn[pos[q]];
+      if (v > best) { best = v; bq = q; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b2 = __shfl_xor(best, o, 64);
+      const int q2 = __shfl_xor(bq, o, 64);
+      if (b2 > best || (b2 == best && q2 < bq)) { best = b2; bq = q2; }
+    }
+    if (!(best > thr)) { r = j; break; }
+    const int pc = pos[bq], pj = pos[j];
+    if (j > 0) {
+      // deferred: the previous pivot column becomes v_{j-1}, R_{j-1,j-1}
+      double* ap = A + (int64_t)prev_col * lda;
+      if (prev_scale != 0.0)
+        for (int i = j + tid; i < m; i += NT) ap[i] *= prev_scale;
+      if (tid == 0) ap[j - 1] = prev_beta;
+    }
+    for (int q = tid; q < n; q += NT) S.pos[nxt][q] = (q == j) ? pc : (q == bq) ? pj : pos[q];
+    const double* a = A + (int64_t)pc * lda;
+    const double alpha = a[j];
+    const int C = n - j - 1;
+    double sp = 0.0, t = 0.0, beta = alpha, scale = 0.0;
+    flops += 2.0 * (m - j) + 6.0 * (double)(m - j) * C;
+    if (C > 0) {
+      const int g = group_size(C);
+      const int c = tid / g, gl = tid % g;
+      const int q = j + 1 + (c < C ? c : 0);
+      const int col = (q == bq) ? pj : pos[q];
+      double* ac = A + (int64_t)col * lda;
+      const int64_t i0 = j + 1 + gl;
+      const int64_t g4 = 4 * (int64_t)g;
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+      double dot = 0.0, acj = 0.0;
+      if (c < C) {
+        acj = ac[j];
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int64_t i = i0;
+        for (; i + 3 * g < m; i += g4) {
+          const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+          const double y0 = ac[i], y1 = ac[i + g], y2 = ac[i + 2 * g], y3 = ac[i + 3 * g];
+          n0 += x0 * x0; n1 += x1 * x1; n2 += x2 * x2; n3 += x3 * x3;
+          d0 += x0 * y0; d1 += x1 * y1; d2 += x2 * y2; d3 += x3 * y3;
+        }
+        for (; i < m; i += g) {
+          const double x = a[i];
+          n0 += x * x;
+          d0 += x * ac[i];
+        }
+        dot = (d0 + d1) + (d2 + d3);
+      } else {
+        int64_t i = i0;
+        for (; i + 3 * g < m; i += g4) {
+          const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+          n0 += x0 * x0; n1 += x1 * x1; n2 += x2 * x2; n3 += x3 * x3;
+        }
+        for (; i < m; i += g) n0 += a[i] * a[i];
+      }
+      double nrm = (n0 + n1) + (n2 + n3);
+      for (int o = 1; o < g; o <<= 1) {
+        nrm += __shfl_xor(nrm, o, 64);
+        dot += __shfl_xor(dot, o, 64);
+      }
+      sp = nrm;
+      if (sp != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + sp), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      if (c < C) {
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        int64_t i = i0;
+        if (sp != 0.0) {
+          const double f = t * (acj + scale * dot);
+          const double fs = f * scale;
+          if (gl == 0) ac[j] = acj - f;
+          for (; i + 3 * g < m; i += g4) {
+            const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
+            const double y0 = ac[i] - fs * x0, y1 = ac[i + g] - fs * x1;
+            const double y2 = ac[i + 2 * g] - fs * x2, y3 = ac[i + 3 * g] - fs * x3;
+            ac[i] = y0; ac[i + g] = y1; ac[i + 2 * g] = y2; ac[i + 3 * g] = y3;
+            p0 += y0 * y0; p1 += y1 * y1; p2 += y2 * y2; p3 += y3 * y3;
+          }
+          for (; i < m; i += g) {
+            const double y = ac[i] - fs * a[i];
+            ac[i] = y;
+            p0 += y * y;
+          }
+        } else {
+          for (; i < m; i += g) p0 += ac[i] * ac[i];
+        }
+        double pn = (p0 + p1) + (p2 + p3);
+        for (int o = 1; o < g; o <<= 1) pn += __shfl_xor(pn, o, 64);
+        if (gl == 0) S.cn[nxt][col] = pn;
+      }
+    } else {
+      double part = 0.0;
+      for (int64_t i = j + 1 + tid; i < m; i += NT) part += a[i] * a[i];
+      sp = block_sum(part, S.red);
+      if (sp != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + sp), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+    }
+    if (tid == 0) S.tau_p[j] = t;
+    prev_scale = (sp != 0.0) ? scale : 0.0;
+    prev_beta = beta;
+    prev_col = pc;
+    __syncthreads();
+  }
+  if (r > 0) {
+    double* ap = A + (int64_t)prev_col * lda;
+    if (prev_scale != 0.0)
+      for (int i = r + tid; i < m; i += NT) ap[i] *= prev_scale;
+    if (tid == 0) ap[r - 1] = prev_beta;
+  }
+  if (tid == 0) S.flops += flops;
+  __syncthreads();
+  return r;
+}
+
+// Best approximation of an explicit m x n matrix A (lda; destroyed; n <= CMAX)
+// at the accuracy of D (relative eps, or the fixed rank), capped at D.kmax.
+// Pivoted QR A P = Q R (wg_cpqr; in the accuracy mode stopped at a remainder
+// below min(2 max(m,n) u, eps / 1000) ||A||_F, far under what any truncation
+// keeps), then one-sided Jacobi on the columns of R^T (n x r): R^T J = W Sigma
+// with W orthonormal, so that A = Q [J Sigma; 0] (P W)^T up to the discarded
+// remainder.  The Jacobi iteration on the transposed triangular factor of a
+// pivoted QR needs a few sweeps where it needs many on A itself.  Writes
+//   U (mU x k, ldu):  Q [R W ; 0]            (the singular values ride on U)
+//   V (nV x k, ldv):  P W Sigma^{-1}         (orthonormal columns)
+// with rows m..mU-1 of U and n..nV-1 of V set to zero; returns k.
+// gws: global workspace of at least odd_ld(n) * min(m, n) doubles, used for
+// R^T when it does not fit in lds (lds_cap doubles).
+__device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_t lda, double* U, int64_t mU,
+                               int64_t ldu, double* V, int64_t nV, int64_t ldv, double* gws, double* lds,
+                               int lds_cap, Smem& S, bool timed = false) {
+  const int tid = threadIdx.x;
+  int64_t c0 = (timed && tid == 0) ? clk() : 0;
+  const double u = 2.220446049250313e-16;
+  double tolrel = 0.0;
+  if (D.kfix <= 0) {
+    tolrel = 2.0 * (double)(m > n ? m : n) * u;
+    if (1e-3 * D.eps < tolrel) tolrel = 1e-3 * D.eps;
+  }
+  const int r = wg_cpqr(A, m, n, lda, tolrel, S);
+  if (timed && tid == 0) { const int64_t c1 = clk(); S.ph[0] += c1 - c0; c0 = c1; }
+  if (r == 0) return 0;
+  const int32_t* pos = S.pos[r & 1];
+  const int ldg = (int)odd_ld(n);
+  double* G = ((int64_t)ldg * r <= lds_cap) ? lds : gws;
+  for (int e = tid; e < n * r; e += NT) {
+    const int q = e % n, i = e / n;
+    G[q + i * ldg] = (i <= q) ? A[i + (int64_t)pos[q] * lda] : 0.0;
+  }
+  __syncthreads();
+  wg_jacobi(G, n, r, ldg, S);
+  for (int l = tid; l < r; l += NT) {
+    double sq = 0.0;
+    for (int q = 0; q < n; ++q) sq += G[q + l * ldg] * G[q + l * ldg];
+    S.sig[l] = sqrt(sq);
+  }
+  __syncthreads();
+  for (int l = tid; l < r; l += NT) {
+    int rk = 0;
+    const double sl = S.sig[l];
+    for (int i = 0; i < r; ++i) {
+      const double si = S.sig[i];
+      if (si > sl || (si == sl && i < l)) ++rk;
+    }
+    S.ord[rk] = l;
+  }
+  __syncthreads();
+  if (timed && tid == 0) { const int64_t c1 = clk(); S.ph[1] += c1 - c0; c0 = c1; }
+  const double s1 = S.sig[S.ord[0]];
+  int k = 0;
+  if (s1 > 0.0) {
+    if (D.kfix > 0) {
+      for (int l = 0; l < r; ++l) if (S.sig[S.ord[l]] > 0.0) ++k;
+      if (k > D.kfix) k = D.kfix;
+    } else {
+      for (int l = 0; l < r; ++l) if (S.sig[S.ord[l]] > D.eps * s1) ++k;
+    }
+    if (k > D.kmax) k = D.kmax;
+  }
+  // V(pos[q], l) = G(q, o_l) / sigma_l
+  for (int64_t e = tid; e < nV * k; e += NT) {
+    const int64_t c = e % nV;
+    const int l = (int)(e / nV);
+    V[c + l * ldv] = 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * k; e += NT) {
+    const int q = e % n, l = e / n;
+    const int o = S.ord[l];
+    V[pos[q] + l * ldv] = G[q + o * ldg] / S.sig[o];
+  }
+  // U(i, l) = (R G(:, o_l))_i / sigma_l for i < r, zero below
+  for (int64_t e = tid; e < mU * k; e += NT) {
+    const int64_t i = e % mU;
+    const int l = (int)(e / mU);
+    double acc = 0.0;
+    if (i < r) {
+      const int o = S.ord[l];
+      for (int q = (int)i; q < n; ++q) acc += A[i + (int64_t)pos[q] * lda] * G[q + o * ldg];
+      acc /= S.sig[o];
+    }
+    U[i + l * ldu] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double f = 2.0 * (double)r * n * k;
+    for (int j = 0; j < r; ++j) f += 4.0 * (double)(m - j) * k;
+    S.flops += f;
+  }
+  wg_apply_q(A, m, r, lda, S.tau_p, U, k, ldu, pos);
+  if (timed && tid == 0) S.ph[2] += clk() - c0;
+  return k;
+}
+
 // Best approximation of X Y^T (X: m x r, Y: n x r, in workspace, destroyed) at
 // relative accuracy eps (kfix == 0) or rank kfix, capped at kmax: Householder
-// QR of both factors, one-sided Jacobi SVD of the small core Rx Ry^T, then the
-// kept singular vectors mapped back through the reflectors.  Writes
-// U (m x k, ldu = m) and V (n x k, ldv = n); returns k.
-// scratch: at least 2 r^2 doubles of global workspace.
+// QR of both factors, the small core Rx Ry^T truncated by wg_svd_explicit, and
+// its factors mapped back through the reflectors.  Writes U (m x k, ldu = m)
+// and V (n x k, ldv = n); returns k.
+// scratch: at least 2 (r + 1) r doubles of global workspace.
 __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, int64_t n, int r,
                            double* U, double* V, double* scratch, double* lds_g, int lds_cap, Smem& S) {
   const int tid = threadIdx.x;
@@ -488,71 +774,33 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
     }
   }
   const int px = (int)(m < r ? m : r), py = (int)(n < r ? n : r);
-  // M = Rx Ry^T  (px x py), keep a copy for the right singular vectors
-  double* M = scratch;
-  const int gld = (int)odd_ld(px);
-  double* G = ((int64_t)gld * py <= lds_cap) ? lds_g : scratch + (int64_t)px * py;
+  // M = Rx Ry^T (px x py), in LDS when it fits
+  const int ldm = (int)odd_ld(px);
+  const bool m_lds = (int64_t)ldm * py <= lds_cap;
+  double* M = m_lds ? lds_g : scratch;
   for (int e = tid; e < px * py; e += NT) {
     const int i = e % px, j = e / px;
     const int l0 = i > j ? i : j;
     double acc = 0.0;
     for (int l = l0; l < r; ++l) acc += X[i + (int64_t)l * m] * Y[j + (int64_t)l * n];
-    M[e] = acc;
-    G[i + j * gld] = acc;
-  }
-  __syncthreads();
-  if (tid == 0) { const int64_t c1 = clk(); S.ph[0] += c1 - c0; c0 = c1; }
-  wg_jacobi(G, px, py, gld, S);
-  if (tid == 0) { const int64_t c1 = clk(); S.ph[1] += c1 - c0; c0 = c1; }
-  // singular values, ordering (descending, ties by index)
-  for (int j = tid; j < py; j += NT) {
-    double s = 0.0;
-    for (int i = 0; i < px; ++i) s += G[i + j * gld] * G[i + j * gld];
-    S.sig[j] = sqrt(s);
-  }
-  __syncthreads();
-  for (int j = tid; j < py; j += NT) {
-    int rk = 0;
-    const double sj = S.sig[j];
-    for (int i = 0; i < py; ++i) {
-      const double si = S.sig[i];
-      if (si > sj || (si == sj && i < j)) ++rk;
-    }
-    S.ord[rk] = j;
-  }
-  __syncthreads();
-  const double s1 = S.sig[S.ord[0]];
-  int k = 0;
-  if (s1 > 0.0) {
-    if (D.kfix > 0) {
-      for (int l = 0; l < py; ++l) if (S.sig[S.ord[l]] > 0.0) ++k;
-      if (k > D.kfix) k = D.kfix;
-    } else {
-      for (int l = 0; l < py; ++l) if (S.sig[S.ord[l]] > D.eps * s1) ++k;
-    }
-    if (k > D.kmax) k = D.kmax;
-  }
-  // U = Qx [G(:, ord) ; 0],  V = Qy [M^T G(:, ord) / sigma^2 ; 0]
-  for (int64_t e = tid; e < m * (int64_t)k; e += NT) {
-    const int64_t i = e % m;
-    const int l = (int)(e / m);
-    U[e] = (i < px) ? G[i + (int64_t)S.ord[l] * gld] : 0.0;
-  }
-  for (int64_t e = tid; e < n * (int64_t)k; e += NT) {
-    const int64_t j = e % n;
-    const int l = (int)(e / n);
-    double v = 0.0;
-    if (j < py) {
-      const int o = S.ord[l];
-      const double sg = S.sig[o];
-      for (int i = 0; i < px; ++i) v += M[i + (int64_t)j * px] * G[i + (int64_t)o * gld];
-      v = v / (sg * sg);
-    }
-    V[e] = v;
+    M[i + j * ldm] = acc;
   }
   __syncthreads();
   if (tid == 0) {
-    double f = 2.0 * px * py * r + 2.0 * (double)n * k * px;   // core product, right vectors
+    S.flops += 2.0 * px * py * r;
+    const int64_t c1 = clk();
+    S.ph[0] += c1 - c0;
+    c0 = c1;
+  }
+  // core: U = [Uc ; 0], V = [Vc ; 0] with Uc Vc^T the best approximation of M
+  double* gl_lds = m_lds ? lds_g + (int64_t)ldm * py : lds_g;
+  const int gl_cap = m_lds ? lds_cap - ldm * py : lds_cap;
+  double* gws = m_lds ? scratch : scratch + (int64_t)ldm * py;
+  const int k = wg_svd_explicit(D, M, px, py, ldm, U, m, m, V, n, n, gws, gl_lds, gl_cap, S);
+  if (tid == 0) { const int64_t c1 = clk(); S.ph[1] += c1 - c0; c0 = c1; }
+  __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
     for (int j = 0; j < px; ++j) f += 4.0 * (double)(m - j) * k;
     for (int j = 0; j < py; ++j) f += 4.0 * (double)(n - j) * k;
     S.flops += f;
@@ -787,41 +1035,50 @@ __device__ void task_term(const DevData& D, int32_t tid_term, double* tmp, Smem&
   }
 }
 
-// Subtracts a leaf's restricted update terms, in order, from an m x n tile
-// held in registers (entry e = tid + q NT of the column-major tile in
-// dreg[q]).  Term factors are staged through LDS 32 columns at a time.
-__device__ void apply_terms(const DevData& D, const Task& tk, int m, int n, double (&dreg)[16], double* lds,
-                            Smem& S) {
+// Subtracts a leaf's restricted update terms, in order, from the tm x tn tile
+// at (ti0, tj0) of the block, held in registers (entry e = tid + q NT of the
+// column-major tile in dreg[q]).  Term factors are staged through LDS 32
+// columns at a time.
+__device__ void apply_terms(const DevData& D, const Task& tk, int ti0, int tj0, int tm, int tn, double (&dreg)[NQ],
+                            double* lds, Smem& S) {
   const int tid = threadIdx.x;
-  const int cnt = m * n;
+  const int cnt = tm * tn;
   double* Xs = lds;                 // 64 x 32 chunk, row stride 33
   double* Ys = lds + 64 * 33;       // 64 x 32 chunk, row stride 33
   for (int32_t ii = 0; ii < tk.ninst; ++ii) {
     const TermInst in = D.insts[tk.inst_begin + ii];
+    // the term's rectangle, clipped to the tile (block coordinates)
+    const int r0 = in.lr0 > ti0 ? in.lr0 : ti0;
+    const int r1 = (in.lr0 + in.mx < ti0 + tm) ? in.lr0 + in.mx : ti0 + tm;
+    const int c0 = in.lc0 > tj0 ? in.lc0 : tj0;
+    const int c1 = (in.lc0 + in.ny < tj0 + tn) ? in.lc0 + in.ny : tj0 + tn;
+    if (r0 >= r1 || c0 >= c1) continue;
+    const int mx = r1 - r0, ny = c1 - c0;
     const TermDef t = D.terms[in.term];
     const int r = term_rank(D, t);
     const double *X, *Y;
     int64_t ldx, ldy;
     term_factors(D, t, X, ldx, Y, ldy);
-    if (tid == 0) S.flops += 2.0 * in.mx * in.ny * r;
+    const int64_t xr = in.xr0 + (r0 - in.lr0), yr = in.yr0 + (c0 - in.lc0);
+    if (tid == 0) S.flops += 2.0 * mx * ny * r;
     for (int l0 = 0; l0 < r; l0 += 32) {
       const int lc = (r - l0 < 32) ? (r - l0) : 32;
       __syncthreads();
-      for (int e = tid; e < in.mx * lc; e += NT) {
-        const int i = e % in.mx, l = e / in.mx;
-        Xs[i * 33 + l] = X[in.xr0 + i + (int64_t)(l0 + l) * ldx];
+      for (int e = tid; e < mx * lc; e += NT) {
+        const int i = e % mx, l = e / mx;
+        Xs[i * 33 + l] = X[xr + i + (int64_t)(l0 + l) * ldx];
       }
-      for (int e = tid; e < in.ny * lc; e += NT) {
-        const int j = e % in.ny, l = e / in.ny;
-        Ys[j * 33 + l] = Y[in.yr0 + j + (int64_t)(l0 + l) * ldy];
+      for (int e = tid; e < ny * lc; e += NT) {
+        const int j = e % ny, l = e / ny;
+        Ys[j * 33 + l] = Y[yr + j + (int64_t)(l0 + l) * ldy];
       }
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         const int e = tid + q * NT;
         if (e < cnt) {
-          const int i = e % m - in.lr0, j = e / m - in.lc0;
-          if (i >= 0 && i < in.mx && j >= 0 && j < in.ny) {
+          const int i = ti0 + e % tm - r0, j = tj0 + e / tm - c0;
+          if (i >= 0 && i < mx && j >= 0 && j < ny) {
             double acc = 0.0;
             for (int l = 0; l < lc; ++l) acc += Xs[i * 33 + l] * Ys[j * 33 + l];
             dreg[q] -= acc;
@@ -839,18 +1096,18 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
   const Block bk = D.bk[b];
   const int m = (int)bk.m, n = (int)bk.n;
   double* Dg = D.dense + D.dense_off[b];
-  double dreg[16];
+  double dreg[NQ];
   const int cnt = m * n;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int e = tid + q * NT;
     dreg[q] = (e < cnt) ? Dg[e] : 0.0;
   }
-  apply_terms(D, tk, m, n, dreg, lds, S);
+  apply_terms(D, tk, 0, 0, m, n, dreg, lds, S);
   __syncthreads();
   double* A = lds;                  // m x n tile, column-major
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int e = tid + q * NT;
     if (e < cnt) A[e] = dreg[q];
   }
@@ -903,11 +1160,13 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
   __syncthreads();
 }
 
-// Low-rank leaf whose row and column clusters are both leaves (at most
-// n_min x n_min): the updated block U V^T - sum X Y^T is formed exactly in
-// registers and replaced by its truncated SVD (one-sided Jacobi on the tile).
-// Returns the new rank (also written to D.rank).
-__device__ int lr_dense_flush(const DevData& D, const Task& tk, double* lds, Smem& S) {
+// Low-rank leaf whose row and column clusters both hold at most D.dflush
+// points (<= CMAX): the updated block U V^T - sum X Y^T is formed exactly, one
+// LEAF_MAX x LEAF_MAX tile at a time in registers, and replaced by its best
+// approximation (wg_svd_explicit).  The explicit block lives in LDS when it is
+// a single tile, else in the work-group's global workspace slot.  Returns the
+// new rank (also written to D.rank).
+__device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
   const int tid = threadIdx.x;
   const int32_t b = tk.obj;
   const Block bk = D.bk[b];
@@ -915,84 +1174,53 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* lds, Sme
   double* U = D.lr + D.lr_off[b];
   double* V = U + (int64_t)m * K_MAX;
   const int k0 = D.rank[b];
-  const int cnt = m * n;
-  double dreg[16];
+  const int64_t c0 = (tid == 0) ? clk() : 0;
+  const bool small = m <= LEAF_MAX && n <= LEAF_MAX;
+  const int stage = 2 * 64 * 33;                 // apply_terms staging
+  const int lda = small ? (m | 1) : m;
+  double* A = small ? lds + stage : slot;
+  for (int tj0 = 0; tj0 < n; tj0 += LEAF_MAX) {
+    for (int ti0 = 0; ti0 < m; ti0 += LEAF_MAX) {
+      const int tm = (m - ti0 < LEAF_MAX) ? m - ti0 : LEAF_MAX;
+      const int tn = (n - tj0 < LEAF_MAX) ? n - tj0 : LEAF_MAX;
+      const int cnt = tm * tn;
+      double dreg[NQ];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + q * NT;
-    double acc = 0.0;
-    if (e < cnt) {
-      const int i = e % m, j = e / m;
-      for (int l = 0; l < k0; ++l) acc += U[i + l * m] * V[j + l * n];
-    }
-    dreg[q] = acc;
-  }
-  if (tid == 0) S.flops += 2.0 * m * n * k0;
-  apply_terms(D, tk, m, n, dreg, lds, S);
-  __syncthreads();
-  const int ld = m | 1;
-  double* A0 = lds;                 // the updated block, kept for the right vectors
-  double* G = lds + ld * n;         // Jacobi working copy
+      for (int q = 0; q < NQ; ++q) {
+        const int e = tid + q * NT;
+        double acc = 0.0;
+        if (e < cnt) {
+          const int i = ti0 + e % tm, j = tj0 + e / tm;
+          for (int l = 0; l < k0; ++l) acc += U[i + (int64_t)l * m] * V[j + (int64_t)l * n];
+        }
+        dreg[q] = acc;
+      }
+      apply_terms(D, tk, ti0, tj0, tm, tn, dreg, lds, S);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + q * NT;
-    if (e < cnt) {
-      const int i = e % m, j = e / m;
-      A0[i + j * ld] = dreg[q];
-      G[i + j * ld] = dreg[q];
+      for (int q = 0; q < NQ; ++q) {
+        const int e = tid + q * NT;
+        if (e < cnt) A[(ti0 + e % tm) + (int64_t)(tj0 + e / tm) * lda] = dreg[q];
+      }
     }
-  }
-  __syncthreads();
-  wg_jacobi(G, m, n, ld, S);
-  for (int j = tid; j < n; j += NT) {
-    double sq = 0.0;
-    for (int i = 0; i < m; ++i) sq += G[i + j * ld] * G[i + j * ld];
-    S.sig[j] = sqrt(sq);
-  }
-  __syncthreads();
-  for (int j = tid; j < n; j += NT) {
-    int rk = 0;
-    const double sj = S.sig[j];
-    for (int i = 0; i < n; ++i) {
-      const double si = S.sig[i];
-      if (si > sj || (si == sj && i < j)) ++rk;
-    }
-    S.ord[rk] = j;
-  }
-  __syncthreads();
-  const double s1 = S.sig[S.ord[0]];
-  int k = 0;
-  if (s1 > 0.0) {
-    if (D.kfix > 0) {
-      for (int l = 0; l < n; ++l) if (S.sig[S.ord[l]] > 0.0) ++k;
-      if (k > D.kfix) k = D.kfix;
-    } else {
-      for (int l = 0; l < n; ++l) if (S.sig[S.ord[l]] > D.eps * s1) ++k;
-    }
-    if (k > D.kmax) k = D.kmax;
-  }
-  for (int e = tid; e < m * k; e += NT) {
-    const int i = e % m, l = e / m;
-    U[i + l * m] = G[i + S.ord[l] * ld];
-  }
-  for (int e = tid; e < n * k; e += NT) {
-    const int j = e % n, l = e / n;
-    const int o = S.ord[l];
-    const double sg = S.sig[o];
-    double v = 0.0;
-    for (int i = 0; i < m; ++i) v += A0[i + j * ld] * G[i + o * ld];
-    V[j + l * n] = v / (sg * sg);
   }
   if (tid == 0) {
-    S.flops += 2.0 * (double)n * m * k;
-    D.rank[b] = k;
+    S.flops += 2.0 * m * n * k0;
+    S.ph[4] += clk() - c0;     // explicit formation
   }
+  __syncthreads();
+  // R^T of the pivoted QR: after the block in LDS, else from the start of LDS
+  double* glds = small ? lds + stage + lda * n : lds;
+  const int gcap = small ? LDS_FACTOR - stage - lda * n : LDS_FACTOR;
+  double* gws = slot + (small ? 0 : (int64_t)m * n);
+  const int k = wg_svd_explicit(D, A, m, n, lda, U, m, m, V, n, n, gws, glds, gcap, S, true);
+  if (tid == 0) D.rank[b] = k;
   __syncthreads();
   return k;
 }
 
-// Low-rank leaf: truncate U V^T minus its terms (in order, R_ACC at a time),
-// then V <- L_{sigma sigma}^{-1} V.
+// Low-rank leaf: flush its terms (explicitly for blocks of at most D.dflush x
+// D.dflush, else in factored form, truncating whenever the accumulated rank
+// would exceed R_ACC), then V <- L_{sigma sigma}^{-1} V.
 __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
   const int tid = threadIdx.x;
   const int32_t b = tk.obj;
@@ -1001,9 +1229,9 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   const int RW = 2 * K_MAX;
   double* U = D.lr + D.lr_off[b];
   double* V = U + m * K_MAX;
-  const bool leafpair = D.cl[bk.row].son[0] < 0 && D.cl[bk.col].son[0] < 0;
-  if (tk.ninst > 0 && leafpair) {
-    const int kk = lr_dense_flush(D, tk, lds, S);
+  const bool explicit_sum = m <= D.dflush && n <= D.dflush;
+  if (tk.ninst > 0 && explicit_sum) {
+    const int kk = lr_dense_flush(D, tk, slot, lds, S);
     if (tid == 0) S.ival[0] = kk;
     __syncthreads();
   } else if (tk.ninst > 0) {
@@ -1137,16 +1365,16 @@ __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1)
     const Task tk = D.tasks[t];
     const int32_t prog = D.task_prog[t];
     int64_t ts = 0;
-    if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = 0; }
+    if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0; }
     if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
     if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
     else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
     else task_dense(D, tk, prog, dyn, S);
     __syncthreads();
     if (D.task_times && threadIdx.x == 0) {
-      D.task_times[6 * t] = ts;
-      D.task_times[6 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
-      for (int q = 0; q < 4; ++q) D.task_times[6 * t + 2 + q] = S.ph[q];
+      D.task_times[7 * t] = ts;
+      D.task_times[7 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
+      for (int q = 0; q < 5; ++q) D.task_times[7 * t + 2 + q] = S.ph[q];
     }
     if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
   }
@@ -1185,7 +1413,7 @@ __global__ void k_permute(const double* Z, const int64_t* perm, int64_t n, int r
 // out[0] = log|C| (2 sum over diagonal leaves in order), out[1 + c] = v_c^T v_c.
 __global__ void __launch_bounds__(NT) k_reduce(DevData D, const int32_t* diag_ids, int32_t ndiag,
                                                const double* W, int r, double* out) {
-  __shared__ double red[8];
+  __shared__ double red[NW];
   const int tid = threadIdx.x;
   // log-determinant: per-thread contiguous chunks of leaves, fixed order
   double s = 0.0;
@@ -1217,7 +1445,7 @@ __global__ void __launch_bounds__(NT) k_truncate_test(DevData D, const double* X
   double* scratch = Ya + n * r;
   for (int64_t e = threadIdx.x; e < m * r; e += NT) Xa[e] = X[e];
   for (int64_t e = threadIdx.x; e < n * r; e += NT) Ya[e] = Y[e];
-  if (threadIdx.x == 0) S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = 0;
+  if (threadIdx.x == 0) S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0;
   __syncthreads();
   const int k = wg_truncate(D, Xa, m, Ya, n, r, U, V, scratch, dyn, LDS_FACTOR, S);
   if (threadIdx.x == 0) {
@@ -1269,9 +1497,9 @@ hipError_t launch_factor(const DevData& D, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t nlevels, int max_grid,
-                                hipStream_t st) {
-  hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
+hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, bool init,
+                                int max_grid, hipStream_t st) {
+  if (init) hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_level, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1279,7 +1507,7 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  for (int32_t l = 0; l < nlevels; ++l) {
+  for (int32_t l = l0; l < l1; ++l) {
     const int32_t t0 = level_begin[l], t1 = level_begin[l + 1];
     const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
     if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);

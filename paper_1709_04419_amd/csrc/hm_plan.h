@@ -15,6 +15,9 @@ namespace hm {
 // it is truncated.  Both are named constants of the method.
 constexpr int K_MAX = 64;
 constexpr int R_ACC = 64;
+// Low-rank blocks whose clusters both hold at most DENSE_FLUSH * n_min points
+// take their pending updates on the explicit matrix and are truncated once.
+constexpr int DENSE_FLUSH = 4;
 // Largest leaf size n_min the device kernels accept (dense tiles <= 64 x 64).
 constexpr int LEAF_MAX = 64;
 
