@@ -230,6 +230,105 @@ __device__ __forceinline__ int group_size(int cols) {
   return g;
 }
 
+// Panels with more rows than this are processed one wavefront per column.
+#define TALL_ROWS 512
+
+// Lane-strided partial dot product sum_{i = i0, i0 + 64, ... < m} x[i] y[i],
+// eight rows in flight (combine across the wave with wave_sum).
+__device__ __forceinline__ double wave_rows_dot(const double* x, const double* y, int64_t i0, int64_t m) {
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  int64_t i = i0;
+  for (; i + 7 * 64 < m; i += 8 * 64) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { xv[u] = x[i + u * 64]; yv[u] = y[i + u * 64]; }
+    d0 += xv[0] * yv[0]; d1 += xv[1] * yv[1]; d2 += xv[2] * yv[2]; d3 += xv[3] * yv[3];
+    d0 += xv[4] * yv[4]; d1 += xv[5] * yv[5]; d2 += xv[6] * yv[6]; d3 += xv[7] * yv[7];
+  }
+  for (; i < m; i += 64) d0 += x[i] * y[i];
+  return (d0 + d1) + (d2 + d3);
+}
+
+// y[i] += alpha x[i] for the lane's rows i = i0, i0 + 64, ... < m.
+__device__ __forceinline__ void wave_rows_axpy(double alpha, const double* x, double* y, int64_t i0, int64_t m) {
+  int64_t i = i0;
+  for (; i + 7 * 64 < m; i += 8 * 64) {
+    double xv[8], yv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { xv[u] = x[i + u * 64]; yv[u] = y[i + u * 64]; }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[i + u * 64] = yv[u] + alpha * xv[u];
+  }
+  for (; i < m; i += 64) y[i] += alpha * x[i];
+}
+
+// Up to four columns at once (nc <= 4; unused slots alias x and are ignored):
+// d[q] = sum over the lane's rows of x[i] y_q[i] and, if want_xx, xx = sum
+// x[i]^2; eight rows in flight per column.
+__device__ __forceinline__ void wave_rows_dot4(const double* x, const double* const (&y)[4], int nc, int64_t i0,
+                                               int64_t m, bool want_xx, double (&d)[4], double& xx) {
+  double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  double n0 = 0.0, n1 = 0.0;
+  int64_t i = i0;
+  for (; i + 7 * 64 < m; i += 8 * 64) {
+    double xv[8], yv[4][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[i + u * 64];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nc) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) yv[q][u] = y[q][i + u * 64];
+      }
+    if (want_xx) {
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) { n0 += xv[u] * xv[u]; n1 += xv[u + 1] * xv[u + 1]; }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nc) {
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) { acc[q][0] += xv[u] * yv[q][u]; acc[q][1] += xv[u + 1] * yv[q][u + 1]; }
+      }
+  }
+  for (; i < m; i += 64) {
+    const double xv = x[i];
+    if (want_xx) n0 += xv * xv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nc) acc[q][0] += xv * y[q][i];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) d[q] = acc[q][0] + acc[q][1];
+  xx = n0 + n1;
+}
+
+// y_q[i] += alpha_q x[i] over the lane's rows, for q < nc (<= 4).
+__device__ __forceinline__ void wave_rows_axpy4(const double (&alpha)[4], const double* x, double* const (&y)[4],
+                                                int nc, int64_t i0, int64_t m) {
+  int64_t i = i0;
+  for (; i + 7 * 64 < m; i += 8 * 64) {
+    double xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[i + u * 64];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nc) {
+        double yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) yv[u] = y[q][i + u * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y[q][i + u * 64] = yv[u] + alpha[q] * xv[u];
+      }
+  }
+  for (; i < m; i += 64) {
+    const double xv = x[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < nc) y[q][i] += alpha[q] * xv;
+  }
+}
+
 // In-place Householder QR of A (m x r, column-major, lda); p = min(m, r)
 // reflectors H_j = I - tau_j v_j v_j^T, v_j(j) = 1 implicit, stored below the
 // diagonal; R on and above it.
@@ -258,22 +357,69 @@ __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Sme
     const double alpha = a[j];
     const int C = r - j - 1;
     double s = 0.0, t = 0.0, beta = alpha, scale = 0.0;
-    if (C > 0) {
+    if (C > 0 && m - j > TALL_ROWS) {
+      // tall panel: one wavefront per trailing column (each load instruction
+      // reads 64 consecutive rows), columns dealt round-robin to the waves;
+      // every wave forms the pivot norm itself, over the same rows and order
+      // (four columns of a wave at a time; the pivot norm rides on the first
+      // batch of every wave)
+      const int lane = tid & 63, wv = tid >> 6;
+      bool first = true;
+      for (int c0 = 4 * wv; first || c0 < C; c0 += 4 * NW) {
+        const int nc = (c0 < C) ? ((C - c0 < 4) ? C - c0 : 4) : 0;
+        double* cols[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cols[q] = (q < nc) ? A + (int64_t)(j + 1 + c0 + q) * lda : (double*)a;
+        double acj[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acj[q] = (q < nc) ? cols[q][j] : 0.0;
+        double dots[4], xx;
+        wave_rows_dot4(a, cols, nc, j + 1 + lane, m, first, dots, xx);
+        if (first) {
+          s = wave_sum(xx);
+          if (s != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + s), alpha);
+            t = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+          }
+          first = false;
+        }
+        if (nc == 0 || s == 0.0) continue;
+        double fs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double dq = wave_sum(dots[q]);
+          const double f = t * (acj[q] + scale * dq);
+          if (q < nc && lane == 0) cols[q][j] = acj[q] - f;
+          fs[q] = -f * scale;
+        }
+        wave_rows_axpy4(fs, a, cols, nc, j + 1 + lane, m);
+      }
+    } else if (C > 0) {
       const int g = group_size(C);
       const int c = tid / g, gl = tid % g;
       // the first C groups own a trailing column each; the remaining (idle)
       // groups only form the pivot norm, over the same row partition
       double* ac = A + (int64_t)(j + 1 + (c < C ? c : 0)) * lda;
       double dot = 0.0, nrm = 0.0, acj = 0.0;
-      // four rows in flight per iteration; the partial sums are combined in
-      // a fixed order, identical in every group
+      // eight (then four) rows in flight per iteration; the partial sums are
+      // combined in a fixed order, identical in every group
       const int64_t i0 = j + 1 + gl;
-      const int64_t g4 = 4 * (int64_t)g;
+      const int64_t g4 = 4 * (int64_t)g, g8 = 8 * (int64_t)g;
       double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
       if (c < C) {
         acj = ac[j];
         double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
         int64_t i = i0;
+        for (; i + 7 * g < m; i += g8) {
+          double x[8], y[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) { x[u] = a[i + u * g]; y[u] = ac[i + u * g]; }
+          n0 += x[0] * x[0]; n1 += x[1] * x[1]; n2 += x[2] * x[2]; n3 += x[3] * x[3];
+          d0 += x[0] * y[0]; d1 += x[1] * y[1]; d2 += x[2] * y[2]; d3 += x[3] * y[3];
+          n0 += x[4] * x[4]; n1 += x[5] * x[5]; n2 += x[6] * x[6]; n3 += x[7] * x[7];
+          d0 += x[4] * y[4]; d1 += x[5] * y[5]; d2 += x[6] * y[6]; d3 += x[7] * y[7];
+        }
         for (; i + 3 * g < m; i += g4) {
           const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
           const double y0 = ac[i], y1 = ac[i + g], y2 = ac[i + 2 * g], y3 = ac[i + 3 * g];
@@ -288,6 +434,13 @@ __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Sme
         dot = (d0 + d1) + (d2 + d3);
       } else {
         int64_t i = i0;
+        for (; i + 7 * g < m; i += g8) {
+          double x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = a[i + u * g];
+          n0 += x[0] * x[0]; n1 += x[1] * x[1]; n2 += x[2] * x[2]; n3 += x[3] * x[3];
+          n0 += x[4] * x[4]; n1 += x[5] * x[5]; n2 += x[6] * x[6]; n3 += x[7] * x[7];
+        }
         for (; i + 3 * g < m; i += g4) {
           const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
           n0 += x0 * x0; n1 += x1 * x1; n2 += x2 * x2; n3 += x3 * x3;
@@ -309,6 +462,13 @@ __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Sme
           const double fs = f * scale;
           if (gl == 0) ac[j] -= f;
           int64_t i = i0;
+          for (; i + 7 * g < m; i += g8) {
+            double x[8], y[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) { x[u] = a[i + u * g]; y[u] = ac[i + u * g]; }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ac[i + u * g] = y[u] - fs * x[u];
+          }
           for (; i + 3 * g < m; i += g4) {
             const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
             const double y0 = ac[i], y1 = ac[i + g], y2 = ac[i + 2 * g], y3 = ac[i + 3 * g];
@@ -350,6 +510,41 @@ __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const
                            double* B, int k, int64_t ldb, const int32_t* pos = nullptr) {
   const int tid = threadIdx.x;
   if (k <= 0) return;
+  if (m > TALL_ROWS) {
+    // tall: one wavefront per column of B, which it carries through all the
+    // reflectors with no work-group barrier in between.  Row i of the column
+    // belongs to lane i mod 64 throughout, so every value a lane reads was
+    // last written by that same lane (row j, read by all lanes for reflector
+    // j, is not modified by the reflectors applied before it).
+    // Four columns of a wave at a time.
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int c0 = 4 * wv; c0 < k; c0 += 4 * NW) {
+      const int nc = (k - c0 < 4) ? k - c0 : 4;
+      double* cols[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cols[q] = B + (int64_t)(c0 + (q < nc ? q : 0)) * ldb;
+      for (int j = p - 1; j >= 0; --j) {
+        const double t = tau[j];
+        if (t == 0.0) continue;
+        const double* a = A + (int64_t)(pos ? pos[j] : j) * lda;
+        const int64_t i0 = j + 1 + ((lane - (j + 1)) & 63);
+        double bj[4], dots[4], xx;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bj[q] = (q < nc) ? cols[q][j] : 0.0;
+        wave_rows_dot4(a, cols, nc, i0, m, false, dots, xx);
+        double fneg[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double f = t * (bj[q] + wave_sum(dots[q]));
+          if (q < nc && lane == (j & 63)) cols[q][j] = bj[q] - f;
+          fneg[q] = -f;
+        }
+        wave_rows_axpy4(fneg, a, cols, nc, i0, m);
+      }
+    }
+    __syncthreads();
+    return;
+  }
   const int g = group_size(k);
   const int c0 = tid / g, gl = tid % g;
   const int cstep = NT / g;
@@ -360,9 +555,16 @@ __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const
       for (int c = c0; c < k; c += cstep) {
         double* bc = B + (int64_t)c * ldb;
         const int64_t i0 = j + 1 + gl;
-        const int64_t g4 = 4 * (int64_t)g;
+        const int64_t g4 = 4 * (int64_t)g, g8 = 8 * (int64_t)g;
         double d0 = (gl == 0) ? bc[j] : 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
         int64_t i = i0;
+        for (; i + 7 * g < m; i += g8) {
+          double x[8], y[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) { x[u] = a[i + u * g]; y[u] = bc[i + u * g]; }
+          d0 += x[0] * y[0]; d1 += x[1] * y[1]; d2 += x[2] * y[2]; d3 += x[3] * y[3];
+          d0 += x[4] * y[4]; d1 += x[5] * y[5]; d2 += x[6] * y[6]; d3 += x[7] * y[7];
+        }
         for (; i + 3 * g < m; i += g4) {
           d0 += a[i] * bc[i];
           d1 += a[i + g] * bc[i + g];
@@ -375,6 +577,13 @@ __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const
         const double f = t * dot;
         if (gl == 0) bc[j] -= f;
         i = i0;
+        for (; i + 7 * g < m; i += g8) {
+          double x[8], y[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) { x[u] = a[i + u * g]; y[u] = bc[i + u * g]; }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) bc[i + u * g] = y[u] - f * x[u];
+        }
         for (; i + 3 * g < m; i += g4) {
           const double x0 = a[i], x1 = a[i + g], x2 = a[i + 2 * g], x3 = a[i + 3 * g];
           const double y0 = bc[i], y1 = bc[i + g], y2 = bc[i + 2 * g], y3 = bc[i + 3 * g];
