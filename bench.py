@@ -10,18 +10,31 @@ forward solve, log-determinant.  The data Z is a seeded standard-normal
 vector (the cost of an evaluation does not depend on Z).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu-baseline]
+                    [--calib-copy-gib G]
 
-Prints one JSON line.  `value` is evals/s with the dataset (locations, trees,
-schedule, Z) resident on the device before timing starts.  The roofline
-entry is for the dominant kernel, the H-Cholesky task executor: algorithmic
-flops counted by the device per launch over its average launch duration
-(HIP events on the library's stream), against the FP64 vector peak.
-`cpu_baseline` times the CPU oracle (oracle/, single thread) on a bounded
-sample of the same workload and scales it to n by n log^2 n.
+Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
+with the dataset (locations, trees, task schedule, Z) resident on the device
+before timing starts.
+
+roofline: the dominant kernel is the H-Cholesky executor k_level, launched once
+per dependency level of the task graph.  achieved = (algorithmic flops of one
+factorisation, counted by the device from the actual ranks) / (number of
+launches) / (average launch duration), where the launch duration is the
+factorisation time measured with HIP events on the library's stream divided
+by the number of launches; peak = MI355X FP64 vector rate.  traffic comes from
+the committed rocprofv3 counter summary for k_level when the kernel source is
+unchanged since the counters were taken, else null.
+
+cpu_baseline times the oracle (oracle/, one thread) on a bounded sample of the
+same workload and scales it to n by n log^2 n.
+
+--calib-copy-gib G adds one plain device copy of G GiB after the timed steps
+(outside the timed region), the reference kernel for HBM counter calibration.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,11 +47,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "likelihood evals/sec at n=256k, ε=1e-7 (FP64 vs mixed); p50/p99 latency"
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU
+KERNEL_SRC = os.path.join(ROOT, "paper_1709_04419_amd", "csrc", "hm_device.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_level_basin256k_traffic.json")
+THETA, NUGGET, LEAF, ETA = (1.0, 0.1, 0.325), 1e-6, 64, 2.0
 
 
-def cpu_baseline(n_full: int, sample_n: int = 3000) -> dict:
-    """Time the oracle (one evaluation) on a sample of the workload, in a
-    single-threaded child process, and scale to n_full by n log^2 n."""
+def log(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n_full: int, eps: float, sample_n: int = 6000) -> dict:
+    """Time one oracle evaluation (assembly, H-Cholesky, solve; the trees are
+    built before the clock starts, as on the device) at n = sample_n of the
+    same generator, single-threaded in a child process, and scale to n_full
+    by n log^2 n."""
     code = f"""
 import sys, time, json
 sys.path.insert(0, {ROOT!r})
@@ -46,33 +68,50 @@ from oracle.hchol import HLikelihood
 from paper_1709_04419_amd import workloads as wl
 P = wl.basin_clusters({sample_n}, 31)
 Z = wl.standard_normal({sample_n}, 1, 32)
+H = HLikelihood(P, {LEAF}, {ETA})
 t = time.perf_counter()
-H = HLikelihood(P, 64, 2.0)
-r = H.loglik((1.0, 0.1, 0.325), 1e-6, Z, 1e-7, 0)
+r = H.loglik({THETA!r}, {NUGGET}, Z, {eps}, 0)
 print(json.dumps(dict(seconds=time.perf_counter() - t, status=r['status'])))
 """
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
     res = json.loads(out.stdout.strip().splitlines()[-1])
     sec = res["seconds"]
     scale = (n_full * math.log2(n_full) ** 2) / (sample_n * math.log2(sample_n) ** 2)
     return {"value": 1.0 / (sec * scale), "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"one oracle evaluation at n={sample_n} (same generator, theta, eps, leaf) "
-                      f"took {sec:.2f} s on 1 thread; scaled to n={n_full} by n log^2 n (x{scale:.1f})"}
+            "sample": f"one oracle evaluation (assembly + H-Cholesky + solve) at n={sample_n} of the same "
+                      f"generator, theta, eps, leaf size and eta took {sec:.2f} s on 1 thread; scaled to "
+                      f"n={n_full} by n log^2 n (x{scale:.1f})"}
+
+
+def traffic_per_launch(n: int):
+    """HBM bytes per k_level launch from the committed counter summary, or None
+    when there is none for this workload or the kernel source has changed."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha or rec.get("n") != n:
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256000)
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding of the evaluation is not implemented.", file=sys.stderr)
+              "the evaluation is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -82,33 +121,50 @@ def main():
     from paper_1709_04419_amd import workloads as wl
 
     n, eps = args.n, args.eps
-    theta, nugget, leaf, eta = (1.0, 0.1, 0.325), 1e-6, 64, 2.0
     P = wl.basin_clusters(n, 31)
     Z = wl.standard_normal(n, 1, 32)
     ctx = hmlik.Context(0)
     t0 = time.perf_counter()
-    ds = hmlik.Dataset(ctx, P, leaf, eta)
+    ds = hmlik.Dataset(ctx, P, LEAF, ETA)
     t_setup = time.perf_counter() - t0
     ds.set_z(Z)
     info = ds.info()
-    for _ in range(args.warmup):
-        ds.loglik(theta, nugget, eps, 0)
+    log(f"dataset n={n}: {info['nblocks']} blocks, {info['ntasks']} tasks, {info['nlevels']} levels, "
+        f"set-up {t_setup:.2f} s")
+    for w in range(args.warmup):
+        s = time.perf_counter()
+        ds.loglik(THETA, NUGGET, eps, 0)
+        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - s:.2f} s")
     torch.cuda.synchronize()
     lat, fac, asm, sol = [], [], [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         s = time.perf_counter()
-        r = ds.loglik(theta, nugget, eps, 0)
+        r = ds.loglik(THETA, NUGGET, eps, 0)
         lat.append(time.perf_counter() - s)
         fac.append(r["t_factor"][0])
         asm.append(r["t_assemble"][0])
         sol.append(r["t_solve"][0])
+        log(f"step {k + 1}/{args.steps}: {lat[-1]:.2f} s (factor {fac[-1]:.2f} s)")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    if int(r["status"][0]) != 0:
+        raise SystemExit(f"bench: evaluation failed with status {int(r['status'][0])}")
+    if args.calib_copy_gib > 0:
+        m = int(args.calib_copy_gib * (1 << 30)) // 8
+        src = torch.ones(m, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {m * 8} bytes done")
+        del src, dst
+
     flops = ds.factor_flops()
-    nlaunch = info["nlevels"] if "nlevels" in info else None
+    launches = info["nlevels"]
     t_fac = float(np.mean(fac))
-    achieved = flops / t_fac / 1e12
+    avg_launch = t_fac / launches
+    achieved = flops / launches / avg_launch / 1e12
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -123,21 +179,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "basin256k" if n == 256000 else f"basin{n}", "n": n, "points": "basin_clusters(seed 31)",
-                   "theta": {"sigma2": 1.0, "ell": 0.1, "nu": 0.325}, "nugget": nugget, "eps": eps,
-                   "leaf_size": leaf, "eta": eta, "precision": "fp64", "tasks": info["ntasks"],
-                   "blocks": info["nblocks"]},
+        "config": {"workload": "basin256k" if n == 256000 else f"basin{n}", "n": n,
+                   "points": "basin_clusters(seed 31): 80% uniform in a non-convex basin, 20% in 10 clusters",
+                   "theta": {"sigma2": THETA[0], "ell": THETA[1], "nu": THETA[2]}, "nugget": NUGGET,
+                   "eps": eps, "leaf_size": LEAF, "eta": ETA, "precision": "fp64",
+                   "blocks": info["nblocks"], "tasks": info["ntasks"], "levels": launches},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "phases_ms": {"assemble": float(np.mean(asm)) * 1e3, "factor": t_fac * 1e3, "solve": float(np.mean(sol)) * 1e3,
-                      "dataset_setup_host": t_setup * 1e3},
+        "phases_ms": {"assemble": float(np.mean(asm)) * 1e3, "factor": t_fac * 1e3,
+                      "solve": float(np.mean(sol)) * 1e3, "dataset_setup_host": t_setup * 1e3},
         "loglik": float(r["loglik"][0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_level (H-Cholesky task executor)", "flops_per_eval": flops},
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_per_launch(n),
+                     "kernel": "k_level (H-Cholesky task executor, one launch per dependency level)",
+                     "launches": launches, "avg_launch_ms": avg_launch * 1e3,
+                     "flops_per_launch": flops / launches},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n)
-    print(json.dumps(out))
+        log("timing the oracle sample on the host")
+        out["cpu_baseline"] = cpu_baseline(n, eps)
+    ds.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

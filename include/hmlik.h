@@ -110,9 +110,12 @@ hm_status hm_solve(hm_dataset *ds, hm_result *out);
 /* hm_assemble + hm_factor + hm_solve. out has r entries. */
 hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, hm_result *out);
 
-/* Introspection (tests): sizes of the trees. */
+/* Introspection: sizes of the trees and of the factorisation's task graph.
+ * nlevels is the number of dependency levels of that graph, which is also the
+ * number of executor kernel launches per factorisation.  Any pointer may be
+ * NULL (that value is not written). */
 hm_status hm_dataset_info(const hm_dataset *ds, int64_t *n, int64_t *nclusters, int64_t *nblocks,
-                          int64_t *ntasks);
+                          int64_t *ntasks, int64_t *nlevels);
 
 /* Permutation (perm[i] = input index at permuted position i, n entries),
  * cluster ranges (2 per cluster: begin, end), boxes (4 per cluster: lo_x,

@@ -519,12 +519,13 @@ hm_status hm_loglik(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hm_
 }
 
 hm_status hm_dataset_info(const hm_dataset* ds, int64_t* n, int64_t* nclusters, int64_t* nblocks,
-                          int64_t* ntasks) {
+                          int64_t* ntasks, int64_t* nlevels) {
   if (!ds) return HM_ERR_ARG;
   if (n) *n = ds->tree.n;
   if (nclusters) *nclusters = (int64_t)ds->tree.cl.size();
   if (nblocks) *nblocks = (int64_t)ds->tree.bk.size();
   if (ntasks) *ntasks = (int64_t)ds->plan.tasks.size();
+  if (nlevels) *nlevels = (int64_t)ds->level_begin.size() - 1;
   return HM_OK;
 }
 

@@ -56,7 +56,7 @@ _sig = {
     "hm_factor": (C.c_int, [_P]),
     "hm_solve": (C.c_int, [_P, C.POINTER(hm_result)]),
     "hm_loglik": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx), C.POINTER(hm_result)]),
-    "hm_dataset_info": (C.c_int, [_P, _P, _P, _P, _P]),
+    "hm_dataset_info": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "hm_dataset_export_tree": (C.c_int, [_P, _P, _P, _P]),
     "hm_dataset_export_blocks": (C.c_int, [_P, _P, _P]),
     "hm_get_block": (C.c_int, [_P, C.c_int64, _P, C.POINTER(C.c_int32)]),
@@ -200,9 +200,9 @@ class Dataset:
         return _results(out)
 
     def info(self):
-        vals = [C.c_int64() for _ in range(4)]
+        vals = [C.c_int64() for _ in range(5)]
         _check(_lib.hm_dataset_info(self._h, *[C.byref(v) for v in vals]), "hm_dataset_info")
-        return dict(zip(("n", "nclusters", "nblocks", "ntasks"), (v.value for v in vals)))
+        return dict(zip(("n", "nclusters", "nblocks", "ntasks", "nlevels"), (v.value for v in vals)))
 
     def export_tree(self):
         inf = self.info()
