@@ -36,6 +36,8 @@ namespace hm {
 #define NQ ((LEAF_MAX * LEAF_MAX + NT - 1) / NT)
 // Most columns of a matrix that is truncated in explicit form.
 #define CMAX (4 * LEAF_MAX)
+// Reflectors per block in the compact WY (I - V T V^T) paths for tall panels.
+#define QB 8
 __device__ __forceinline__ int64_t clk() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
 // LDS arena (doubles) of the executor work-groups: one per CU.
 #define LDS_FACTOR 17408
@@ -214,6 +216,8 @@ struct Smem {
   double cn[2][CMAX];      // pivoted QR: partial column norms^2 (by column), by step parity
   int32_t pos[2][CMAX];    // pivoted QR: column at each position, by step parity
   double tau_p[CMAX];      // pivoted QR: reflector coefficients
+  double Tb[QB][QB];       // compact WY factor of a block of reflectors
+  double gp[NW][QB * (QB - 1) / 2];   // per-wave partial Gram entries of that block
   int32_t flag;
   int32_t task;
   int32_t ival[4];
@@ -504,43 +508,220 @@ __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Sme
   __syncthreads();
 }
 
+// Compact WY factor of reflectors j0 .. j0+nb-1 (nb <= QB; reflector j in
+// column pos[j] (or j) of A, v_j(j) = 1 implicit, zero above row j):
+//   H_{j0} H_{j0+1} ... H_{j0+nb-1} = I - V T V^T,  T upper triangular (S.Tb),
+// built from the Gram matrix V^T V column by column (T(l,l) = tau_l,
+// T(0:l,l) = -tau_l T(0:l,0:l) (V^T v_l)(0:l)).  Rows are dealt to the threads;
+// the partial Gram entries are combined per wave, then over the waves in a
+// fixed order.  Ends with a barrier.
+__device__ void wg_block_T(const double* A, int64_t m, int j0, int nb, int64_t lda, const int32_t* pos,
+                           const double* tau, Smem& S) {
+  constexpr int NP = QB * (QB - 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* v[QB];
+#pragma unroll
+  for (int l = 0; l < QB; ++l) {
+    const int jj = j0 + (l < nb ? l : 0);
+    v[l] = A + (int64_t)(pos ? pos[jj] : jj) * lda;
+  }
+  double g[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) g[q] = 0.0;
+  // the triangular rows j0 .. j0+nb-1, then the full rows
+  if (tid < nb && j0 + tid < m) {
+    const int64_t i = j0 + tid;
+    double x[QB];
+#pragma unroll
+    for (int l = 0; l < QB; ++l) x[l] = (l < nb && i >= j0 + l) ? ((i == j0 + l) ? 1.0 : v[l][i]) : 0.0;
+    int q = 0;
+#pragma unroll
+    for (int l = 0; l < QB; ++l)
+#pragma unroll
+      for (int l2 = l + 1; l2 < QB; ++l2) g[q++] += x[l] * x[l2];
+  }
+  for (int64_t i = j0 + nb + tid; i < m; i += NT) {
+    double x[QB];
+#pragma unroll
+    for (int l = 0; l < QB; ++l) x[l] = (l < nb) ? v[l][i] : 0.0;
+    int q = 0;
+#pragma unroll
+    for (int l = 0; l < QB; ++l)
+#pragma unroll
+      for (int l2 = l + 1; l2 < QB; ++l2) g[q++] += x[l] * x[l2];
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const double t = wave_sum(g[q]);
+    if (lane == 0) S.gp[wv][q] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double G[QB][QB];
+    int q = 0;
+    for (int l = 0; l < QB; ++l)
+      for (int l2 = l + 1; l2 < QB; ++l2) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += S.gp[w][q];
+        G[l][l2] = t;
+        ++q;
+      }
+    for (int l = 0; l < QB; ++l)
+      for (int i = 0; i < QB; ++i) S.Tb[i][l] = 0.0;
+    for (int l = 0; l < nb; ++l) {
+      const double tl = tau[j0 + l];
+      S.Tb[l][l] = tl;
+      for (int i = 0; i < l; ++i) {
+        double t = 0.0;
+        for (int p2 = i; p2 < l; ++p2) t += S.Tb[i][p2] * G[p2][l];
+        S.Tb[i][l] = -tl * t;
+      }
+    }
+    S.flops += (double)(m - j0) * nb * (nb - 1);
+  }
+  __syncthreads();
+}
+
+// B <- (I - V T V^T) B (trans = false) or (I - V T^T V^T) B (trans = true) for
+// the block of reflectors j0 .. j0+nb-1 with T = S.Tb (wg_block_T); B has k
+// columns (ldb) and rows j0 .. m-1 change.  One wavefront per four columns of
+// B; row i belongs to lane i mod 64, so no value crosses lanes between blocks.
+// Two passes over the rows: W = V^T B, then B -= V (T W).
+__device__ void wg_block_apply(const double* A, int64_t m, int j0, int nb, int64_t lda, const int32_t* pos,
+                               bool trans, double* B, int k, int64_t ldb, Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* v[QB];
+#pragma unroll
+  for (int l = 0; l < QB; ++l) {
+    const int jj = j0 + (l < nb ? l : 0);
+    v[l] = A + (int64_t)(pos ? pos[jj] : jj) * lda;
+  }
+  if (tid == 0) S.flops += 4.0 * (double)(m - j0) * nb * k;
+  const int64_t ifirst = j0 + ((lane - j0) & 63);
+  for (int c0 = 4 * wv; c0 < k; c0 += 4 * NW) {
+    const int nc = (k - c0 < 4) ? k - c0 : 4;
+    double* cols[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cols[q] = B + (int64_t)(c0 + (q < nc ? q : 0)) * ldb;
+    double w[QB][4];
+#pragma unroll
+    for (int l = 0; l < QB; ++l)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[l][q] = 0.0;
+    int64_t i = ifirst;
+    if (i < j0 + nb && i < m) {
+      double x[QB];
+#pragma unroll
+      for (int l = 0; l < QB; ++l) x[l] = (l < nb && i >= j0 + l) ? ((i == j0 + l) ? 1.0 : v[l][i]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nc) {
+          const double bq = cols[q][i];
+#pragma unroll
+          for (int l = 0; l < QB; ++l) w[l][q] += x[l] * bq;
+        }
+      i += 64;
+    }
+    for (; i + 64 < m; i += 128) {
+      double x0[QB], x1[QB], b0[4], b1[4];
+#pragma unroll
+      for (int l = 0; l < QB; ++l) { x0[l] = (l < nb) ? v[l][i] : 0.0; x1[l] = (l < nb) ? v[l][i + 64] : 0.0; }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { b0[q] = (q < nc) ? cols[q][i] : 0.0; b1[q] = (q < nc) ? cols[q][i + 64] : 0.0; }
+#pragma unroll
+      for (int l = 0; l < QB; ++l)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[l][q] += x0[l] * b0[q] + x1[l] * b1[q];
+    }
+    if (i < m) {
+      double x[QB];
+#pragma unroll
+      for (int l = 0; l < QB; ++l) x[l] = (l < nb) ? v[l][i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nc) {
+          const double bq = cols[q][i];
+#pragma unroll
+          for (int l = 0; l < QB; ++l) w[l][q] += x[l] * bq;
+        }
+    }
+    // W over the wave, then W' = T W (or T^T W)
+    double wt[QB][4];
+#pragma unroll
+    for (int l = 0; l < QB; ++l)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wt[l][q] = wave_sum(w[l][q]);
+#pragma unroll
+    for (int l = 0; l < QB; ++l)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int l2 = 0; l2 < QB; ++l2) t += (trans ? S.Tb[l2][l] : S.Tb[l][l2]) * wt[l2][q];
+        w[l][q] = t;
+      }
+    // B -= V W'
+    i = ifirst;
+    if (i < j0 + nb && i < m) {
+      double x[QB];
+#pragma unroll
+      for (int l = 0; l < QB; ++l) x[l] = (l < nb && i >= j0 + l) ? ((i == j0 + l) ? 1.0 : v[l][i]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nc) {
+          double t = 0.0;
+#pragma unroll
+          for (int l = 0; l < QB; ++l) t += x[l] * w[l][q];
+          cols[q][i] -= t;
+        }
+      i += 64;
+    }
+    for (; i < m; i += 64) {
+      double x[QB];
+#pragma unroll
+      for (int l = 0; l < QB; ++l) x[l] = (l < nb) ? v[l][i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nc) {
+          double t = 0.0;
+#pragma unroll
+          for (int l = 0; l < QB; ++l) t += x[l] * w[l][q];
+          cols[q][i] -= t;
+        }
+    }
+  }
+}
+
+// Householder QR of a tall A (m > TALL_ROWS) by panels of QB columns: each
+// panel by wg_qr, then its reflectors applied to the trailing columns in the
+// compact WY form.  Same reflectors, tau and R as wg_qr (up to rounding).
+__device__ void wg_qr_blocked(double* A, int64_t m, int r, int64_t lda, double* tau, Smem& S) {
+  const int p = (int)(m < r ? m : r);
+  for (int j0 = 0; j0 < p; j0 += QB) {
+    const int nb = (p - j0 < QB) ? p - j0 : QB;
+    wg_qr(A + j0 + (int64_t)j0 * lda, m - j0, nb, lda, tau + j0, S);
+    const int kt = r - j0 - nb;
+    if (kt > 0) {
+      wg_block_T(A, m, j0, nb, lda, nullptr, tau, S);
+      wg_block_apply(A, m, j0, nb, lda, nullptr, true, A + (int64_t)(j0 + nb) * lda, kt, lda, S);
+      __syncthreads();
+    }
+  }
+}
+
 // B <- Q B with Q = H_0 ... H_{p-1} from wg_qr (B is m x k, ldb).  With a
 // column map, reflector j is stored in column pos[j] of A (wg_cpqr).
 __device__ void wg_apply_q(const double* A, int64_t m, int p, int64_t lda, const double* tau,
-                           double* B, int k, int64_t ldb, const int32_t* pos = nullptr) {
+                           double* B, int k, int64_t ldb, Smem& S, const int32_t* pos = nullptr) {
   const int tid = threadIdx.x;
   if (k <= 0) return;
   if (m > TALL_ROWS) {
-    // tall: one wavefront per column of B, which it carries through all the
-    // reflectors with no work-group barrier in between.  Row i of the column
-    // belongs to lane i mod 64 throughout, so every value a lane reads was
-    // last written by that same lane (row j, read by all lanes for reflector
-    // j, is not modified by the reflectors applied before it).
-    // Four columns of a wave at a time.
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int c0 = 4 * wv; c0 < k; c0 += 4 * NW) {
-      const int nc = (k - c0 < 4) ? k - c0 : 4;
-      double* cols[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cols[q] = B + (int64_t)(c0 + (q < nc ? q : 0)) * ldb;
-      for (int j = p - 1; j >= 0; --j) {
-        const double t = tau[j];
-        if (t == 0.0) continue;
-        const double* a = A + (int64_t)(pos ? pos[j] : j) * lda;
-        const int64_t i0 = j + 1 + ((lane - (j + 1)) & 63);
-        double bj[4], dots[4], xx;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) bj[q] = (q < nc) ? cols[q][j] : 0.0;
-        wave_rows_dot4(a, cols, nc, i0, m, false, dots, xx);
-        double fneg[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double f = t * (bj[q] + wave_sum(dots[q]));
-          if (q < nc && lane == (j & 63)) cols[q][j] = bj[q] - f;
-          fneg[q] = -f;
-        }
-        wave_rows_axpy4(fneg, a, cols, nc, i0, m);
-      }
+    // tall: blocks of QB reflectors, last block first, each applied in the
+    // compact WY form (two passes over B per block)
+    for (int j0 = ((p - 1) / QB) * QB; j0 >= 0; j0 -= QB) {
+      const int nb = (p - j0 < QB) ? p - j0 : QB;
+      wg_block_T(A, m, j0, nb, lda, pos, tau, S);
+      wg_block_apply(A, m, j0, nb, lda, pos, false, B, k, ldb, S);
     }
     __syncthreads();
     return;
@@ -672,7 +853,7 @@ __device__ __forceinline__ int64_t odd_ld(int64_t rows) { return rows | 1; }
 // B <- Q B (wg_apply_q) with the reflectors and B staged through LDS when both
 // fit (odd leading dimensions against bank conflicts).
 __device__ void wg_apply_q_staged(const double* A, int64_t m, int p, const double* tau, double* B, int k,
-                                  double* lds, int lds_cap) {
+                                  double* lds, int lds_cap, Smem& S) {
   const int tid = threadIdx.x;
   if (k <= 0) return;
   const int64_t ld = odd_ld(m);
@@ -682,11 +863,11 @@ __device__ void wg_apply_q_staged(const double* A, int64_t m, int p, const doubl
     for (int64_t e = tid; e < m * p; e += NT) As[(e % m) + (e / m) * ld] = A[e];
     for (int64_t e = tid; e < m * k; e += NT) Bs[(e % m) + (e / m) * ld] = B[e];
     __syncthreads();
-    wg_apply_q(As, m, p, ld, tau, Bs, k, ld);
+    wg_apply_q(As, m, p, ld, tau, Bs, k, ld, S);
     for (int64_t e = tid; e < m * k; e += NT) B[e] = Bs[(e % m) + (e / m) * ld];
     __syncthreads();
   } else {
-    wg_apply_q(A, m, p, m, tau, B, k, m);
+    wg_apply_q(A, m, p, m, tau, B, k, m, S);
   }
 }
 
@@ -950,7 +1131,7 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
     for (int j = 0; j < r; ++j) f += 4.0 * (double)(m - j) * k;
     S.flops += f;
   }
-  wg_apply_q(A, m, r, lda, S.tau_p, U, k, ldu, pos);
+  wg_apply_q(A, m, r, lda, S.tau_p, U, k, ldu, S, pos);
   if (timed && tid == 0) S.ph[2] += clk() - c0;
   return k;
 }
@@ -978,6 +1159,8 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
       wg_qr(lds_g, rows, r, ld, tau, S);
       for (int64_t e = tid; e < rows * r; e += NT) A[e] = lds_g[(e % rows) + (e / rows) * ld];
       __syncthreads();
+    } else if (rows > TALL_ROWS) {
+      wg_qr_blocked(A, rows, r, rows, tau, S);
     } else {
       wg_qr(A, rows, r, rows, tau, S);
     }
@@ -1014,8 +1197,8 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
     for (int j = 0; j < py; ++j) f += 4.0 * (double)(n - j) * k;
     S.flops += f;
   }
-  wg_apply_q_staged(X, m, px, S.tau_x, U, k, lds_g, lds_cap);
-  wg_apply_q_staged(Y, n, py, S.tau_y, V, k, lds_g, lds_cap);
+  wg_apply_q_staged(X, m, px, S.tau_x, U, k, lds_g, lds_cap, S);
+  wg_apply_q_staged(Y, n, py, S.tau_y, V, k, lds_g, lds_cap, S);
   __syncthreads();
   if (tid == 0) S.ph[2] += clk() - c0;
   return k;

@@ -101,6 +101,7 @@ CASES = [
     (784, ("grid", 7), 24, (2.0, 0.0334, 0.5), 1e-4, 1e-6, 0),          # perturbed grid of eq. (3)
     (777, ("uniform", 9), 20, (1.0, 0.05, 2.2), 1e-6, 1e-9, 0),         # ragged n, nu > 2 (two recurrences)
     (1000, ("uniform", 22), 32, (1.0, 0.2, 1.5), 1e-6, 0.0, 5),         # fixed rank 5: breaks down (not SPD)
+    (6000, ("basin", 31), 64, (1.0, 0.1, 0.325), 1e-6, 1e-7, 0),       # low-rank blocks of 750 rows (tall panels)
 ]
 
 
@@ -202,11 +203,14 @@ def test_argument_errors(H, ctx):
 
 
 @pytest.mark.parametrize("m,n,r,eps,rk", [(64, 64, 20, 1e-8, 0), (250, 125, 64, 1e-7, 0), (31, 200, 40, 1e-6, 0),
-                                          (128, 100, 90, 1e-8, 0), (64, 64, 64, 0.0, 7), (1, 50, 3, 1e-7, 0)])
+                                          (128, 100, 90, 1e-8, 0), (64, 64, 64, 0.0, 7), (1, 50, 3, 1e-7, 0),
+                                          (700, 650, 40, 1e-7, 0), (1500, 600, 64, 1e-7, 0), (300, 1400, 50, 1e-7, 0),
+                                          (900, 800, 61, 0.0, 9), (3000, 2500, 64, 1e-7, 0), (2000, 530, 128, 1e-7, 0)])
 def test_truncation_parity(H, ctx, m, n, r, eps, rk):
     """Device truncation of X Y^T vs numpy's SVD of the explicit product:
-    same rank, Eckart-Young optimal error."""
-    P = wl.uniform_square(4000, 2)
+    same rank, Eckart-Young optimal error.  Panels of more than 512 rows take
+    the blocked (compact WY) QR and Q application."""
+    P = wl.uniform_square(16000 if m + n > 2000 else 4000, 2)
     ds = H.Dataset(ctx, P, 64, 2.0)
     rng = np.random.default_rng(m * 1000 + r)
     X = (rng.standard_normal((m, min(r, 25))) @ rng.standard_normal((min(r, 25), r))) * np.logspace(0, -13, r)
