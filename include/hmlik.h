@@ -151,8 +151,12 @@ hm_status hm_get_term(hm_dataset *ds, int64_t term, double *data, int32_t *kind,
  * 1 <= r <= 128) at relative accuracy eps (fixed_rank == 0) or rank
  * fixed_rank, through the same device routine the H-Cholesky uses.  U (m x 64)
  * and V (n x 64) receive the k = *k factors; seconds (4 entries, may be NULL)
- * the kernel time and its QR, SVD and back-transformation phases.  Uses the
- * dataset's workspace (m, n at most its largest low-rank block). */
+ * the kernel time and its QR, SVD and back-transformation phases.  With
+ * Y == NULL and r == 0, X is instead an explicit m x n matrix (n <= 256)
+ * truncated by the routine of the explicit flush of small low-rank blocks
+ * (pivoted QR, then one-sided Jacobi on R^T); the phases are then the pivoted
+ * QR, the Jacobi iteration and the formation of U and V.  Uses the dataset's
+ * workspace (HM_ERR_ARG if the matrices do not fit in one slot of it). */
 hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const double *Y, int64_t n, int32_t r,
                            double eps, int32_t fixed_rank, double *U, double *V, int32_t *k, double *seconds);
 

@@ -621,9 +621,14 @@ hm_status hm_get_term(hm_dataset* ds, int64_t term, double* data, int32_t* kind,
 
 hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const double* Y, int64_t n, int32_t r,
                            double eps, int32_t fixed_rank, double* U, double* V, int32_t* k, double* seconds) {
-  if (!ds || !X || !Y || !U || !V || !k || m < 1 || n < 1 || r < 1 || r > 2 * K_MAX) return HM_ERR_ARG;
+  const bool expl = (Y == nullptr);
+  if (!ds || !X || !U || !V || !k || m < 1 || n < 1) return HM_ERR_ARG;
+  if (expl ? (r != 0 || n > 4 * LEAF_MAX) : (r < 1 || r > 2 * K_MAX)) return HM_ERR_ARG;
   if (fixed_rank < 0 || fixed_rank > K_MAX || (fixed_rank == 0 && !finite_pos(eps))) return HM_ERR_ARG;
-  if ((m + n) * (int64_t)r + 2 * (int64_t)(r + 1) * r + 64 > ds->D.ws_stride) return HM_ERR_ARG;
+  const int64_t need = expl ? m * n + (n | 1) * (m < n ? m : n) + 64
+                            : (m + n) * (int64_t)r + 2 * (int64_t)(r + 1) * r + 64;
+  if (need > ds->D.ws_stride) return HM_ERR_ARG;
+  const int64_t xs = expl ? m * n : m * (int64_t)r;
   HIPTRY(hipSetDevice(ds->ctx->device));
   hipStream_t st = ds->ctx->stream;
   DevData D = ds->D;
@@ -632,15 +637,16 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
   D.kmax = fixed_rank > 0 ? fixed_rank : K_MAX;
   void *dX = nullptr, *dY = nullptr, *dU = nullptr, *dV = nullptr, *dk = nullptr, *dph = nullptr;
   hm_status s = HM_OK;
-  if (hipMalloc(&dX, sizeof(double) * m * r) != hipSuccess || hipMalloc(&dY, sizeof(double) * n * r) != hipSuccess ||
+  if (hipMalloc(&dX, sizeof(double) * xs) != hipSuccess ||
+      (!expl && hipMalloc(&dY, sizeof(double) * n * r) != hipSuccess) ||
       hipMalloc(&dU, sizeof(double) * m * K_MAX) != hipSuccess ||
       hipMalloc(&dV, sizeof(double) * n * K_MAX) != hipSuccess || hipMalloc(&dk, sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&dph, sizeof(int64_t) * 4) != hipSuccess)
     s = HM_ERR_OOM;
   if (s == HM_OK) {
     float ms = 0;
-    if (hipMemcpy(dX, X, sizeof(double) * m * r, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dY, Y, sizeof(double) * n * r, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(dX, X, sizeof(double) * xs, hipMemcpyHostToDevice) != hipSuccess ||
+        (!expl && hipMemcpy(dY, Y, sizeof(double) * n * r, hipMemcpyHostToDevice) != hipSuccess) ||
         hipEventRecord(ds->ev[0], st) != hipSuccess ||
         launch_truncate_test(D, (double*)dX, m, (double*)dY, n, r, (double*)dU, (double*)dV, (int32_t*)dk,
                              (int64_t*)dph, st) !=

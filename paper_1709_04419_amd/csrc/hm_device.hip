@@ -234,8 +234,10 @@ __device__ __forceinline__ int group_size(int cols) {
   return g;
 }
 
-// Panels with more rows than this are processed one wavefront per column.
-#define TALL_ROWS 512
+// Panels with more rows than these take the wave-per-column QR steps and the
+// blocked QR (TALL_QR_ROWS), and the blocked application of Q (TALL_ROWS).
+#define TALL_QR_ROWS 512
+#define TALL_ROWS 256
 
 // Lane-strided partial dot product sum_{i = i0, i0 + 64, ... < m} x[i] y[i],
 // eight rows in flight (combine across the wave with wave_sum).
@@ -361,7 +363,7 @@ __device__ void wg_qr(double* A, int64_t m, int r, int64_t lda, double* tau, Sme
     const double alpha = a[j];
     const int C = r - j - 1;
     double s = 0.0, t = 0.0, beta = alpha, scale = 0.0;
-    if (C > 0 && m - j > TALL_ROWS) {
+    if (C > 0 && m - j > TALL_QR_ROWS) {
       // tall panel: one wavefront per trailing column (each load instruction
       // reads 64 consecutive rows), columns dealt round-robin to the waves;
       // every wave forms the pivot norm itself, over the same rows and order
@@ -692,7 +694,7 @@ __device__ void wg_block_apply(const double* A, int64_t m, int j0, int nb, int64
   }
 }
 
-// Householder QR of a tall A (m > TALL_ROWS) by panels of QB columns: each
+// Householder QR of a tall A (m > TALL_QR_ROWS) by panels of QB columns: each
 // panel by wg_qr, then its reflectors applied to the trailing columns in the
 // compact WY form.  Same reflectors, tau and R as wg_qr (up to rounding).
 __device__ void wg_qr_blocked(double* A, int64_t m, int r, int64_t lda, double* tau, Smem& S) {
@@ -1159,7 +1161,7 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
       wg_qr(lds_g, rows, r, ld, tau, S);
       for (int64_t e = tid; e < rows * r; e += NT) A[e] = lds_g[(e % rows) + (e / rows) * ld];
       __syncthreads();
-    } else if (rows > TALL_ROWS) {
+    } else if (rows > TALL_QR_ROWS) {
       wg_qr_blocked(A, rows, r, rows, tau, S);
     } else {
       wg_qr(A, rows, r, rows, tau, S);
@@ -1832,14 +1834,23 @@ __global__ void __launch_bounds__(NT) k_truncate_test(DevData D, const double* X
                                                       double* V, int32_t* kout, int64_t* phases) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
-  double* Xa = D.ws;
-  double* Ya = Xa + m * r;
-  double* scratch = Ya + n * r;
-  for (int64_t e = threadIdx.x; e < m * r; e += NT) Xa[e] = X[e];
-  for (int64_t e = threadIdx.x; e < n * r; e += NT) Ya[e] = Y[e];
   if (threadIdx.x == 0) S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0;
-  __syncthreads();
-  const int k = wg_truncate(D, Xa, m, Ya, n, r, U, V, scratch, dyn, LDS_FACTOR, S);
+  int k;
+  if (Y == nullptr) {
+    // explicit m x n matrix (n <= CMAX): the path of the explicit flush
+    double* A = D.ws;
+    for (int64_t e = threadIdx.x; e < m * n; e += NT) A[e] = X[e];
+    __syncthreads();
+    k = wg_svd_explicit(D, A, (int)m, (int)n, m, U, m, m, V, n, n, A + m * n, dyn, LDS_FACTOR, S, true);
+  } else {
+    double* Xa = D.ws;
+    double* Ya = Xa + m * r;
+    double* scratch = Ya + n * r;
+    for (int64_t e = threadIdx.x; e < m * r; e += NT) Xa[e] = X[e];
+    for (int64_t e = threadIdx.x; e < n * r; e += NT) Ya[e] = Y[e];
+    __syncthreads();
+    k = wg_truncate(D, Xa, m, Ya, n, r, U, V, scratch, dyn, LDS_FACTOR, S);
+  }
   if (threadIdx.x == 0) {
     *kout = k;
     for (int q = 0; q < 3; ++q) phases[q] = S.ph[q];

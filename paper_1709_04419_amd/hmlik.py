@@ -254,17 +254,24 @@ class Dataset:
         return U, V
 
 
-def test_truncate(ds: "Dataset", X, Y, eps=0.0, rank=0):
-    """hm_test_truncate: device truncation of X Y^T; returns (U, V, [total, qr, svd, back] seconds)."""
+def test_truncate(ds: "Dataset", X, Y=None, eps=0.0, rank=0):
+    """hm_test_truncate: device truncation of X Y^T, or of the explicit matrix X
+    when Y is None; returns (U, V, [total, phase1, phase2, phase3] seconds)."""
     X = np.asfortranarray(X, dtype=np.float64)
-    Y = np.asfortranarray(Y, dtype=np.float64)
-    m, r = X.shape
-    n = Y.shape[0]
+    if Y is None:
+        m, n = X.shape
+        r = 0
+        yp = None
+    else:
+        Y = np.asfortranarray(Y, dtype=np.float64)
+        m, r = X.shape
+        n = Y.shape[0]
+        yp = _ptr(Y)
     U = np.zeros((m, 64), order="F")
     V = np.zeros((n, 64), order="F")
     k = C.c_int32()
     sec = (C.c_double * 4)()
-    _check(_lib.hm_test_truncate(ds._h, _ptr(X), m, _ptr(Y), n, r, float(eps), int(rank), _ptr(U), _ptr(V),
+    _check(_lib.hm_test_truncate(ds._h, _ptr(X), m, yp, n, r, float(eps), int(rank), _ptr(U), _ptr(V),
                                  C.byref(k), sec), "hm_test_truncate")
     kk = k.value
     Uo = np.asarray(U.reshape(-1, order="F")[:m * kk].reshape(kk, m).T)

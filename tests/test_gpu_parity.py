@@ -223,3 +223,25 @@ def test_truncation_parity(H, ctx, m, n, r, eps, rk):
     opt = sv[k] if k < len(sv) else 0.0
     assert np.linalg.norm(M - U @ V.T, 2) <= opt * (1 + 1e-6) + 1e-13 * sv[0]
     ds.close()
+
+
+@pytest.mark.parametrize("m,n,eps,rk", [(62, 62, 1e-7, 0), (125, 125, 1e-7, 0), (250, 250, 1e-7, 0),
+                                        (250, 180, 1e-8, 0), (200, 256, 0.0, 10), (1, 40, 1e-7, 0),
+                                        (70, 1, 1e-7, 0), (256, 256, 1e-12, 0)])
+def test_explicit_truncation_parity(H, ctx, m, n, eps, rk):
+    """Truncation of an explicit matrix (the explicit flush of small low-rank
+    blocks: pivoted QR, then Jacobi on R^T) vs numpy's SVD: same rank,
+    Eckart-Young optimal error."""
+    ds = H.Dataset(ctx, wl.uniform_square(4000, 2), 64, 2.0)
+    rng = np.random.default_rng(m * 7 + n)
+    q = min(m, n)
+    A = rng.standard_normal((m, q)) * np.logspace(0, -15, q)
+    B = rng.standard_normal((q, n))
+    M = A @ B
+    U, V, _ = H.test_truncate(ds, M, None, eps, rk)
+    sv = np.linalg.svd(M, compute_uv=False)
+    k = min(rk, int(np.count_nonzero(sv > 0))) if rk else min(int(np.count_nonzero(sv > eps * sv[0])), 64)
+    assert U.shape[1] == k
+    opt = sv[k] if k < len(sv) else 0.0
+    assert np.linalg.norm(M - U @ V.T, 2) <= opt * (1 + 1e-6) + 1e-13 * sv[0]
+    ds.close()
