@@ -80,8 +80,11 @@ typedef struct {
 } hm_result;
 
 /* Create a context on HIP device `device`.  `stream` is a hipStream_t (NULL =
- * the default stream) on which all work of this context is ordered. */
+ * the default stream) on which all work of this context is ordered.  The
+ * context owns the work-group workspace its datasets share (grown, with a
+ * synchronisation, when a dataset that needs more is created). */
 hm_status hm_ctx_create(int device, void *stream, hm_ctx **out);
+/* Destroy every dataset of a context before the context itself. */
 void hm_ctx_destroy(hm_ctx *ctx);
 
 /* Build the cluster tree and block cluster tree for n locations (App. B,
@@ -109,6 +112,21 @@ hm_status hm_solve(hm_dataset *ds, hm_result *out);
 
 /* hm_assemble + hm_factor + hm_solve. out has r entries. */
 hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, hm_result *out);
+
+/* Batched evaluation of eq. (4) (Monte-Carlo replicates, several theta on
+ * copies of one dataset, or unrelated datasets): dataset ds[i] is evaluated at
+ * theta[i] and approx[i], i < m.  The assemblies are enqueued back to back and
+ * the H-Cholesky of all datasets runs together, one launch per level index of
+ * their task graphs, so that the datasets fill work-groups one alone leaves
+ * idle.  Every dataset gets bitwise the results of hm_loglik alone.  out
+ * receives sum_i r_i results, dataset by dataset (r_i = columns of its Z).
+ * The datasets must be distinct, belong to ctx and have Z set (else
+ * HM_ERR_ARG).  Returns HM_ERR_NOT_SPD if any factorisation broke down (the
+ * per-result status says which); t_factor is the batch's factorisation time.
+ * Allocates two small device tables per call (the level table and the
+ * datasets' descriptors). */
+hm_status hm_loglik_batch(hm_ctx *ctx, int32_t m, hm_dataset *const *ds, const hm_theta *theta,
+                          const hm_approx *approx, hm_result *out);
 
 /* Introspection: sizes of the trees and of the factorisation's task graph.
  * nlevels is the number of dependency levels of that graph, which is also the

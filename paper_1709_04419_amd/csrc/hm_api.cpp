@@ -21,6 +21,10 @@ using namespace hm;
 struct hm_ctx {
   int device;
   hipStream_t stream;
+  // workspace slots shared by the context's datasets (evaluations on one
+  // context are ordered on its stream); grown when a dataset needs more
+  double* ws = nullptr;
+  int64_t ws_stride = 0;
 };
 
 namespace {
@@ -141,6 +145,12 @@ MaternConst make_matern(const hm_theta& th) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// The dataset's kernels use the context's current workspace.
+void use_ctx_ws(hm_dataset* ds) {
+  ds->D.ws = ds->ctx->ws;
+  ds->D.ws_stride = ds->ctx->ws_stride;
+}
+
 hm_status build_device(hm_dataset* ds) {
   const Tree& T = ds->tree;
   const Plan& P = ds->plan;
@@ -200,9 +210,21 @@ hm_status build_device(hm_dataset* ds) {
   int64_t stride = 2 * mr * (2 * K_MAX) + mr + 2 * (2 * K_MAX + 1) * (2 * K_MAX) + 4096;
   if (stride < df * df + (df + 1) * df + 64) stride = df * df + (df + 1) * df + 64;
   stride = (stride + 63) & ~(int64_t)63;
-  D.ws_stride = stride;
-  TRY(dev_alloc(ds, sizeof(double) * stride * NSLOTS, &p));
-  D.ws = (double*)p;
+  hm_ctx* c = ds->ctx;
+  if (c->ws_stride < stride) {
+    HIPTRY(hipStreamSynchronize(c->stream));
+    if (c->ws) (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_stride = 0;
+    void* w = nullptr;
+    if (hipMalloc(&w, sizeof(double) * stride * NSLOTS) != hipSuccess) {
+      (void)hipGetLastError();
+      return HM_ERR_OOM;
+    }
+    c->ws = (double*)w;
+    c->ws_stride = stride;
+  }
+  use_ctx_ws(ds);
   TRY(dev_alloc(ds, sizeof(double) * (P.tasks.size() + 1), &p));
   D.task_flops = (double*)p;
   if (getenv("HMLIK_TASK_TIMES")) {
@@ -246,7 +268,15 @@ hm_status hm_ctx_create(int device, void* stream, hm_ctx** out) {
   return HM_OK;
 }
 
-void hm_ctx_destroy(hm_ctx* ctx) { delete ctx; }
+void hm_ctx_destroy(hm_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->ws) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->ws);
+  }
+  delete ctx;
+}
 
 hm_status hm_dataset_create(hm_ctx* ctx, const double* coords, int64_t n, const hm_tree_opts* opts,
                             hm_dataset** out) {
@@ -341,15 +371,23 @@ hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t o
   return HM_OK;
 }
 
-hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
-  if (!ds || !th || !ap) return HM_ERR_ARG;
+static hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
+  if (!th || !ap) return HM_ERR_ARG;
   if (!finite_pos(th->sigma2) || !finite_pos(th->ell) || !finite_pos(th->nu)) return HM_ERR_ARG;
   if (!std::isfinite(th->nugget) || th->nugget < 0.0) return HM_ERR_ARG;
   if (ap->fixed_rank < 0 || ap->fixed_rank > K_MAX) return HM_ERR_ARG;
   if (ap->fixed_rank == 0 && !finite_pos(ap->eps)) return HM_ERR_ARG;
   if (ap->fixed_rank > 0 && !(std::isfinite(ap->eps) && ap->eps >= 0.0)) return HM_ERR_ARG;
   if (th->nu > 50.0) return HM_ERR_ARG;
+  return HM_OK;
+}
+
+// Sets theta and the accuracy and enqueues the assembly, bracketed by ev[0],
+// ev[1] (no synchronisation).
+static hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
+  TRY(check_theta_approx(th, ap));
   HIPTRY(hipSetDevice(ds->ctx->device));
+  use_ctx_ws(ds);
   DevData& D = ds->D;
   D.mc = make_matern(*th);
   D.kfix = ap->fixed_rank;
@@ -360,6 +398,12 @@ hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
   HIPTRY(launch_assemble(D, st));
   HIPTRY(launch_aca(D, NSLOTS, st));
   HIPTRY(hipEventRecord(ds->ev[1], st));
+  return HM_OK;
+}
+
+hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
+  if (!ds) return HM_ERR_ARG;
+  TRY(assemble_launch(ds, th, ap));
   HIPTRY(hipEventSynchronize(ds->ev[1]));
   float ms = 0;
   HIPTRY(hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]));
@@ -369,46 +413,8 @@ hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
   return HM_OK;
 }
 
-hm_status hm_factor(hm_dataset* ds) {
-  if (!ds || !ds->assembled) return HM_ERR_ARG;
-  HIPTRY(hipSetDevice(ds->ctx->device));
+static hm_status finish_factor(hm_dataset* ds) {
   DevData& D = ds->D;
-  hipStream_t st = ds->ctx->stream;
-  HIPTRY(hipEventRecord(ds->ev[1], st));
-  if (getenv("HMLIK_PERSISTENT_EXECUTOR")) {
-    // persistent ticket scheduler: disabled by default (stalled on the device,
-    // cause not yet established)
-    int grid = NEXEC;
-    if (const char* e = getenv("HMLIK_EXEC_WGS")) {
-      grid = atoi(e);
-      if (grid < 1 || grid > NSLOTS) grid = NEXEC;
-    }
-    HIPTRY(launch_factor(D, grid, st));
-  } else {
-    const int32_t nlev = (int32_t)ds->level_begin.size() - 1;
-    // HMLIK_PROGRESS=<levels>: synchronise every <levels> levels and report
-    // progress on stderr (for long factorisations; costs a sync per chunk)
-    int32_t chunk = nlev;
-    if (const char* e = getenv("HMLIK_PROGRESS")) chunk = std::max(1, atoi(e));
-    for (int32_t l0 = 0; l0 < nlev; l0 += chunk) {
-      const int32_t l1 = std::min(nlev, l0 + chunk);
-      HIPTRY(launch_factor_levels(D, ds->level_begin.data(), l0, l1, l0 == 0, NSLOTS, st));
-      if (l1 < nlev) {
-        HIPTRY(hipStreamSynchronize(st));
-        HIPTRY(hipEventRecord(ds->ev[2], st));
-        HIPTRY(hipEventSynchronize(ds->ev[2]));
-        float ms = 0;
-        HIPTRY(hipEventElapsedTime(&ms, ds->ev[1], ds->ev[2]));
-        fprintf(stderr, "hmlik factor: level %d of %d, task %d of %d, %.1f s\n", l1, nlev, ds->level_begin[l1],
-                ds->level_begin[nlev], ms * 1e-3);
-      }
-    }
-  }
-  HIPTRY(hipEventRecord(ds->ev[2], st));
-  HIPTRY(hipEventSynchronize(ds->ev[2]));
-  float ms = 0;
-  HIPTRY(hipEventElapsedTime(&ms, ds->ev[1], ds->ev[2]));
-  ds->t_factor = ms * 1e-3;
   int32_t flags[2];
   unsigned long long key = 0;
   HIPTRY(hipMemcpy(&flags[0], D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -461,6 +467,50 @@ hm_status hm_factor(hm_dataset* ds) {
   }
   ds->factor_status = HM_OK;
   return HM_OK;
+}
+
+hm_status hm_factor(hm_dataset* ds) {
+  if (!ds || !ds->assembled) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  use_ctx_ws(ds);
+  DevData& D = ds->D;
+  hipStream_t st = ds->ctx->stream;
+  HIPTRY(hipEventRecord(ds->ev[1], st));
+  if (getenv("HMLIK_PERSISTENT_EXECUTOR")) {
+    // persistent ticket scheduler: disabled by default (stalled on the device,
+    // cause not yet established)
+    int grid = NEXEC;
+    if (const char* e = getenv("HMLIK_EXEC_WGS")) {
+      grid = atoi(e);
+      if (grid < 1 || grid > NSLOTS) grid = NEXEC;
+    }
+    HIPTRY(launch_factor(D, grid, st));
+  } else {
+    const int32_t nlev = (int32_t)ds->level_begin.size() - 1;
+    // HMLIK_PROGRESS=<levels>: synchronise every <levels> levels and report
+    // progress on stderr (for long factorisations; costs a sync per chunk)
+    int32_t chunk = nlev;
+    if (const char* e = getenv("HMLIK_PROGRESS")) chunk = std::max(1, atoi(e));
+    for (int32_t l0 = 0; l0 < nlev; l0 += chunk) {
+      const int32_t l1 = std::min(nlev, l0 + chunk);
+      HIPTRY(launch_factor_levels(D, ds->level_begin.data(), l0, l1, l0 == 0, NSLOTS, st));
+      if (l1 < nlev) {
+        HIPTRY(hipStreamSynchronize(st));
+        HIPTRY(hipEventRecord(ds->ev[2], st));
+        HIPTRY(hipEventSynchronize(ds->ev[2]));
+        float ms = 0;
+        HIPTRY(hipEventElapsedTime(&ms, ds->ev[1], ds->ev[2]));
+        fprintf(stderr, "hmlik factor: level %d of %d, task %d of %d, %.1f s\n", l1, nlev, ds->level_begin[l1],
+                ds->level_begin[nlev], ms * 1e-3);
+      }
+    }
+  }
+  HIPTRY(hipEventRecord(ds->ev[2], st));
+  HIPTRY(hipEventSynchronize(ds->ev[2]));
+  float ms = 0;
+  HIPTRY(hipEventElapsedTime(&ms, ds->ev[1], ds->ev[2]));
+  ds->t_factor = ms * 1e-3;
+  return finish_factor(ds);
 }
 
 hm_status hm_solve(hm_dataset* ds, hm_result* out) {
@@ -516,6 +566,78 @@ hm_status hm_loglik(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hm_
   hm_status s = hm_factor(ds);
   if (s != HM_OK && s != HM_ERR_NOT_SPD) return s;
   return hm_solve(ds, out);
+}
+
+hm_status hm_loglik_batch(hm_ctx* ctx, int32_t m, hm_dataset* const* ds, const hm_theta* theta,
+                          const hm_approx* approx, hm_result* out) {
+  if (!ctx || m < 1 || !ds || !theta || !approx || !out) return HM_ERR_ARG;
+  for (int32_t i = 0; i < m; ++i) {
+    if (!ds[i] || ds[i]->ctx != ctx || ds[i]->r < 1) return HM_ERR_ARG;
+    for (int32_t j = 0; j < i; ++j)
+      if (ds[j] == ds[i]) return HM_ERR_ARG;
+    TRY(check_theta_approx(&theta[i], &approx[i]));
+  }
+  HIPTRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  for (int32_t i = 0; i < m; ++i) TRY(assemble_launch(ds[i], &theta[i], &approx[i]));
+  // per level index l, the task range of each dataset (empty past its last level)
+  int32_t L = 0;
+  for (int32_t i = 0; i < m; ++i) L = std::max(L, (int32_t)ds[i]->level_begin.size() - 1);
+  std::vector<int32_t> seg((size_t)L * 2 * m, 0), total(L, 0);
+  std::vector<DevData> hD(m);
+  for (int32_t i = 0; i < m; ++i) {
+    hD[i] = ds[i]->D;
+    const std::vector<int32_t>& lb = ds[i]->level_begin;
+    for (int32_t l = 0; l + 1 < (int32_t)lb.size(); ++l) {
+      seg[((size_t)l * m + i) * 2] = lb[l];
+      seg[((size_t)l * m + i) * 2 + 1] = lb[l + 1];
+      total[l] += lb[l + 1] - lb[l];
+    }
+  }
+  void *dD = nullptr, *dseg = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hm_status s = HM_OK;
+  if (hipMalloc(&dD, sizeof(DevData) * m) != hipSuccess ||
+      hipMalloc(&dseg, sizeof(int32_t) * std::max<size_t>(seg.size(), 2)) != hipSuccess)
+    s = HM_ERR_OOM;
+  if (s == HM_OK &&
+      (hipMemcpyAsync(dD, hD.data(), sizeof(DevData) * m, hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipMemcpyAsync(dseg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    s = HM_ERR_DEVICE;
+  float ms = 0;
+  if (s == HM_OK) {
+    bool ok = hipEventRecord(e0, st) == hipSuccess;
+    for (int32_t i = 0; ok && i < m; ++i) ok = launch_factor_init(hD[i], st) == hipSuccess;
+    for (int32_t l = 0; ok && l < L; ++l)
+      ok = launch_level_batch((const DevData*)dD, (const int32_t*)dseg + (size_t)l * 2 * m, m, total[l], NSLOTS,
+                              st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (!ok) s = HM_ERR_DEVICE;
+  }
+  (void)hipStreamSynchronize(st);
+  if (dD) (void)hipFree(dD);
+  if (dseg) (void)hipFree(dseg);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  if (s != HM_OK) return s;
+  hm_status any = HM_OK;
+  size_t off = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    float ma = 0;
+    HIPTRY(hipEventElapsedTime(&ma, ds[i]->ev[0], ds[i]->ev[1]));
+    ds[i]->t_assemble = ma * 1e-3;
+    ds[i]->t_factor = ms * 1e-3;
+    const hm_status fs = finish_factor(ds[i]);
+    if (fs != HM_OK && fs != HM_ERR_NOT_SPD) return fs;
+    const hm_status ss = hm_solve(ds[i], out + off);
+    if (ss != HM_OK && ss != HM_ERR_NOT_SPD) return ss;
+    if (ss == HM_ERR_NOT_SPD) any = HM_ERR_NOT_SPD;
+    off += (size_t)ds[i]->r;
+  }
+  return any;
 }
 
 hm_status hm_dataset_info(const hm_dataset* ds, int64_t* n, int64_t* nclusters, int64_t* nblocks,
@@ -627,6 +749,7 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
   if (fixed_rank < 0 || fixed_rank > K_MAX || (fixed_rank == 0 && !finite_pos(eps))) return HM_ERR_ARG;
   const int64_t need = expl ? m * n + (n | 1) * (m < n ? m : n) + 64
                             : (m + n) * (int64_t)r + 2 * (int64_t)(r + 1) * r + 64;
+  use_ctx_ws(ds);
   if (need > ds->D.ws_stride) return HM_ERR_ARG;
   const int64_t xs = expl ? m * n : m * (int64_t)r;
   HIPTRY(hipSetDevice(ds->ctx->device));

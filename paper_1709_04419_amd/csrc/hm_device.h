@@ -88,6 +88,13 @@ hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, co
 // clears the breakdown flags first (the first chunk of a factorisation).
 hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, bool init,
                                 int max_grid, hipStream_t st);
+// Clears the breakdown flags of one dataset before a batched factorisation.
+hipError_t launch_factor_init(const DevData& D, hipStream_t st);
+// One level of several datasets' factorisations in one launch: Ds (device
+// array of nseg DevData), seg (device, 2 nseg ints: the level's task range per
+// dataset), total = the number of tasks over all of them.
+hipError_t launch_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg, int32_t total, int max_grid,
+                              hipStream_t st);
 hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,
                         const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st);
 }  // namespace hm

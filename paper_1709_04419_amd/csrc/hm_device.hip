@@ -1751,26 +1751,49 @@ __global__ void __launch_bounds__(NT) k_factor(DevData D) {
 // have no dependencies among themselves, and all their predecessors belong to
 // earlier levels, completed by earlier launches.  Work-group w takes tasks
 // t0 + w, t0 + w + gridDim.x, ... of the level; it uses workspace slot w.
+// One task of the factorisation (shared by the level executors).
+__device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn, Smem& S) {
+  const Task tk = D.tasks[t];
+  const int32_t prog = D.task_prog[t];
+  int64_t ts = 0;
+  if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0; }
+  if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
+  if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
+  else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
+  else task_dense(D, tk, prog, dyn, S);
+  __syncthreads();
+  if (D.task_times && threadIdx.x == 0) {
+    D.task_times[7 * t] = ts;
+    D.task_times[7 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
+    for (int q = 0; q < 5; ++q) D.task_times[7 * t + 2 + q] = S.ph[q];
+  }
+  if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
+}
+
 __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
   double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
-  for (int32_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) {
-    const Task tk = D.tasks[t];
-    const int32_t prog = D.task_prog[t];
-    int64_t ts = 0;
-    if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0; }
-    if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
-    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
-    else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
-    else task_dense(D, tk, prog, dyn, S);
-    __syncthreads();
-    if (D.task_times && threadIdx.x == 0) {
-      D.task_times[7 * t] = ts;
-      D.task_times[7 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
-      for (int q = 0; q < 5; ++q) D.task_times[7 * t + 2 + q] = S.ph[q];
+  for (int32_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) run_task(D, t, slot, dyn, S);
+}
+
+// Level executor over several datasets: seg holds (t0, t1) of this level for
+// each of the nseg datasets; work-group w takes tasks w, w + grid, ... of their
+// concatenation, with workspace slot w (the datasets share one workspace).
+__global__ void __launch_bounds__(NT) k_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg,
+                                                    int32_t total) {
+  extern __shared__ double dyn[];
+  __shared__ Smem S;
+  for (int32_t idx = blockIdx.x; idx < total; idx += gridDim.x) {
+    int32_t s = 0, base = 0;
+    for (; s < nseg - 1; ++s) {
+      const int32_t len = seg[2 * s + 1] - seg[2 * s];
+      if (idx < base + len) break;
+      base += len;
     }
-    if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
+    const DevData& D = Ds[s];
+    double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+    run_task(D, seg[2 * s] + (idx - base), slot, dyn, S);
   }
 }
 
@@ -1915,6 +1938,26 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
     const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
     if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_init(const DevData& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg, int32_t total, int max_grid,
+                              hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_level_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_FACTOR * sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int g = total < max_grid ? total : max_grid;
+  if (g > 0)
+    hipLaunchKernelGGL(k_level_batch, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, Ds, seg, nseg, total);
   return hipGetLastError();
 }
 

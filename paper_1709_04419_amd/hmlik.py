@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -56,6 +57,8 @@ _sig = {
     "hm_factor": (C.c_int, [_P]),
     "hm_solve": (C.c_int, [_P, C.POINTER(hm_result)]),
     "hm_loglik": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx), C.POINTER(hm_result)]),
+    "hm_loglik_batch": (C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(hm_theta), C.POINTER(hm_approx),
+                                  C.POINTER(hm_result)]),
     "hm_dataset_info": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "hm_dataset_export_tree": (C.c_int, [_P, _P, _P, _P]),
     "hm_dataset_export_blocks": (C.c_int, [_P, _P, _P]),
@@ -106,9 +109,14 @@ class Context:
         _check(_lib.hm_ctx_create(int(device), C.c_void_p(raw) if raw else None, C.byref(h)),
                "hm_ctx_create")
         self._h = h
+        self._datasets = weakref.WeakSet()
 
     def close(self):
+        """Destroys the context, closing its datasets first (a dataset must not
+        outlive the context it was created in)."""
         if self._h:
+            for ds in list(self._datasets):
+                ds.close()
             _lib.hm_ctx_destroy(self._h)
             self._h = None
 
@@ -134,6 +142,7 @@ class Dataset:
                "hm_dataset_create")
         self._h = h
         self.r = 0
+        ctx._datasets.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -277,6 +286,33 @@ def test_truncate(ds: "Dataset", X, Y=None, eps=0.0, rank=0):
     Uo = np.asarray(U.reshape(-1, order="F")[:m * kk].reshape(kk, m).T)
     Vo = np.asarray(V.reshape(-1, order="F")[:n * kk].reshape(kk, n).T)
     return Uo, Vo, list(sec)
+
+
+def loglik_batch(ctx: "Context", datasets, thetas, nuggets, eps=0.0, rank=0):
+    """hm_loglik_batch: eq. (4) for several datasets in one call; dataset i at
+    thetas[i] with nuggets[i] and accuracy eps[i] / rank[i] (eps and rank may
+    also be single values).  Returns one result dict per dataset."""
+    m = len(datasets)
+    eps = list(eps) if np.ndim(eps) else [eps] * m
+    rank = list(rank) if np.ndim(rank) else [rank] * m
+    th = (hm_theta * m)()
+    ap = (hm_approx * m)()
+    hs = (_P * m)()
+    for i, ds in enumerate(datasets):
+        t, a = ds._args(thetas[i], nuggets[i], eps[i], rank[i])
+        th[i] = t
+        ap[i] = a
+        hs[i] = ds._h.value
+    total = sum(ds.r for ds in datasets)
+    out = (hm_result * total)()
+    s = _lib.hm_loglik_batch(ctx._h, m, hs, th, ap, out)
+    if s not in (HM_OK, HM_ERR_NOT_SPD):
+        raise HMError(s, "hm_loglik_batch")
+    res, off = [], 0
+    for ds in datasets:
+        res.append(_results(out[off:off + ds.r]))
+        off += ds.r
+    return res
 
 
 def _results(out):

@@ -245,3 +245,31 @@ def test_explicit_truncation_parity(H, ctx, m, n, eps, rk):
     opt = sv[k] if k < len(sv) else 0.0
     assert np.linalg.norm(M - U @ V.T, 2) <= opt * (1 + 1e-6) + 1e-13 * sv[0]
     ds.close()
+
+
+def test_loglik_batch_equals_single(H, ctx):
+    """hm_loglik_batch: datasets of different sizes, shapes and theta (one of
+    them breaking down) evaluated together give bitwise the results of
+    separate hm_loglik calls."""
+    specs = [(1500, ("uniform", 11), 32, (1.0, 0.1, 0.5), 1e-6, 1e-8, 0),
+             (1200, ("basin", 31), 64, (1.0, 0.1, 0.325), 1e-6, 1e-7, 0),
+             (784, ("grid", 7), 24, (2.0, 0.0334, 0.5), 1e-4, 1e-6, 0),
+             (1000, ("uniform", 22), 32, (1.0, 0.2, 1.5), 1e-6, 0.0, 5)]
+    single, dss = [], []
+    for n, (kind, seed), leaf, theta, nug, eps, k in specs:
+        P = wl.make_points(kind, n, seed)
+        ds = H.Dataset(ctx, P, leaf, 2.0)
+        ds.set_z(wl.standard_normal(n, 2, seed + 1))
+        single.append(ds.loglik(theta, nug, eps, k))
+        dss.append(ds)
+    try:
+        res = H.loglik_batch(ctx, dss, [s[3] for s in specs], [s[4] for s in specs], [s[5] for s in specs],
+                             [s[6] for s in specs])
+        assert single[3]["status"][0] == H.HM_ERR_NOT_SPD       # the fixed-rank case breaks down
+        for i, r in enumerate(res):
+            for key in ("loglik", "logdet", "quadform", "status", "fail_block", "fail_pivot", "max_rank"):
+                assert np.array_equal(r[key], single[i][key], equal_nan=key in ("loglik", "logdet", "quadform")), \
+                    (i, key)
+    finally:
+        for ds in dss:
+            ds.close()
