@@ -10,11 +10,13 @@ forward solve, log-determinant.  The data Z is a seeded standard-normal
 vector (the cost of an evaluation does not depend on Z).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu-baseline]
-                    [--calib-copy-gib G]
+                    [--no-tune] [--calib-copy-gib G]
 
 Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
 with the dataset (locations, trees, task schedule, Z) resident on the device
-before timing starts.
+before timing starts.  Before the timed steps, one untimed evaluation times
+every task and the level schedule is re-balanced from those times
+(hm_tune_schedule; results are unchanged); --no-tune skips it.
 
 roofline: the dominant kernel is the H-Cholesky executor k_level, launched once
 per dependency level of the task graph.  achieved = (algorithmic flops of one
@@ -103,7 +105,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the longest-path level schedule")
     ap.add_argument("--n", type=int, default=256000)
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,6 +134,12 @@ def main():
     info = ds.info()
     log(f"dataset n={n}: {info['nblocks']} blocks, {info['ntasks']} tasks, {info['nlevels']} levels, "
         f"set-up {t_setup:.2f} s")
+    t_tune = 0.0
+    if not args.no_tune:
+        s = time.perf_counter()
+        ds.tune_schedule(THETA, NUGGET, eps, 0)
+        t_tune = time.perf_counter() - s
+        log(f"schedule tuned from one timed evaluation: {t_tune:.2f} s")
     for w in range(args.warmup):
         s = time.perf_counter()
         ds.loglik(THETA, NUGGET, eps, 0)
@@ -183,10 +192,13 @@ def main():
                    "points": "basin_clusters(seed 31): 80% uniform in a non-convex basin, 20% in 10 clusters",
                    "theta": {"sigma2": THETA[0], "ell": THETA[1], "nu": THETA[2]}, "nugget": NUGGET,
                    "eps": eps, "leaf_size": LEAF, "eta": ETA, "precision": "fp64",
-                   "blocks": info["nblocks"], "tasks": info["ntasks"], "levels": launches},
+                   "blocks": info["nblocks"], "tasks": info["ntasks"], "levels": launches,
+                   "schedule": "longest-path levels" if args.no_tune else
+                               "levels re-balanced from one timed evaluation (untimed, before the steps)"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "phases_ms": {"assemble": float(np.mean(asm)) * 1e3, "factor": t_fac * 1e3,
-                      "solve": float(np.mean(sol)) * 1e3, "dataset_setup_host": t_setup * 1e3},
+                      "solve": float(np.mean(sol)) * 1e3, "dataset_setup_host": t_setup * 1e3,
+                      "schedule_tuning": t_tune * 1e3},
         "loglik": float(r["loglik"][0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_per_launch(n),

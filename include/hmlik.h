@@ -113,6 +113,17 @@ hm_status hm_solve(hm_dataset *ds, hm_result *out);
 /* hm_assemble + hm_factor + hm_solve. out has r entries. */
 hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, hm_result *out);
 
+/* Schedule tuning: runs one evaluation at theta (assembly and factorisation,
+ * with per-task timing), then re-assigns the factorisation's tasks to levels:
+ * sweeping backwards, a task moves to the latest level before its first
+ * dependent task whose longest task (as timed) is at least as long, so that it
+ * no longer sets the length of a level.  Later factorisations of the dataset,
+ * at any theta, use the new assignment; they run the same tasks on the same
+ * inputs, so results are bitwise unchanged.  Returns the evaluation's status
+ * (on HM_ERR_NOT_SPD the schedule is left as it was).  Allocates the timing
+ * records on first use. */
+hm_status hm_tune_schedule(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx);
+
 /* Batched evaluation of eq. (4) (Monte-Carlo replicates, several theta on
  * copies of one dataset, or unrelated datasets): dataset ds[i] is evaluated at
  * theta[i] and approx[i], i < m.  The assemblies are enqueued back to back and

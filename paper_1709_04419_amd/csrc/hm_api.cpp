@@ -10,6 +10,7 @@
 #include <cstring>
 #include <exception>
 #include <new>
+#include <set>
 #include <vector>
 
 #include "../../include/hmlik.h"
@@ -57,7 +58,10 @@ struct hm_dataset {
   int32_t fail_pivot = -1;
   double t_assemble = 0, t_factor = 0, t_solve = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<int32_t> level_begin;   // task index where each DAG level starts (+ end)
+  std::vector<int32_t> level_begin;   // position in `order` where each level starts (+ end)
+  std::vector<int32_t> order;         // execution order (task ids), level by level
+  int32_t* d_order = nullptr;
+  int64_t* tt_buf = nullptr;          // per-task timing records (allocated on first use)
 };
 
 namespace {
@@ -177,6 +181,8 @@ hm_status build_device(hm_dataset* ds) {
   TRY(upload(ds, P.terms, const_cast<TermDef**>(&D.terms)));
   TRY(upload(ds, P.insts, const_cast<TermInst**>(&D.insts)));
   TRY(upload(ds, P.tasks, const_cast<Task**>(&D.tasks)));
+  TRY(upload(ds, ds->order, &ds->d_order));
+  D.order = ds->d_order;
   TRY(upload(ds, P.deps, const_cast<int32_t**>(&D.deps)));
   TRY(upload(ds, P.task_prog, const_cast<int32_t**>(&D.task_prog)));
   D.ntasks = (int32_t)P.tasks.size();
@@ -230,6 +236,7 @@ hm_status build_device(hm_dataset* ds) {
   if (getenv("HMLIK_TASK_TIMES")) {
     TRY(dev_alloc(ds, sizeof(int64_t) * 7 * (P.tasks.size() + 1), &p));
     D.task_times = (int64_t*)p;
+    ds->tt_buf = D.task_times;
   }
   D.spin_limit = getenv("HMLIK_SPIN_LIMIT_S") ? (int64_t)(atof(getenv("HMLIK_SPIN_LIMIT_S")) * 1e8) : 3000000000LL;  // 100 MHz counter; 30 s default
   return HM_OK;
@@ -302,6 +309,8 @@ hm_status hm_dataset_create(hm_ctx* ctx, const double* coords, int64_t n, const 
   }
   {
     const auto& tasks = ds->plan.tasks;
+    ds->order.resize(tasks.size());
+    for (size_t i = 0; i < tasks.size(); ++i) ds->order[i] = (int32_t)i;
     ds->level_begin.clear();
     int32_t cur = -1;
     for (int32_t i = 0; i < (int32_t)tasks.size(); ++i)
@@ -419,7 +428,7 @@ static hm_status finish_factor(hm_dataset* ds) {
   unsigned long long key = 0;
   HIPTRY(hipMemcpy(&flags[0], D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(&key, D.fail_key, sizeof(key), hipMemcpyDeviceToHost));
-  if (D.task_times) {
+  if (D.task_times && getenv("HMLIK_TASK_TIMES")) {
     const char* path = getenv("HMLIK_TASK_TIMES");
     std::vector<int64_t> tt(7 * ds->plan.tasks.size());
     if (hipMemcpy(tt.data(), D.task_times, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost) == hipSuccess) {
@@ -638,6 +647,82 @@ hm_status hm_loglik_batch(hm_ctx* ctx, int32_t m, hm_dataset* const* ds, const h
     off += (size_t)ds[i]->r;
   }
   return any;
+}
+
+// Re-assigns tasks to levels.  Starting from the longest-path levels and
+// sweeping from the last task to the first, a task moves to the latest level
+// before its earliest successor (at most `horizon` levels on) whose longest
+// task, by the measured durations, is at least as long as it: it then no longer
+// sets the duration of a level.  Every dependency stays in an earlier level and
+// the number of levels does not change.
+static void relevel(const Plan& P, const std::vector<double>& dur, int32_t horizon, std::vector<int32_t>& lev) {
+  const int32_t nt = (int32_t)P.tasks.size();
+  lev.resize(nt);
+  int32_t L = 0;
+  for (int32_t t = 0; t < nt; ++t) {
+    lev[t] = P.tasks[t].level;
+    L = std::max(L, lev[t] + 1);
+  }
+  std::vector<int32_t> sbeg(nt + 1, 0), succ(P.deps.size());
+  for (int32_t t = 0; t < nt; ++t)
+    for (int32_t q = 0; q < P.tasks[t].ndeps; ++q) ++sbeg[P.deps[P.tasks[t].dep_begin + q] + 1];
+  for (int32_t t = 0; t < nt; ++t) sbeg[t + 1] += sbeg[t];
+  {
+    std::vector<int32_t> fill(sbeg.begin(), sbeg.end() - 1);
+    for (int32_t t = 0; t < nt; ++t)
+      for (int32_t q = 0; q < P.tasks[t].ndeps; ++q) succ[fill[P.deps[P.tasks[t].dep_begin + q]]++] = t;
+  }
+  std::vector<std::multiset<double>> at(L);
+  for (int32_t t = 0; t < nt; ++t) at[lev[t]].insert(dur[t]);
+  for (int32_t t = nt - 1; t >= 0; --t) {
+    int32_t hi = L - 1;
+    for (int32_t q = sbeg[t]; q < sbeg[t + 1]; ++q) hi = std::min(hi, lev[succ[q]] - 1);
+    const int32_t l0 = lev[t];
+    for (int32_t l = std::min(hi, l0 + horizon); l > l0; --l) {
+      if (!at[l].empty() && *at[l].rbegin() >= dur[t]) {
+        at[l0].erase(at[l0].find(dur[t]));
+        at[l].insert(dur[t]);
+        lev[t] = l;
+        break;
+      }
+    }
+  }
+}
+
+hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_approx* approx) {
+  if (!ds || ds->r < 1) return HM_ERR_ARG;
+  TRY(check_theta_approx(theta, approx));
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  const int32_t nt = (int32_t)ds->plan.tasks.size();
+  if (!ds->tt_buf) {
+    void* p = nullptr;
+    TRY(dev_alloc(ds, sizeof(int64_t) * 7 * ((size_t)nt + 1), &p));
+    ds->tt_buf = (int64_t*)p;
+  }
+  int64_t* saved = ds->D.task_times;
+  ds->D.task_times = ds->tt_buf;
+  hm_status s = hm_assemble(ds, theta, approx);
+  if (s == HM_OK) s = hm_factor(ds);
+  ds->D.task_times = saved;
+  if (s != HM_OK) return s;
+  std::vector<int64_t> tt(7 * (size_t)nt);
+  HIPTRY(hipMemcpy(tt.data(), ds->tt_buf, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost));
+  std::vector<double> dur(nt);
+  for (int32_t t = 0; t < nt; ++t) dur[t] = (double)(tt[7 * (size_t)t + 1] - tt[7 * (size_t)t]);
+  std::vector<int32_t> lev;
+  relevel(ds->plan, dur, 512, lev);
+  // counting sort of the task ids by level (stable)
+  int32_t L = 0;
+  for (int32_t v : lev) L = std::max(L, v + 1);
+  std::vector<int32_t> cnt(L + 1, 0);
+  for (int32_t v : lev) ++cnt[v + 1];
+  for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
+  ds->level_begin.assign(cnt.begin(), cnt.end());
+  std::vector<int32_t> order(nt);
+  for (int32_t t = 0; t < nt; ++t) order[cnt[lev[t]]++] = t;
+  ds->order = order;
+  HIPTRY(hipMemcpy(ds->d_order, ds->order.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+  return HM_OK;
 }
 
 hm_status hm_dataset_info(const hm_dataset* ds, int64_t* n, int64_t* nclusters, int64_t* nblocks,

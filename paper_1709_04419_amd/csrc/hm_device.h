@@ -39,6 +39,7 @@ struct DevData {
   const TermInst* insts;
   // schedule
   const Task* tasks;
+  const int32_t* order;       // execution order of the tasks, level by level
   const int32_t* deps;
   int32_t ntasks;
   int32_t* ticket;

@@ -1747,10 +1747,6 @@ __global__ void __launch_bounds__(NT) k_factor(DevData D) {
   }
 }
 
-// Level-synchronous executor: the tasks of one DAG level (longest-path depth)
-// have no dependencies among themselves, and all their predecessors belong to
-// earlier levels, completed by earlier launches.  Work-group w takes tasks
-// t0 + w, t0 + w + gridDim.x, ... of the level; it uses workspace slot w.
 // One task of the factorisation (shared by the level executors).
 __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn, Smem& S) {
   const Task tk = D.tasks[t];
@@ -1770,11 +1766,15 @@ __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn,
   if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
 }
 
+// Level-synchronous executor: the tasks of one level have no dependencies
+// among themselves, and all their predecessors belong to earlier levels,
+// completed by earlier launches.  Work-group w takes tasks order[t0 + w],
+// order[t0 + w + gridDim.x], ... of the level; it uses workspace slot w.
 __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
   double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
-  for (int32_t t = t0 + blockIdx.x; t < t1; t += gridDim.x) run_task(D, t, slot, dyn, S);
+  for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) run_task(D, D.order[q], slot, dyn, S);
 }
 
 // Level executor over several datasets: seg holds (t0, t1) of this level for
@@ -1793,7 +1793,7 @@ __global__ void __launch_bounds__(NT) k_level_batch(const DevData* Ds, const int
     }
     const DevData& D = Ds[s];
     double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
-    run_task(D, seg[2 * s] + (idx - base), slot, dyn, S);
+    run_task(D, D.order[seg[2 * s] + (idx - base)], slot, dyn, S);
   }
 }
 

@@ -57,6 +57,7 @@ _sig = {
     "hm_factor": (C.c_int, [_P]),
     "hm_solve": (C.c_int, [_P, C.POINTER(hm_result)]),
     "hm_loglik": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx), C.POINTER(hm_result)]),
+    "hm_tune_schedule": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx)]),
     "hm_loglik_batch": (C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(hm_theta), C.POINTER(hm_approx),
                                   C.POINTER(hm_result)]),
     "hm_dataset_info": (C.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -207,6 +208,15 @@ class Dataset:
         if s not in (HM_OK, HM_ERR_NOT_SPD):
             raise HMError(s, "hm_loglik")
         return _results(out)
+
+    def tune_schedule(self, theta, nugget, eps=0.0, rank=0) -> int:
+        """hm_tune_schedule: one timed evaluation, then the level assignment of
+        the factorisation's tasks is re-balanced (results unchanged)."""
+        th, ap = self._args(theta, nugget, eps, rank)
+        s = _lib.hm_tune_schedule(self._h, C.byref(th), C.byref(ap))
+        if s not in (HM_OK, HM_ERR_NOT_SPD):
+            raise HMError(s, "hm_tune_schedule")
+        return s
 
     def info(self):
         vals = [C.c_int64() for _ in range(5)]

@@ -273,3 +273,31 @@ def test_loglik_batch_equals_single(H, ctx):
     finally:
         for ds in dss:
             ds.close()
+
+
+def test_tuned_schedule_same_results(H, ctx):
+    """hm_tune_schedule re-balances the factorisation's levels; the results of
+    later evaluations (other theta too, alone and batched) stay bitwise equal,
+    and still match the oracle."""
+    n = 3000
+    P = wl.basin_clusters(n, 31)
+    Z = wl.standard_normal(n, 1, 32)
+    theta, nug, eps = (1.0, 0.1, 0.325), 1e-6, 1e-7
+    ds = H.Dataset(ctx, P, 32, 2.0)
+    ds2 = H.Dataset(ctx, wl.uniform_square(1500, 11), 32, 2.0)
+    try:
+        ds.set_z(Z)
+        ds2.set_z(wl.standard_normal(1500, 1, 12))
+        before = [ds.loglik(theta, nug, eps, 0), ds.loglik((1.2, 0.08, 0.5), nug, eps, 0)]
+        assert ds.tune_schedule(theta, nug, eps, 0) == H.HM_OK
+        after = [ds.loglik(theta, nug, eps, 0), ds.loglik((1.2, 0.08, 0.5), nug, eps, 0)]
+        for b, a in zip(before, after):
+            for key in ("loglik", "logdet", "quadform", "max_rank"):
+                assert np.array_equal(a[key], b[key]), key
+        o = HLikelihood(P, 32, 2.0).loglik(theta, nug, Z, eps, 0)
+        np.testing.assert_allclose(after[0]["loglik"], o["loglik"], rtol=REL, atol=0)
+        res = H.loglik_batch(ctx, [ds, ds2], [theta, (1.0, 0.1, 0.5)], [nug, nug], [eps, 1e-8], [0, 0])
+        assert np.array_equal(res[0]["loglik"], after[0]["loglik"])
+    finally:
+        ds.close()
+        ds2.close()
