@@ -118,26 +118,32 @@ class HLikelihood:
         self.stats = Stats()
         self.D, self.U, self.V = {}, {}, {}
         self.pending = {}
-        Pp = self.Pp
-        kmax = kfix if kfix > 0 else K_MAX
         for i, b in enumerate(self.bt.blocks):
             if b.kind == NODE:
                 continue
             self.pending[i] = []
-            r0, r1 = self.rng_r[i]
-            c0, c1 = self.rng_c[i]
-            rows = np.arange(r0, r1)
-            cols = np.arange(c0, c1)
             if b.kind == DENSE:
-                self.D[i] = covariance_block(Pp, rows, cols, theta, nugget)
+                self.D[i] = self.assemble_block(i, theta, nugget, eps, kfix)
             else:
-                row_fn = lambda li, rows=rows, cols=cols: covariance_block(
-                    Pp, rows[li:li + 1], cols, theta, 0.0)[0]
-                col_fn = lambda lj, rows=rows, cols=cols: covariance_block(
-                    Pp, rows, cols[lj:lj + 1], theta, 0.0)[:, 0]
-                U, V = aca(row_fn, col_fn, r1 - r0, c1 - c0, eps, kmax)
-                self.stats.aca_ranks.append(U.shape[1])
-                self.U[i], self.V[i] = truncate(U, V, eps, kfix)
+                self.U[i], self.V[i] = self.assemble_block(i, theta, nugget, eps, kfix)
+
+    def assemble_block(self, i, theta, nugget, eps, kfix):
+        """One leaf of C~: the dense block (entries of eq. 2 plus the nugget on
+        the diagonal), or (U, V) of a low-rank block by ACA + TRUNCATE."""
+        b = self.bt.blocks[i]
+        r0, r1 = self.rng_r[i]
+        c0, c1 = self.rng_c[i]
+        rows = np.arange(r0, r1)
+        cols = np.arange(c0, c1)
+        Pp = self.Pp
+        if b.kind == DENSE:
+            return covariance_block(Pp, rows, cols, theta, nugget)
+        row_fn = lambda li: covariance_block(Pp, rows[li:li + 1], cols, theta, 0.0)[0]
+        col_fn = lambda lj: covariance_block(Pp, rows, cols[lj:lj + 1], theta, 0.0)[:, 0]
+        U, V = aca(row_fn, col_fn, r1 - r0, c1 - c0, eps, kfix if kfix > 0 else K_MAX)
+        if getattr(self, "stats", None) is not None:
+            self.stats.aca_ranks.append(U.shape[1])
+        return truncate(U, V, eps, kfix)
 
     def to_dense(self):
         """Explicit matrix of the current H representation (lower blocks
