@@ -11,6 +11,7 @@ vector (the cost of an evaluation does not depend on Z).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu-baseline]
                     [--no-tune] [--calib-copy-gib G]
+    python bench.py --form served [--datasets D] [--requests R] [--max-active A] [--n N]
 
 Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
 with the dataset (locations, trees, task schedule, Z) resident on the device
@@ -32,6 +33,14 @@ same workload and scales it to n by n log^2 n.
 
 --calib-copy-gib G adds one plain device copy of G GiB after the timed steps
 (outside the timed region), the reference kernel for HBM counter calibration.
+
+--form served measures the request server instead: D resident datasets of the
+same generator (seeds 31, 41, ...), each with its schedule tuned (untimed), and
+R requests submitted at once, round-robin over the datasets, at theta values
+perturbed around the workload's theta as a Nelder-Mead simplex would be (seeded).
+The server batches up to A requests (one level launch advances each of them).
+value = completed evaluations / wall time from the first submission to the last
+result; latency percentiles are per request (submission to result).
 """
 from __future__ import annotations
 
@@ -111,11 +120,18 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
+    ap.add_argument("--form", choices=("plain", "served"), default="plain")
+    ap.add_argument("--datasets", type=int, default=2)
+    ap.add_argument("--requests", type=int, default=4)
+    ap.add_argument("--max-active", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the evaluation is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
+
+    if args.form == "served":
+        return served(args)
 
     import numpy as np
     import torch
@@ -210,6 +226,78 @@ def main():
         log("timing the oracle sample on the host")
         out["cpu_baseline"] = cpu_baseline(n, eps)
     ds.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def served(args):
+    """The served form: continuous batching of evaluations over resident datasets."""
+    import numpy as np
+
+    from paper_1709_04419_amd import hmlik
+    from paper_1709_04419_amd import workloads as wl
+
+    n, eps = args.n, args.eps
+    ctx = hmlik.Context(0)
+    dss = []
+    for i in range(args.datasets):
+        ds = hmlik.Dataset(ctx, wl.basin_clusters(n, 31 + 10 * i), LEAF, ETA)
+        ds.set_z(wl.standard_normal(n, 1, 32 + 10 * i))
+        if not args.no_tune:
+            s = time.perf_counter()
+            ds.tune_schedule(THETA, NUGGET, eps, 0)
+            log(f"dataset {i}: schedule tuned ({time.perf_counter() - s:.1f} s)")
+        dss.append(ds)
+    info = dss[0].info()
+    rng = np.random.default_rng(5200)
+    base = np.log(np.array(THETA))
+    thetas = [tuple(np.exp(base + rng.uniform(-0.1, 0.1, 3))) for _ in range(args.requests)]
+    sv = hmlik.Server(ctx, max_active=args.max_active)
+    t0 = time.perf_counter()
+    tickets = [sv.submit(dss[j % args.datasets], thetas[j], NUGGET, eps, 0) for j in range(args.requests)]
+    res = []
+    for j, t in enumerate(tickets):
+        r = sv.poll(t, wait=True)
+        res.append(r)
+        log(f"request {j + 1}/{args.requests}: status {r['request_status']}, latency {r['t_latency']:.1f} s, "
+            f"peak batch {r['peak_batch']}")
+    wall = time.perf_counter() - t0
+    sv.close()
+    flops = sum(ds.factor_flops() for ds in dss) * args.requests / args.datasets
+    done = sum(1 for r in res if r["request_status"] in (hmlik.HM_OK, hmlik.HM_ERR_NOT_SPD))
+    lat = np.array([r["t_latency"] for r in res]) * 1e3
+    achieved = flops / wall / 1e12
+    out = {
+        "metric": METRIC,
+        "value": done / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": wall / args.requests * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "form": "served",
+        "config": {"workload": ("basin256k" if n == 256000 else f"basin{n}") + "_served", "n": n,
+                   "datasets": args.datasets, "requests": args.requests, "max_active": args.max_active,
+                   "points": "basin_clusters(seeds 31, 41, ...)", "eps": eps, "leaf_size": LEAF, "eta": ETA,
+                   "theta": "exp(log(1, 0.1, 0.325) + U(-0.1, 0.1)^3), seed 5200", "nugget": NUGGET,
+                   "blocks": info["nblocks"], "tasks": info["ntasks"],
+                   "schedule": "longest-path levels" if args.no_tune else "levels tuned per dataset (untimed)"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "requests": [{"latency_s": r["t_latency"], "queue_s": r["t_queue"], "steps": r["steps"],
+                      "peak_batch": r["peak_batch"], "status": r["request_status"],
+                      "loglik": float(r["loglik"][0])} for r in res],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_level_batch (whole-run average: algorithmic flops of all factorisations "
+                               "/ wall time)"},
+    }
+    for ds in dss:
+        ds.close()
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -20,7 +20,11 @@
  *   - All arithmetic is FP64.  Results are deterministic: the same inputs give
  *     bitwise-equal outputs.
  *   - Calls on one dataset must not overlap; different datasets may be used
- *     from different threads only with different contexts.
+ *     from different threads only with different contexts.  While a request
+ *     server (hm_server_*) exists on a context, it alone issues that context's
+ *     device work: the evaluation, set-up and readback calls on the context
+ *     and its datasets return HM_ERR_BUSY (the introspection calls
+ *     hm_dataset_info, _export_tree, _export_blocks and _footprint still work).
  */
 #ifndef HMLIK_H
 #define HMLIK_H
@@ -39,11 +43,14 @@ typedef enum {
                            accuracy, Tables 6 and 7); outputs are NaN, fail_block/fail_pivot set */
   HM_ERR_OOM = 3,       /* device allocation failed */
   HM_ERR_DEVICE = 4,    /* a HIP runtime call failed */
-  HM_ERR_INTERNAL = 5   /* the task executor aborted (bounded wait exceeded) */
+  HM_ERR_INTERNAL = 5,  /* the task executor aborted (bounded wait exceeded) */
+  HM_ERR_CANCELLED = 6, /* the request was cancelled before it finished */
+  HM_ERR_BUSY = 7       /* a request server owns the context (see Conventions) */
 } hm_status;
 
 typedef struct hm_ctx hm_ctx;
 typedef struct hm_dataset hm_dataset;
+typedef struct hm_server hm_server;
 
 /* theta = (sigma^2, ell, nu) of eq. (2) and the nugget tau^2. */
 typedef struct {
@@ -84,7 +91,8 @@ typedef struct {
  * context owns the work-group workspace its datasets share (grown, with a
  * synchronisation, when a dataset that needs more is created). */
 hm_status hm_ctx_create(int device, void *stream, hm_ctx **out);
-/* Destroy every dataset of a context before the context itself. */
+/* Destroy every dataset of a context before the context itself.  A server
+ * still running on the context is destroyed first (hm_server_destroy). */
 void hm_ctx_destroy(hm_ctx *ctx);
 
 /* Build the cluster tree and block cluster tree for n locations (App. B,
@@ -92,7 +100,25 @@ void hm_ctx_destroy(hm_ctx *ctx);
  * them.  coords: host pointer, n x 2 row-major, finite. */
 hm_status hm_dataset_create(hm_ctx *ctx, const double *coords, int64_t n, const hm_tree_opts *opts,
                             hm_dataset **out);
+/* Frees all of the dataset's device memory.  If a server runs on its context,
+ * the server's queued requests on ds are cancelled and the call waits until
+ * none of them is on the device. */
 void hm_dataset_destroy(hm_dataset *ds);
+
+/* Device memory of a dataset.  resident_bytes: trees, schedule, Z and the
+ * small per-evaluation arrays, held from creation to destruction.
+ * factor_bytes: the factor storage (dense leaves, low-rank factors U, V at
+ * rank cap 64, update-term buffers) that the evaluations assemble C~ into and
+ * factorise in place; *attached says whether it is currently allocated.  Any
+ * pointer may be NULL. */
+hm_status hm_dataset_footprint(const hm_dataset *ds, int64_t *resident_bytes, int64_t *factor_bytes,
+                               int32_t *attached);
+
+/* Frees the factor storage (the last matrix and factor are lost; hm_get_block
+ * then returns HM_ERR_ARG).  The next evaluation allocates it again
+ * (HM_ERR_OOM if that fails).  Lets many datasets stay resident with only the
+ * factor storage of those being evaluated allocated. */
+hm_status hm_dataset_release(hm_dataset *ds);
 
 /* Data Z: n x r column-major in input (not permuted) order, 1 <= r <= 64.
  * on_device != 0: Z is a device pointer read in stream order during this call. */
@@ -188,6 +214,75 @@ hm_status hm_get_term(hm_dataset *ds, int64_t term, double *data, int32_t *kind,
  * workspace (HM_ERR_ARG if the matrices do not fit in one slot of it). */
 hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const double *Y, int64_t n, int32_t r,
                            double eps, int32_t fixed_rank, double *U, double *V, int32_t *k, double *seconds);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A request server evaluates eq. (4) for a stream of requests (dataset, theta,
+ * accuracy) on resident datasets of one context, with continuous batching: a
+ * worker thread runs the H-Cholesky of every admitted request together, one
+ * kernel launch per step that advances each of them by one dependency level
+ * of its own task graph, and admits newly arrived requests between steps (an
+ * admitted request is assembled and joins at its first level while the
+ * others continue).  Its forward solve then runs on a second stream, beside
+ * the next steps.  Each request gets bitwise the result of hm_loglik alone.
+ *
+ * Admission, in arrival order, takes a request when a batch slot is free, no
+ * other admitted request uses its dataset (requests on one dataset run in
+ * arrival order), and its dataset's factor storage fits the HBM budget: the
+ * factor storage attached over all datasets of the context, plus what the
+ * request needs if its dataset has none attached, must stay within
+ * hbm_budget bytes.  To make room, the server releases the factor storage of
+ * datasets that no admitted request uses, least recently used first.  A
+ * request that cannot get room waits, and so do the requests after it (no
+ * later request overtakes a request held back for memory).
+ */
+typedef struct {
+  int32_t max_active; /* requests batched together, 1..64 */
+  int64_t hbm_budget; /* bytes of attached factor storage over the context's datasets; 0 = no limit */
+} hm_server_opts;
+
+/* Per-request timing and batching record. */
+typedef struct {
+  double t_queue;      /* seconds from submission to admission (host clock) */
+  double t_latency;    /* seconds from submission to the result being ready (host clock) */
+  int32_t steps;       /* level steps the request's factorisation took part in */
+  int32_t peak_batch;  /* largest number of requests in one of those steps */
+} hm_request_stats;
+
+/* Starts a server (worker thread and two streams of default priority) on ctx.
+ * The context's datasets must already exist: dataset creation is refused
+ * while the server runs.  HM_ERR_ARG if ctx has no dataset or the options are
+ * out of range; HM_ERR_BUSY if ctx already has a server.  Allocates its
+ * per-slot tables, pinned staging buffers and one workspace slot for the
+ * solve stream. */
+hm_status hm_server_create(hm_ctx *ctx, const hm_server_opts *opts, hm_server **out);
+
+/* Queues the evaluation of ds (with its current Z) at theta and approx;
+ * *ticket identifies it.  HM_ERR_ARG for invalid theta/approx, a dataset of
+ * another context or one without Z; HM_ERR_OOM if the dataset's factor storage
+ * alone exceeds the budget; HM_ERR_DEVICE after a device failure of the
+ * server.  Thread-safe. */
+hm_status hm_server_submit(hm_server *sv, hm_dataset *ds, const hm_theta *theta, const hm_approx *approx,
+                           uint64_t *ticket);
+
+/* Result of a request.  wait != 0 blocks until it is ready.  When ready,
+ * *done = 1, out receives r results (r = columns of the dataset's Z at
+ * submission), stats (may be NULL) its record, the ticket is retired, and the
+ * request's status is returned (HM_OK, HM_ERR_NOT_SPD, HM_ERR_CANCELLED,
+ * HM_ERR_DEVICE, ...).  When not ready (wait == 0), *done = 0 and HM_OK.
+ * HM_ERR_ARG for an unknown or retired ticket.  Thread-safe. */
+hm_status hm_server_poll(hm_server *sv, uint64_t ticket, int32_t wait, hm_result *out, hm_request_stats *stats,
+                         int32_t *done);
+
+/* Cancels a request: a queued one at once, an admitted one before its next
+ * level step (one whose solve has started finishes it).  Its poll then
+ * returns HM_ERR_CANCELLED.  HM_ERR_ARG for an unknown ticket, HM_OK (no
+ * effect) if it already finished.  Thread-safe. */
+hm_status hm_server_cancel(hm_server *sv, uint64_t ticket);
+
+/* Cancels queued requests, lets admitted ones finish, joins the worker and
+ * frees the server; the context's direct entry points work again. */
+void hm_server_destroy(hm_server *sv);
 
 const char *hm_status_string(hm_status s);
 

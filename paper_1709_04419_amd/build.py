@@ -44,6 +44,11 @@ def build_library(verbose: bool = False) -> str:
     _run([HIPCC, "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", *inc, "-c",
           os.path.join(CSRC, "hm_api.cpp"), "-o", o])
     objs.append(o)
+    # request server
+    o = os.path.join(BUILD, "hm_server.o")
+    _run([HIPCC, "-O2", "-std=c++17", "-fPIC", *inc, "-c",
+          os.path.join(CSRC, "hm_server.cpp"), "-o", o])
+    objs.append(o)
     # device kernels
     o = os.path.join(BUILD, "hm_device.o")
     _run([HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", *inc,
@@ -51,7 +56,7 @@ def build_library(verbose: bool = False) -> str:
           "-c", os.path.join(CSRC, "hm_device.hip"), "-o", o])
     objs.append(o)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

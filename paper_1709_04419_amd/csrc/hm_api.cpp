@@ -15,54 +15,11 @@
 
 #include "../../include/hmlik.h"
 #include "hm_device.h"
+#include "hm_internal.h"
 #include "hm_plan.h"
 
 using namespace hm;
-
-struct hm_ctx {
-  int device;
-  hipStream_t stream;
-  // workspace slots shared by the context's datasets (evaluations on one
-  // context are ordered on its stream); grown when a dataset needs more
-  double* ws = nullptr;
-  int64_t ws_stride = 0;
-};
-
-namespace {
-
-constexpr int NSLOTS = 512;   // workspace slots (ACA kernel work-groups)
-constexpr int NEXEC = 256;    // executor work-groups: one per CU (LDS arena of ~140 KB each)
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
-}  // namespace
-
-struct hm_dataset {
-  hm_ctx* ctx = nullptr;
-  Tree tree;
-  Plan plan;
-  std::vector<DevBuf> bufs;
-  DevData D{};
-  int64_t* d_perm = nullptr;
-  int32_t* d_diag_ids = nullptr;
-  double* d_Z = nullptr;
-  double* d_W = nullptr;
-  double* d_out = nullptr;
-  int32_t r = 0;
-  bool assembled = false, factored = false;
-  hm_status factor_status = HM_OK;
-  int64_t fail_block = -1;
-  int32_t fail_pivot = -1;
-  double t_assemble = 0, t_factor = 0, t_solve = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<int32_t> level_begin;   // position in `order` where each level starts (+ end)
-  std::vector<int32_t> order;         // execution order (task ids), level by level
-  int32_t* d_order = nullptr;
-  int64_t* tt_buf = nullptr;          // per-task timing records (allocated on first use)
-};
+using namespace hm_int;
 
 namespace {
 
@@ -149,11 +106,64 @@ MaternConst make_matern(const hm_theta& th) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// While a request server runs on a context it alone issues the context's
+// device work; the direct entry points then return HM_ERR_BUSY.
+bool busy(const hm_ctx* c) { return c->server.load() != nullptr; }
+
 // The dataset's kernels use the context's current workspace.
 void use_ctx_ws(hm_dataset* ds) {
   ds->D.ws = ds->ctx->ws;
   ds->D.ws_stride = ds->ctx->ws_stride;
 }
+
+// Carves the factor storage at `base` into the dense-leaf pool, the low-rank
+// factor pool and the update-term pool (each 256-byte aligned); returns its
+// size in bytes.  With base == nullptr only the size is computed.
+size_t store_layout(const Plan& P, void* base, DevData& D) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t a = up(sizeof(double) * (size_t)P.dense_pool);
+  const size_t b = up(sizeof(double) * (size_t)P.lr_pool);
+  const size_t c = up(sizeof(double) * (size_t)P.term_pool);
+  if (base) {
+    char* q = static_cast<char*>(base);
+    D.dense = (double*)q;
+    D.lr = (double*)(q + a);
+    D.termbuf = (double*)(q + a + b);
+  } else {
+    D.dense = D.lr = D.termbuf = nullptr;
+  }
+  return a + b + c + 256;
+}
+
+}  // namespace
+
+namespace hm_int {
+
+hm_status attach_store(hm_dataset* ds) {
+  if (ds->store) return HM_OK;
+  void* p = nullptr;
+  if (hipMalloc(&p, ds->store_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return HM_ERR_OOM;
+  }
+  ds->store = p;
+  store_layout(ds->plan, p, ds->D);
+  return HM_OK;
+}
+
+void release_store(hm_dataset* ds) {
+  if (!ds->store) return;
+  (void)hipSetDevice(ds->ctx->device);
+  (void)hipStreamSynchronize(ds->ctx->stream);
+  (void)hipFree(ds->store);
+  ds->store = nullptr;
+  store_layout(ds->plan, nullptr, ds->D);
+  ds->assembled = ds->factored = false;
+}
+
+}  // namespace hm_int
+
+namespace {
 
 hm_status build_device(hm_dataset* ds) {
   const Tree& T = ds->tree;
@@ -166,18 +176,14 @@ hm_status build_device(hm_dataset* ds) {
   TRY(upload(ds, T.diag_of, const_cast<int32_t**>(&D.diag_of)));
   D.nblocks = (int32_t)T.bk.size();
   void* p;
-  TRY(dev_alloc(ds, sizeof(double) * P.dense_pool, &p));
-  D.dense = (double*)p;
   TRY(upload(ds, P.dense_off, const_cast<int64_t**>(&D.dense_off)));
-  TRY(dev_alloc(ds, sizeof(double) * P.lr_pool, &p));
-  D.lr = (double*)p;
   TRY(upload(ds, P.lr_off, const_cast<int64_t**>(&D.lr_off)));
   {
     std::vector<int32_t> rk(T.bk.size(), 0);
     TRY(upload(ds, rk, &D.rank));
   }
-  TRY(dev_alloc(ds, sizeof(double) * P.term_pool, &p));
-  D.termbuf = (double*)p;
+  ds->store_bytes = store_layout(P, nullptr, D);
+  TRY(attach_store(ds));
   TRY(upload(ds, P.terms, const_cast<TermDef**>(&D.terms)));
   TRY(upload(ds, P.insts, const_cast<TermInst**>(&D.insts)));
   TRY(upload(ds, P.tasks, const_cast<Task**>(&D.tasks)));
@@ -254,6 +260,8 @@ const char* hm_status_string(hm_status s) {
     case HM_ERR_OOM: return "device out of memory";
     case HM_ERR_DEVICE: return "HIP runtime error";
     case HM_ERR_INTERNAL: return "task executor aborted";
+    case HM_ERR_CANCELLED: return "request cancelled";
+    case HM_ERR_BUSY: return "a request server owns this context";
   }
   return "unknown status";
 }
@@ -277,6 +285,7 @@ hm_status hm_ctx_create(int device, void* stream, hm_ctx** out) {
 
 void hm_ctx_destroy(hm_ctx* ctx) {
   if (!ctx) return;
+  if (hm_server* sv = ctx->server.load()) hm_server_destroy(sv);
   if (ctx->ws) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
@@ -289,6 +298,7 @@ hm_status hm_dataset_create(hm_ctx* ctx, const double* coords, int64_t n, const 
                             hm_dataset** out) {
   if (!ctx || !coords || !opts || !out || n < 1) return HM_ERR_ARG;
   *out = nullptr;
+  if (busy(ctx)) return HM_ERR_BUSY;
   if (opts->leaf_size < 1 || opts->leaf_size > LEAF_MAX) return HM_ERR_ARG;
   if (!std::isfinite(opts->eta) || opts->eta < 0.0) return HM_ERR_ARG;
   for (int64_t i = 0; i < 2 * n; ++i)
@@ -342,22 +352,47 @@ hm_status hm_dataset_create(hm_ctx* ctx, const double* coords, int64_t n, const 
     hm_dataset_destroy(ds);
     return s;
   }
+  ctx->datasets.insert(ds);
   *out = ds;
   return HM_OK;
 }
 
 void hm_dataset_destroy(hm_dataset* ds) {
   if (!ds) return;
+  if (hm_server* sv = ds->ctx->server.load()) server_forget_dataset(sv, ds);
   (void)hipSetDevice(ds->ctx->device);
   (void)hipStreamSynchronize(ds->ctx->stream);
   for (auto& b : ds->bufs) (void)hipFree(b.p);
+  if (ds->store) (void)hipFree(ds->store);
   for (int i = 0; i < 4; ++i)
     if (ds->ev[i]) (void)hipEventDestroy(ds->ev[i]);
+  ds->ctx->datasets.erase(ds);
   delete ds;
+}
+
+hm_status hm_dataset_release(hm_dataset* ds) {
+  if (!ds) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  release_store(ds);
+  return HM_OK;
+}
+
+hm_status hm_dataset_footprint(const hm_dataset* ds, int64_t* resident_bytes, int64_t* factor_bytes,
+                               int32_t* attached) {
+  if (!ds) return HM_ERR_ARG;
+  if (resident_bytes) {
+    int64_t s = 0;
+    for (const auto& b : ds->bufs) s += (int64_t)b.bytes;
+    *resident_bytes = s;
+  }
+  if (factor_bytes) *factor_bytes = (int64_t)ds->store_bytes;
+  if (attached) *attached = ds->store != nullptr;
+  return HM_OK;
 }
 
 hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t on_device) {
   if (!ds || !Z || r < 1 || r > 64) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   HIPTRY(hipSetDevice(ds->ctx->device));
   const int64_t n = ds->tree.n;
   if (r > ds->r) {
@@ -380,7 +415,11 @@ hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t o
   return HM_OK;
 }
 
-static hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
+}  // extern "C"
+
+namespace hm_int {
+
+hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
   if (!th || !ap) return HM_ERR_ARG;
   if (!finite_pos(th->sigma2) || !finite_pos(th->ell) || !finite_pos(th->nu)) return HM_ERR_ARG;
   if (!std::isfinite(th->nugget) || th->nugget < 0.0) return HM_ERR_ARG;
@@ -391,18 +430,16 @@ static hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
   return HM_OK;
 }
 
-// Sets theta and the accuracy and enqueues the assembly, bracketed by ev[0],
-// ev[1] (no synchronisation).
-static hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
+hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st) {
   TRY(check_theta_approx(th, ap));
   HIPTRY(hipSetDevice(ds->ctx->device));
+  TRY(attach_store(ds));
   use_ctx_ws(ds);
   DevData& D = ds->D;
   D.mc = make_matern(*th);
   D.kfix = ap->fixed_rank;
   D.eps = (ap->fixed_rank > 0) ? 0.0 : ap->eps;
   D.kmax = (ap->fixed_rank > 0) ? ap->fixed_rank : K_MAX;
-  hipStream_t st = ds->ctx->stream;
   HIPTRY(hipEventRecord(ds->ev[0], st));
   HIPTRY(launch_assemble(D, st));
   HIPTRY(launch_aca(D, NSLOTS, st));
@@ -410,9 +447,61 @@ static hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_ap
   return HM_OK;
 }
 
+hm_status decode_factor_status(hm_dataset* ds, int32_t abort_flag, unsigned long long key) {
+  ds->assembled = false;
+  ds->factored = true;
+  ds->fail_block = -1;
+  ds->fail_pivot = -1;
+  if (abort_flag) {
+    ds->factor_status = HM_ERR_INTERNAL;
+    return HM_ERR_INTERNAL;
+  }
+  if (key != ~0ull) {
+    const int64_t prog = (int64_t)(key >> 8);
+    ds->fail_pivot = (int32_t)(key & 0xff);
+    ds->fail_block = (prog >= 0 && prog < (int64_t)ds->plan.prog_obj.size()) ? ds->plan.prog_obj[prog] : -1;
+    ds->factor_status = HM_ERR_NOT_SPD;
+    return HM_ERR_NOT_SPD;
+  }
+  ds->factor_status = HM_OK;
+  return HM_OK;
+}
+
+int32_t max_lr_rank(const hm_dataset* ds, const int32_t* rank) {
+  int32_t mr = 0;
+  for (int32_t b : ds->plan.lr_ids) mr = rank[b] > mr ? rank[b] : mr;
+  return mr;
+}
+
+void fill_results(const hm_dataset* ds, const double* res, int32_t max_rank, hm_result* out) {
+  const double c0 = -0.5 * (double)ds->tree.n * std::log(2.0 * 3.14159265358979323846);
+  for (int c = 0; c < ds->r; ++c) {
+    hm_result& o = out[c];
+    o.status = ds->factor_status;
+    o.max_rank = max_rank;
+    o.fail_block = ds->fail_block;
+    o.fail_pivot = ds->fail_pivot;
+    o.t_assemble = ds->t_assemble;
+    o.t_factor = ds->t_factor;
+    o.t_solve = ds->t_solve;
+    if (ds->factor_status == HM_OK) {
+      o.logdet = res[0];
+      o.quadform = res[1 + c];
+      o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.quadform;
+    } else {
+      o.logdet = o.quadform = o.loglik = NAN;
+    }
+  }
+}
+
+}  // namespace hm_int
+
+extern "C" {
+
 hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
   if (!ds) return HM_ERR_ARG;
-  TRY(assemble_launch(ds, th, ap));
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  TRY(assemble_launch(ds, th, ap, ds->ctx->stream));
   HIPTRY(hipEventSynchronize(ds->ev[1]));
   float ms = 0;
   HIPTRY(hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]));
@@ -444,12 +533,8 @@ static hm_status finish_factor(hm_dataset* ds) {
       }
     }
   }
-  ds->assembled = false;
-  ds->factored = true;
-  ds->fail_block = -1;
-  ds->fail_pivot = -1;
-  if (flags[0]) {
-    ds->factor_status = HM_ERR_INTERNAL;
+  const hm_status fs = decode_factor_status(ds, flags[0], key);
+  if (fs == HM_ERR_INTERNAL) {
     if (getenv("HMLIK_DUMP_EXECUTOR")) {
       std::vector<int32_t> dbg(4 * NSLOTS), done(ds->plan.tasks.size());
       (void)hipMemcpy(dbg.data(), D.dbg, sizeof(int32_t) * dbg.size(), hipMemcpyDeviceToHost);
@@ -465,21 +550,13 @@ static hm_status finish_factor(hm_dataset* ds) {
                   (dep >= 0 && dep < (int)done.size()) ? done[dep] : -1, dbg[4 * w + 3]);
       }
     }
-    return HM_ERR_INTERNAL;
   }
-  if (key != ~0ull) {
-    const int64_t prog = (int64_t)(key >> 8);
-    ds->fail_pivot = (int32_t)(key & 0xff);
-    ds->fail_block = (prog >= 0 && prog < (int64_t)ds->plan.prog_obj.size()) ? ds->plan.prog_obj[prog] : -1;
-    ds->factor_status = HM_ERR_NOT_SPD;
-    return HM_ERR_NOT_SPD;
-  }
-  ds->factor_status = HM_OK;
-  return HM_OK;
+  return fs;
 }
 
 hm_status hm_factor(hm_dataset* ds) {
   if (!ds || !ds->assembled) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   HIPTRY(hipSetDevice(ds->ctx->device));
   use_ctx_ws(ds);
   DevData& D = ds->D;
@@ -524,16 +601,16 @@ hm_status hm_factor(hm_dataset* ds) {
 
 hm_status hm_solve(hm_dataset* ds, hm_result* out) {
   if (!ds || !out || !ds->factored || ds->r < 1) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   HIPTRY(hipSetDevice(ds->ctx->device));
   const int r = ds->r;
-  const int64_t n = ds->tree.n;
   DevData& D = ds->D;
   hipStream_t st = ds->ctx->stream;
   int32_t max_rank = 0;
   {
     std::vector<int32_t> rk(ds->tree.bk.size());
     HIPTRY(hipMemcpy(rk.data(), D.rank, sizeof(int32_t) * rk.size(), hipMemcpyDeviceToHost));
-    for (int32_t b : ds->plan.lr_ids) max_rank = rk[b] > max_rank ? rk[b] : max_rank;
+    max_rank = max_lr_rank(ds, rk.data());
   }
   std::vector<double> res(1 + r, NAN);
   if (ds->factor_status == HM_OK) {
@@ -547,30 +624,14 @@ hm_status hm_solve(hm_dataset* ds, hm_result* out) {
     ds->t_solve = ms * 1e-3;
     HIPTRY(hipMemcpy(res.data(), ds->d_out, sizeof(double) * (1 + r), hipMemcpyDeviceToHost));
   }
-  const double c0 = -0.5 * (double)n * std::log(2.0 * 3.14159265358979323846);
-  for (int c = 0; c < r; ++c) {
-    hm_result& o = out[c];
-    o.status = ds->factor_status;
-    o.max_rank = max_rank;
-    o.fail_block = ds->fail_block;
-    o.fail_pivot = ds->fail_pivot;
-    o.t_assemble = ds->t_assemble;
-    o.t_factor = ds->t_factor;
-    o.t_solve = ds->t_solve;
-    if (ds->factor_status == HM_OK) {
-      o.logdet = res[0];
-      o.quadform = res[1 + c];
-      o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.quadform;
-    } else {
-      o.logdet = o.quadform = o.loglik = NAN;
-    }
-  }
+  fill_results(ds, res.data(), max_rank, out);
   return ds->factor_status;
 }
 
 hm_status hm_loglik(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hm_result* out) {
   if (!ds || !out) return HM_ERR_ARG;
   if (ds->r < 1) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   TRY(hm_assemble(ds, th, ap));
   hm_status s = hm_factor(ds);
   if (s != HM_OK && s != HM_ERR_NOT_SPD) return s;
@@ -580,6 +641,7 @@ hm_status hm_loglik(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hm_
 hm_status hm_loglik_batch(hm_ctx* ctx, int32_t m, hm_dataset* const* ds, const hm_theta* theta,
                           const hm_approx* approx, hm_result* out) {
   if (!ctx || m < 1 || !ds || !theta || !approx || !out) return HM_ERR_ARG;
+  if (busy(ctx)) return HM_ERR_BUSY;
   for (int32_t i = 0; i < m; ++i) {
     if (!ds[i] || ds[i]->ctx != ctx || ds[i]->r < 1) return HM_ERR_ARG;
     for (int32_t j = 0; j < i; ++j)
@@ -588,7 +650,7 @@ hm_status hm_loglik_batch(hm_ctx* ctx, int32_t m, hm_dataset* const* ds, const h
   }
   HIPTRY(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
-  for (int32_t i = 0; i < m; ++i) TRY(assemble_launch(ds[i], &theta[i], &approx[i]));
+  for (int32_t i = 0; i < m; ++i) TRY(assemble_launch(ds[i], &theta[i], &approx[i], st));
   // per level index l, the task range of each dataset (empty past its last level)
   int32_t L = 0;
   for (int32_t i = 0; i < m; ++i) L = std::max(L, (int32_t)ds[i]->level_begin.size() - 1);
@@ -691,6 +753,7 @@ static void relevel(const Plan& P, const std::vector<double>& dur, int32_t horiz
 
 hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_approx* approx) {
   if (!ds || ds->r < 1) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   TRY(check_theta_approx(theta, approx));
   HIPTRY(hipSetDevice(ds->ctx->device));
   const int32_t nt = (int32_t)ds->plan.tasks.size();
@@ -772,6 +835,8 @@ hm_status hm_dataset_export_blocks(const hm_dataset* ds, int64_t* rc, int8_t* ki
 
 hm_status hm_get_block(hm_dataset* ds, int64_t block, double* data, int32_t* rank) {
   if (!ds || !data || !rank || block < 0 || block >= (int64_t)ds->tree.bk.size()) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  if (!ds->store) return HM_ERR_ARG;
   const Block& b = ds->tree.bk[block];
   HIPTRY(hipSetDevice(ds->ctx->device));
   HIPTRY(hipStreamSynchronize(ds->ctx->stream));
@@ -795,6 +860,7 @@ hm_status hm_get_block(hm_dataset* ds, int64_t block, double* data, int32_t* ran
 
 hm_status hm_factor_flops(hm_dataset* ds, double* flops) {
   if (!ds || !flops || !ds->factored) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   HIPTRY(hipSetDevice(ds->ctx->device));
   HIPTRY(hipStreamSynchronize(ds->ctx->stream));
   std::vector<double> f(ds->plan.tasks.size());
@@ -817,6 +883,8 @@ hm_status hm_get_term(hm_dataset* ds, int64_t term, double* data, int32_t* kind,
   *rows = t.rows;
   *k = 0;
   if (t.kind == TK_DD) return HM_OK;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  if (!ds->store) return HM_ERR_ARG;
   const int32_t R = (t.kind == TK_LRA) ? t.A : t.B;
   HIPTRY(hipSetDevice(ds->ctx->device));
   HIPTRY(hipStreamSynchronize(ds->ctx->stream));
@@ -830,6 +898,7 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
                            double eps, int32_t fixed_rank, double* U, double* V, int32_t* k, double* seconds) {
   const bool expl = (Y == nullptr);
   if (!ds || !X || !U || !V || !k || m < 1 || n < 1) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
   if (expl ? (r != 0 || n > 4 * LEAF_MAX) : (r < 1 || r > 2 * K_MAX)) return HM_ERR_ARG;
   if (fixed_rank < 0 || fixed_rank > K_MAX || (fixed_rank == 0 && !finite_pos(eps))) return HM_ERR_ARG;
   const int64_t need = expl ? m * n + (n | 1) * (m < n ? m : n) + 64

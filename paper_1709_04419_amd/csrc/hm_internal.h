@@ -1,0 +1,92 @@
+// Library-internal definitions of the handles declared opaque in
+// include/hmlik.h, shared by the evaluation entry points (hm_api.cpp) and the
+// request server (hm_server.cpp).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <cstdint>
+#include <set>
+#include <vector>
+
+#include "../../include/hmlik.h"
+#include "hm_device.h"
+#include "hm_plan.h"
+
+struct hm_ctx {
+  int device;
+  hipStream_t stream;
+  // workspace slots shared by the context's datasets (evaluations on one
+  // context are ordered on its stream); grown when a dataset needs more
+  double* ws = nullptr;
+  int64_t ws_stride = 0;
+  // the context's live datasets (the server's view of resident factor storage)
+  std::set<hm_dataset*> datasets;
+  // non-null while a request server owns the context's device work
+  std::atomic<hm_server*> server{nullptr};
+};
+
+namespace hm_int {
+
+constexpr int NSLOTS = 512;   // workspace slots (ACA and level-kernel work-groups)
+constexpr int NEXEC = 256;    // persistent-executor work-groups: one per CU
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace hm_int
+
+struct hm_dataset {
+  hm_ctx* ctx = nullptr;
+  hm::Tree tree;
+  hm::Plan plan;
+  std::vector<hm_int::DevBuf> bufs;   // resident: trees, plan, schedule, Z, small per-evaluation arrays
+  // factor storage (dense leaves, low-rank factors, update-term buffers): the
+  // theta-dependent bulk of the dataset, one allocation that can be released
+  // between evaluations and is re-attached by the next one
+  void* store = nullptr;
+  size_t store_bytes = 0;
+  hm::DevData D{};
+  int64_t* d_perm = nullptr;
+  int32_t* d_diag_ids = nullptr;
+  double* d_Z = nullptr;
+  double* d_W = nullptr;
+  double* d_out = nullptr;
+  int32_t r = 0;
+  bool assembled = false, factored = false;
+  hm_status factor_status = HM_OK;
+  int64_t fail_block = -1;
+  int32_t fail_pivot = -1;
+  double t_assemble = 0, t_factor = 0, t_solve = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int32_t> level_begin;   // position in `order` where each level starts (+ end)
+  std::vector<int32_t> order;         // execution order (task ids), level by level
+  int32_t* d_order = nullptr;
+  int64_t* tt_buf = nullptr;          // per-task timing records (allocated on first use)
+};
+
+namespace hm_int {
+
+// theta and accuracy checks shared by every evaluation entry point
+hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap);
+// allocates the factor storage if it is not attached
+hm_status attach_store(hm_dataset* ds);
+// frees the factor storage (after the context's stream has drained)
+void release_store(hm_dataset* ds);
+// sets theta and the accuracy, attaches the factor storage and enqueues the
+// assembly on `st`, bracketed by ds->ev[0], ds->ev[1]
+hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st);
+// decodes a finished factorisation's breakdown record into ds->factor_status,
+// fail_block and fail_pivot (key: min over failed pivots of program index << 8 | pivot)
+hm_status decode_factor_status(hm_dataset* ds, int32_t abort_flag, unsigned long long key);
+// largest rank among the low-rank leaves, from a host copy of the rank array
+int32_t max_lr_rank(const hm_dataset* ds, const int32_t* rank);
+// fills r results from the solve output (log-det, then v^T v per column)
+void fill_results(const hm_dataset* ds, const double* res, int32_t max_rank, hm_result* out);
+// cancels the server's queued requests on `ds` and waits until none of its
+// requests is on the device (before the dataset is destroyed)
+void server_forget_dataset(hm_server* sv, hm_dataset* ds);
+
+}  // namespace hm_int

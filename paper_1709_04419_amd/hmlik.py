@@ -23,7 +23,8 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1709_04419_amd.build`")
 _lib = C.CDLL(LIB_PATH)
 
-HM_OK, HM_ERR_ARG, HM_ERR_NOT_SPD, HM_ERR_OOM, HM_ERR_DEVICE, HM_ERR_INTERNAL = range(6)
+(HM_OK, HM_ERR_ARG, HM_ERR_NOT_SPD, HM_ERR_OOM, HM_ERR_DEVICE, HM_ERR_INTERNAL, HM_ERR_CANCELLED,
+ HM_ERR_BUSY) = range(8)
 
 
 class hm_theta(C.Structure):
@@ -44,6 +45,15 @@ class hm_result(C.Structure):
                 ("status", C.c_int32), ("max_rank", C.c_int32), ("fail_block", C.c_int64),
                 ("fail_pivot", C.c_int32), ("t_assemble", C.c_double), ("t_factor", C.c_double),
                 ("t_solve", C.c_double)]
+
+
+class hm_server_opts(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("hbm_budget", C.c_int64)]
+
+
+class hm_request_stats(C.Structure):
+    _fields_ = [("t_queue", C.c_double), ("t_latency", C.c_double), ("steps", C.c_int32),
+                ("peak_batch", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -69,6 +79,14 @@ _sig = {
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "hm_test_truncate": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                                    _P, _P, C.POINTER(C.c_int32), _P]),
+    "hm_dataset_footprint": (C.c_int, [_P, _P, _P, _P]),
+    "hm_dataset_release": (C.c_int, [_P]),
+    "hm_server_create": (C.c_int, [_P, C.POINTER(hm_server_opts), C.POINTER(_P)]),
+    "hm_server_submit": (C.c_int, [_P, _P, C.POINTER(hm_theta), C.POINTER(hm_approx), C.POINTER(C.c_uint64)]),
+    "hm_server_poll": (C.c_int, [_P, C.c_uint64, C.c_int32, C.POINTER(hm_result), C.POINTER(hm_request_stats),
+                                 C.POINTER(C.c_int32)]),
+    "hm_server_cancel": (C.c_int, [_P, C.c_uint64]),
+    "hm_server_destroy": (None, [_P]),
     "hm_status_string": (C.c_char_p, [C.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -111,11 +129,14 @@ class Context:
                "hm_ctx_create")
         self._h = h
         self._datasets = weakref.WeakSet()
+        self._servers = weakref.WeakSet()
 
     def close(self):
-        """Destroys the context, closing its datasets first (a dataset must not
-        outlive the context it was created in)."""
+        """Destroys the context, closing its servers and then its datasets first
+        (neither may outlive the context it was created in)."""
         if self._h:
+            for sv in list(self._servers):
+                sv.close()
             for ds in list(self._datasets):
                 ds.close()
             _lib.hm_ctx_destroy(self._h)
@@ -223,6 +244,17 @@ class Dataset:
         _check(_lib.hm_dataset_info(self._h, *[C.byref(v) for v in vals]), "hm_dataset_info")
         return dict(zip(("n", "nclusters", "nblocks", "ntasks", "nlevels"), (v.value for v in vals)))
 
+    def footprint(self):
+        """hm_dataset_footprint: dict(resident_bytes, factor_bytes, attached)."""
+        res, fac, att = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_lib.hm_dataset_footprint(self._h, C.byref(res), C.byref(fac), C.byref(att)),
+               "hm_dataset_footprint")
+        return dict(resident_bytes=res.value, factor_bytes=fac.value, attached=bool(att.value))
+
+    def release(self):
+        """hm_dataset_release: frees the factor storage until the next evaluation."""
+        _check(_lib.hm_dataset_release(self._h), "hm_dataset_release")
+
     def export_tree(self):
         inf = self.info()
         perm = np.empty(self.n, dtype=np.int64)
@@ -323,6 +355,67 @@ def loglik_batch(ctx: "Context", datasets, thetas, nuggets, eps=0.0, rank=0):
         res.append(_results(out[off:off + ds.r]))
         off += ds.r
     return res
+
+
+class Server:
+    """hm_server_*: continuous-batching request server on a context's resident
+    datasets.  While it is open, the context's direct evaluation calls raise
+    HMError with status HM_ERR_BUSY."""
+
+    def __init__(self, ctx: Context, max_active: int = 8, hbm_budget: int = 0):
+        opts = hm_server_opts(int(max_active), int(hbm_budget))
+        h = _P()
+        _check(_lib.hm_server_create(ctx._h, C.byref(opts), C.byref(h)), "hm_server_create")
+        self._h = h
+        self.ctx = ctx
+        self._r = {}
+        ctx._servers.add(self)
+
+    def submit(self, ds: Dataset, theta, nugget, eps=0.0, rank=0) -> int:
+        th, ap = ds._args(theta, nugget, eps, rank)
+        t = C.c_uint64()
+        _check(_lib.hm_server_submit(self._h, ds._h, C.byref(th), C.byref(ap), C.byref(t)), "hm_server_submit")
+        self._r[t.value] = ds.r
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """None while the request runs (wait=False); else the result dict of
+        Dataset.loglik plus 'request_status', 't_queue', 't_latency', 'steps'
+        and 'peak_batch'.  The ticket is retired once its result is returned."""
+        r = self._r.get(ticket, 1)
+        out = (hm_result * max(1, r))()
+        st = hm_request_stats()
+        done = C.c_int32()
+        s = _lib.hm_server_poll(self._h, C.c_uint64(ticket), 1 if wait else 0, out, C.byref(st), C.byref(done))
+        if s == HM_ERR_ARG and not done.value:
+            raise HMError(s, "hm_server_poll")
+        if not done.value:
+            return None
+        self._r.pop(ticket, None)
+        res = _results(out[:r])
+        res.update(request_status=s, t_queue=st.t_queue, t_latency=st.t_latency, steps=st.steps,
+                   peak_batch=st.peak_batch)
+        return res
+
+    def cancel(self, ticket: int):
+        _check(_lib.hm_server_cancel(self._h, C.c_uint64(ticket)), "hm_server_cancel")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hm_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _results(out):
