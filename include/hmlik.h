@@ -152,16 +152,16 @@ hm_status hm_tune_schedule(hm_dataset *ds, const hm_theta *theta, const hm_appro
 
 /* Batched evaluation of eq. (4) (Monte-Carlo replicates, several theta on
  * copies of one dataset, or unrelated datasets): dataset ds[i] is evaluated at
- * theta[i] and approx[i], i < m.  The assemblies are enqueued back to back and
- * the H-Cholesky of all datasets runs together, one launch per level index of
- * their task graphs, so that the datasets fill work-groups one alone leaves
- * idle.  Every dataset gets bitwise the results of hm_loglik alone.  out
- * receives sum_i r_i results, dataset by dataset (r_i = columns of its Z).
- * The datasets must be distinct, belong to ctx and have Z set (else
- * HM_ERR_ARG).  Returns HM_ERR_NOT_SPD if any factorisation broke down (the
- * per-result status says which); t_factor is the batch's factorisation time.
- * Allocates two small device tables per call (the level table and the
- * datasets' descriptors). */
+ * theta[i] and approx[i], i < m.  Runs a request server (below) on ctx for
+ * the duration of the call, with one batch slot per dataset (at most 16 at
+ * once): each evaluation runs on a stream of its own with its share of the
+ * workspace, so that the datasets fill work-groups one alone leaves idle.
+ * Every dataset gets bitwise the results of hm_loglik alone.  out receives
+ * sum_i r_i results, dataset by dataset (r_i = columns of its Z).  The
+ * datasets must be distinct, belong to ctx and have Z set (else HM_ERR_ARG);
+ * HM_ERR_BUSY if ctx already has a server.  Returns HM_ERR_NOT_SPD if any
+ * factorisation broke down (the per-result status says which); the t_*
+ * fields are each evaluation's own (overlapping) device times. */
 hm_status hm_loglik_batch(hm_ctx *ctx, int32_t m, hm_dataset *const *ds, const hm_theta *theta,
                           const hm_approx *approx, hm_result *out);
 
@@ -217,14 +217,17 @@ hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const dou
 
 /* ------------------------------------------------------------------ serving
  *
- * A request server evaluates eq. (4) for a stream of requests (dataset, theta,
- * accuracy) on resident datasets of one context, with continuous batching: a
- * worker thread runs the H-Cholesky of every admitted request together, one
- * kernel launch per step that advances each of them by one dependency level
- * of its own task graph, and admits newly arrived requests between steps (an
- * admitted request is assembled and joins at its first level while the
- * others continue).  Its forward solve then runs on a second stream, beside
- * the next steps.  Each request gets bitwise the result of hm_loglik alone.
+ * A request server evaluates eq. (4) (Sect. 3.1) for a stream of requests
+ * (dataset, theta, accuracy), the calls a likelihood maximiser issues, on
+ * resident datasets of one context, with continuous batching: every batch slot
+ * has a HIP stream of its own (default priority) and its own share of the
+ * context's work-group workspace, and an admitted request's assembly,
+ * H-Cholesky levels and forward solve run on its slot's stream, so admitted
+ * requests advance independently and their kernels overlap on the device.  A
+ * worker thread feeds the streams (levels in chunks), retires finished
+ * requests and admits queued ones as slots and memory free up; a request that
+ * arrives while others run starts at once if a slot is free.  Each request
+ * gets bitwise the result of hm_loglik alone.
  *
  * Admission, in arrival order, takes a request when a batch slot is free, no
  * other admitted request uses its dataset (requests on one dataset run in
@@ -237,7 +240,8 @@ hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const dou
  * later request overtakes a request held back for memory).
  */
 typedef struct {
-  int32_t max_active; /* requests batched together, 1..64 */
+  int32_t max_active; /* batch slots (requests on the device at once), 1..16; each slot's
+                         kernels use 512 / max_active work-groups at most */
   int64_t hbm_budget; /* bytes of attached factor storage over the context's datasets; 0 = no limit */
 } hm_server_opts;
 
@@ -245,16 +249,15 @@ typedef struct {
 typedef struct {
   double t_queue;      /* seconds from submission to admission (host clock) */
   double t_latency;    /* seconds from submission to the result being ready (host clock) */
-  int32_t steps;       /* level steps the request's factorisation took part in */
-  int32_t peak_batch;  /* largest number of requests in one of those steps */
+  int32_t steps;       /* chunks of levels enqueued for the request's factorisation */
+  int32_t peak_batch;  /* largest number of requests admitted at once while it was admitted */
 } hm_request_stats;
 
-/* Starts a server (worker thread and two streams of default priority) on ctx.
- * The context's datasets must already exist: dataset creation is refused
- * while the server runs.  HM_ERR_ARG if ctx has no dataset or the options are
- * out of range; HM_ERR_BUSY if ctx already has a server.  Allocates its
- * per-slot tables, pinned staging buffers and one workspace slot for the
- * solve stream. */
+/* Starts a server (worker thread, one stream per batch slot) on ctx.  The
+ * context's datasets must already exist: dataset creation is refused while
+ * the server runs.  HM_ERR_ARG if ctx has no dataset or the options are out of
+ * range; HM_ERR_BUSY if ctx already has a server.  Allocates the slots' pinned
+ * host records (ranks, breakdown record, solve output). */
 hm_status hm_server_create(hm_ctx *ctx, const hm_server_opts *opts, hm_server **out);
 
 /* Queues the evaluation of ds (with its current Z) at theta and approx;
@@ -274,9 +277,9 @@ hm_status hm_server_submit(hm_server *sv, hm_dataset *ds, const hm_theta *theta,
 hm_status hm_server_poll(hm_server *sv, uint64_t ticket, int32_t wait, hm_result *out, hm_request_stats *stats,
                          int32_t *done);
 
-/* Cancels a request: a queued one at once, an admitted one before its next
- * level step (one whose solve has started finishes it).  Its poll then
- * returns HM_ERR_CANCELLED.  HM_ERR_ARG for an unknown ticket, HM_OK (no
+/* Cancels a request: a queued one at once, an admitted one at the end of its
+ * chunk of levels in flight (one whose forward solve has started completes
+ * normally).  Its poll then returns HM_ERR_CANCELLED.  HM_ERR_ARG for an unknown ticket, HM_OK (no
  * effect) if it already finished.  Thread-safe. */
 hm_status hm_server_cancel(hm_server *sv, uint64_t ticket);
 

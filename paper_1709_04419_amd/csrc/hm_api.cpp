@@ -430,7 +430,8 @@ hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
   return HM_OK;
 }
 
-hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st) {
+hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st, double* ws,
+                          int grid) {
   TRY(check_theta_approx(th, ap));
   HIPTRY(hipSetDevice(ds->ctx->device));
   TRY(attach_store(ds));
@@ -440,9 +441,11 @@ hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* a
   D.kfix = ap->fixed_rank;
   D.eps = (ap->fixed_rank > 0) ? 0.0 : ap->eps;
   D.kmax = (ap->fixed_rank > 0) ? ap->fixed_rank : K_MAX;
+  DevData Dl = D;
+  if (ws) Dl.ws = ws;
   HIPTRY(hipEventRecord(ds->ev[0], st));
-  HIPTRY(launch_assemble(D, st));
-  HIPTRY(launch_aca(D, NSLOTS, st));
+  HIPTRY(launch_assemble(Dl, st));
+  HIPTRY(launch_aca(Dl, ws ? grid : NSLOTS, st));
   HIPTRY(hipEventRecord(ds->ev[1], st));
   return HM_OK;
 }
@@ -501,7 +504,7 @@ extern "C" {
 hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
   if (!ds) return HM_ERR_ARG;
   if (busy(ds->ctx)) return HM_ERR_BUSY;
-  TRY(assemble_launch(ds, th, ap, ds->ctx->stream));
+  TRY(assemble_launch(ds, th, ap, ds->ctx->stream, nullptr, NSLOTS));
   HIPTRY(hipEventSynchronize(ds->ev[1]));
   float ms = 0;
   HIPTRY(hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]));
@@ -648,67 +651,29 @@ hm_status hm_loglik_batch(hm_ctx* ctx, int32_t m, hm_dataset* const* ds, const h
       if (ds[j] == ds[i]) return HM_ERR_ARG;
     TRY(check_theta_approx(&theta[i], &approx[i]));
   }
-  HIPTRY(hipSetDevice(ctx->device));
-  hipStream_t st = ctx->stream;
-  for (int32_t i = 0; i < m; ++i) TRY(assemble_launch(ds[i], &theta[i], &approx[i], st));
-  // per level index l, the task range of each dataset (empty past its last level)
-  int32_t L = 0;
-  for (int32_t i = 0; i < m; ++i) L = std::max(L, (int32_t)ds[i]->level_begin.size() - 1);
-  std::vector<int32_t> seg((size_t)L * 2 * m, 0), total(L, 0);
-  std::vector<DevData> hD(m);
-  for (int32_t i = 0; i < m; ++i) {
-    hD[i] = ds[i]->D;
-    const std::vector<int32_t>& lb = ds[i]->level_begin;
-    for (int32_t l = 0; l + 1 < (int32_t)lb.size(); ++l) {
-      seg[((size_t)l * m + i) * 2] = lb[l];
-      seg[((size_t)l * m + i) * 2 + 1] = lb[l + 1];
-      total[l] += lb[l + 1] - lb[l];
-    }
-  }
-  void *dD = nullptr, *dseg = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // a request server with one slot per dataset (at most 16 on the device at
+  // once), all requests submitted together
+  const hm_server_opts opts{std::min<int32_t>(m, 16), 0};
+  hm_server* sv = nullptr;
+  TRY(hm_server_create(ctx, &opts, &sv));
+  std::vector<uint64_t> tickets(m, 0);
   hm_status s = HM_OK;
-  if (hipMalloc(&dD, sizeof(DevData) * m) != hipSuccess ||
-      hipMalloc(&dseg, sizeof(int32_t) * std::max<size_t>(seg.size(), 2)) != hipSuccess)
-    s = HM_ERR_OOM;
-  if (s == HM_OK &&
-      (hipMemcpyAsync(dD, hD.data(), sizeof(DevData) * m, hipMemcpyHostToDevice, st) != hipSuccess ||
-       hipMemcpyAsync(dseg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-    s = HM_ERR_DEVICE;
-  float ms = 0;
-  if (s == HM_OK) {
-    bool ok = hipEventRecord(e0, st) == hipSuccess;
-    for (int32_t i = 0; ok && i < m; ++i) ok = launch_factor_init(hD[i], st) == hipSuccess;
-    for (int32_t l = 0; ok && l < L; ++l)
-      ok = launch_level_batch((const DevData*)dD, (const int32_t*)dseg + (size_t)l * 2 * m, m, total[l], NSLOTS,
-                              st) == hipSuccess;
-    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-         hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-    if (!ok) s = HM_ERR_DEVICE;
-  }
-  (void)hipStreamSynchronize(st);
-  if (dD) (void)hipFree(dD);
-  if (dseg) (void)hipFree(dseg);
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  (void)hipGetLastError();
-  if (s != HM_OK) return s;
+  for (int32_t i = 0; i < m && s == HM_OK; ++i) s = hm_server_submit(sv, ds[i], &theta[i], &approx[i], &tickets[i]);
   hm_status any = HM_OK;
   size_t off = 0;
   for (int32_t i = 0; i < m; ++i) {
-    float ma = 0;
-    HIPTRY(hipEventElapsedTime(&ma, ds[i]->ev[0], ds[i]->ev[1]));
-    ds[i]->t_assemble = ma * 1e-3;
-    ds[i]->t_factor = ms * 1e-3;
-    const hm_status fs = finish_factor(ds[i]);
-    if (fs != HM_OK && fs != HM_ERR_NOT_SPD) return fs;
-    const hm_status ss = hm_solve(ds[i], out + off);
-    if (ss != HM_OK && ss != HM_ERR_NOT_SPD) return ss;
-    if (ss == HM_ERR_NOT_SPD) any = HM_ERR_NOT_SPD;
+    if (!tickets[i]) continue;
+    int32_t done = 0;
+    const hm_status q = hm_server_poll(sv, tickets[i], 1, out + off, nullptr, &done);
     off += (size_t)ds[i]->r;
+    if (q == HM_ERR_NOT_SPD) {
+      any = HM_ERR_NOT_SPD;
+    } else if (q != HM_OK && s == HM_OK) {
+      s = q;
+    }
   }
-  return any;
+  hm_server_destroy(sv);
+  return s != HM_OK ? s : any;
 }
 
 // Re-assigns tasks to levels.  Starting from the longest-path levels and

@@ -76,8 +76,11 @@ hm_status attach_store(hm_dataset* ds);
 // frees the factor storage (after the context's stream has drained)
 void release_store(hm_dataset* ds);
 // sets theta and the accuracy, attaches the factor storage and enqueues the
-// assembly on `st`, bracketed by ds->ev[0], ds->ev[1]
-hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st);
+// assembly on `st`, bracketed by ds->ev[0], ds->ev[1]; with ws != nullptr the
+// ACA kernel runs `grid` work-groups on the workspace slots starting at ws
+// (else NSLOTS on the context's workspace)
+hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st, double* ws,
+                          int grid);
 // decodes a finished factorisation's breakdown record into ds->factor_status,
 // fail_block and fail_pivot (key: min over failed pivots of program index << 8 | pivot)
 hm_status decode_factor_status(hm_dataset* ds, int32_t abort_flag, unsigned long long key);

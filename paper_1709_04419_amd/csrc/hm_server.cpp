@@ -1,19 +1,19 @@
 // Request server of libhmlik (hm_server_* in include/hmlik.h): evaluations of
 // eq. (4) of Section 3.1, the calls a likelihood maximiser issues, for a
-// stream of (dataset, theta, accuracy) requests on resident datasets, with
-// continuous batching at the granularity of one dependency level of the
-// H-Cholesky task graph (Section 3.2).
+// stream of (dataset, theta, accuracy) requests on resident datasets.
 //
-// One worker thread owns the context's device work.  Each step it
-//   1. retires requests whose factorisation or forward solve has finished,
-//   2. admits queued requests into free batch slots (assembly of C~(theta),
-//      Section 2.1 and Remark 2.4, enqueued at once),
-//   3. launches one batched level kernel that advances every admitted
-//      factorisation by one level of its own schedule, and waits for it.
-// A finished factorisation's forward solve and log-determinant run on a
-// second stream with a workspace slot of their own, beside the next steps.
-// The tasks, their inputs and their order within each dataset are those of
-// a single evaluation, so every result is bitwise that of hm_loglik.
+// Continuous batching over HIP streams: every batch slot has a stream of its
+// own and its own share of the context's work-group workspace.  An admitted
+// request's assembly (Section 2.1, Remark 2.4), its H-Cholesky levels
+// (Section 3.2) and its forward solve are enqueued on its slot's stream, so
+// the requests advance independently and their kernels overlap on the device
+// (one level of one factorisation fills only a few dozen of the 256 CUs).
+// A worker thread owns the context's device work: it feeds each slot's stream
+// in chunks of levels (two chunks in flight, so that cancellation takes effect
+// at a chunk boundary and the host never holds thousands of launches), retires
+// finished requests, and admits queued ones as slots and memory free up.
+// The tasks, their inputs and their order within each dataset are those of a
+// single evaluation, so every result is bitwise that of hm_loglik.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -37,6 +37,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr int32_t CHUNK_LEVELS = 128;   // levels enqueued per chunk
+
 enum class RState { QUEUED, ACTIVE, SOLVING, DONE };
 
 struct Request {
@@ -48,7 +50,6 @@ struct Request {
   RState state = RState::QUEUED;
   bool cancel = false;
   int slot = -1;
-  int32_t level = 0;   // next level of the dataset's schedule to run
   int32_t max_rank = 0;
   hm_status status = HM_OK;
   std::vector<hm_result> res;
@@ -56,11 +57,17 @@ struct Request {
   Clock::time_point t_submit;
 };
 
-// Host records of one batch slot, written by asynchronous copies on the
-// streams (pinned memory), and the events that say when they are complete.
+// One batch slot: its stream, its workspace share, the progress of its
+// request's enqueued work, and host records written by asynchronous copies
+// (pinned memory) with the events that say when they are complete.
 struct Slot {
   Request* req = nullptr;
-  bool factor_pending = false;   // last level launched; breakdown record being copied
+  hipStream_t st = nullptr;
+  double* ws = nullptr;
+  int32_t next_level = 0;        // first level not yet enqueued
+  int32_t chunks = 0;            // chunks enqueued so far
+  bool fac_enqueued = false;     // all levels and the breakdown record enqueued
+  hipEvent_t ev_chunk[2] = {nullptr, nullptr};
   hipEvent_t ev_fac = nullptr, ev_sol0 = nullptr, ev_sol1 = nullptr;
   int32_t* h_abort = nullptr;
   unsigned long long* h_key = nullptr;
@@ -78,13 +85,8 @@ struct hm_server {
   hm_ctx* ctx = nullptr;
   int32_t max_active = 0;
   int64_t budget = 0;
-  hipStream_t st = nullptr, st_solve = nullptr;
-  DevData* dD = nullptr;     // device: one dataset descriptor per slot
-  int32_t* dseg = nullptr;   // device: the step's task range per slot
-  DevData* hD = nullptr;     // pinned staging of dD
-  int32_t* hseg = nullptr;   // pinned staging of dseg
+  int grid = 0;              // work-groups (= workspace slots) per batch slot
   char* pinned = nullptr;    // the slots' host records, one pinned allocation
-  double* solve_ws = nullptr;
   int64_t max_nblocks = 0;
   int32_t max_r = 0;
   std::vector<Slot> slots;
@@ -119,7 +121,6 @@ void complete(hm_server* sv, Request* q, hm_status status) {
   q->state = RState::DONE;
   if (q->slot >= 0) {
     sv->slots[q->slot].req = nullptr;
-    sv->slots[q->slot].factor_pending = false;
     q->slot = -1;
   }
   q->stats.t_latency = seconds_since(q->t_submit);
@@ -161,60 +162,90 @@ bool make_room(hm_server* sv, const hm_dataset* keep, int64_t need) {
   return true;
 }
 
-// Enqueues, after a factorisation's last level, the copies of its breakdown
-// record and ranks, and the event that marks them complete.
-bool enqueue_factor_end(hm_server* sv, int k) {
-  Slot& s = sv->slots[k];
-  const DevData& D = s.req->ds->D;
-  const size_t nb = s.req->ds->tree.bk.size();
-  bool ok = hipMemcpyAsync(s.h_abort, D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost, sv->st) == hipSuccess &&
-            hipMemcpyAsync(s.h_key, D.fail_key, sizeof(unsigned long long), hipMemcpyDeviceToHost, sv->st) ==
-                hipSuccess &&
-            hipMemcpyAsync(s.h_rank, D.rank, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sv->st) == hipSuccess &&
-            hipEventRecord(s.ev_fac, sv->st) == hipSuccess;
-  s.factor_pending = true;
-  return ok;
+// The dataset's descriptor with the slot's workspace share.
+DevData slot_view(const hm_server* sv, const Slot& s) {
+  DevData D = s.req->ds->D;
+  D.ws = s.ws;
+  (void)sv;
+  return D;
 }
 
-// Admits q into slot k: assembly, breakdown-flag reset and the slot's
-// dataset descriptor, all enqueued on the server's stream.
+// 1: the chunk enqueued two chunks ago (and so everything before it) has
+// finished; 0: not yet; -1: device error.
+int chunk_window_free(const Slot& s) {
+  if (s.chunks < 2) return 1;
+  const hipError_t e = hipEventQuery(s.ev_chunk[s.chunks % 2]);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return -1;
+}
+
+// 1: everything enqueued on the slot's stream has finished; 0: not yet; -1: error.
+int slot_idle(const Slot& s) {
+  if (s.chunks == 0) return 1;
+  const hipError_t e = hipEventQuery(s.fac_enqueued ? s.ev_fac : s.ev_chunk[(s.chunks - 1) % 2]);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return -1;
+}
+
+// Enqueues the next chunk of levels of slot k's factorisation; after the last
+// level, the copies of its breakdown record and ranks and the end event.
+bool enqueue_chunk(hm_server* sv, int k) {
+  Slot& s = sv->slots[k];
+  hm_dataset* ds = s.req->ds;
+  const std::vector<int32_t>& lb = ds->level_begin;
+  const int32_t nlev = (int32_t)lb.size() - 1;
+  const DevData D = slot_view(sv, s);
+  const int32_t l0 = s.next_level, l1 = std::min(nlev, l0 + CHUNK_LEVELS);
+  if (launch_factor_levels(D, lb.data(), l0, l1, l0 == 0, sv->grid, s.st) != hipSuccess) return false;
+  s.next_level = l1;
+  if (hipEventRecord(s.ev_chunk[s.chunks % 2], s.st) != hipSuccess) return false;
+  ++s.chunks;
+  ++s.req->stats.steps;
+  if (l1 < nlev) return true;
+  const size_t nb = ds->tree.bk.size();
+  s.fac_enqueued = true;
+  return hipMemcpyAsync(s.h_abort, D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.st) == hipSuccess &&
+         hipMemcpyAsync(s.h_key, D.fail_key, sizeof(unsigned long long), hipMemcpyDeviceToHost, s.st) ==
+             hipSuccess &&
+         hipMemcpyAsync(s.h_rank, D.rank, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s.st) == hipSuccess &&
+         hipEventRecord(s.ev_fac, s.st) == hipSuccess;
+}
+
+// Admits q into slot k: assembly and the first chunk of levels on the slot's
+// stream.
 bool admit(hm_server* sv, Request* q, int k) {
   hm_dataset* ds = q->ds;
   Slot& s = sv->slots[k];
   q->slot = k;
   s.req = q;
+  s.next_level = 0;
+  s.chunks = 0;
+  s.fac_enqueued = false;
   q->state = RState::ACTIVE;
-  q->level = 0;
   q->stats.t_queue = seconds_since(q->t_submit);
   sv->last_use[ds] = ++sv->use_clock;
-  const hm_status a = assemble_launch(ds, &q->th, &q->ap, sv->st);
+  const hm_status a = assemble_launch(ds, &q->th, &q->ap, s.st, s.ws, sv->grid);
   if (a == HM_ERR_OOM || a == HM_ERR_ARG) {
     complete(sv, q, a);
     return true;
   }
-  if (a != HM_OK) return false;
-  sv->hD[k] = ds->D;
-  if (hipMemcpyAsync(sv->dD + k, sv->hD + k, sizeof(DevData), hipMemcpyHostToDevice, sv->st) != hipSuccess ||
-      launch_factor_init(ds->D, sv->st) != hipSuccess)
-    return false;
-  if ((int32_t)ds->level_begin.size() - 1 <= 0) return enqueue_factor_end(sv, k);
-  return true;
+  return a == HM_OK && enqueue_chunk(sv, k);
 }
 
-// Enqueues the forward solve and log-determinant of slot k's request on the
-// solve stream, after its factorisation's end event.
+// Enqueues the forward solve and log-determinant of slot k's request after
+// its factorisation, on the slot's stream.
 bool enqueue_solve(hm_server* sv, int k) {
   Slot& s = sv->slots[k];
   hm_dataset* ds = s.req->ds;
-  DevData Ds = ds->D;
-  Ds.ws = sv->solve_ws;
-  return hipStreamWaitEvent(sv->st_solve, s.ev_fac, 0) == hipSuccess &&
-         hipEventRecord(s.ev_sol0, sv->st_solve) == hipSuccess &&
-         launch_solve(Ds, ds->d_Z, ds->d_perm, ds->r, ds->d_W, ds->d_diag_ids,
-                      (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, sv->st_solve) == hipSuccess &&
-         hipMemcpyAsync(s.h_out, ds->d_out, sizeof(double) * (1 + ds->r), hipMemcpyDeviceToHost, sv->st_solve) ==
+  const DevData D = slot_view(sv, s);
+  return hipEventRecord(s.ev_sol0, s.st) == hipSuccess &&
+         launch_solve(D, ds->d_Z, ds->d_perm, ds->r, ds->d_W, ds->d_diag_ids,
+                      (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, s.st) == hipSuccess &&
+         hipMemcpyAsync(s.h_out, ds->d_out, sizeof(double) * (1 + ds->r), hipMemcpyDeviceToHost, s.st) ==
              hipSuccess &&
-         hipEventRecord(s.ev_sol1, sv->st_solve) == hipSuccess;
+         hipEventRecord(s.ev_sol1, s.st) == hipSuccess;
 }
 
 float elapsed_s(hipEvent_t a, hipEvent_t b) {
@@ -226,27 +257,37 @@ float elapsed_s(hipEvent_t a, hipEvent_t b) {
   return ms * 1e-3f;
 }
 
-// Host phase part 1: requests whose factorisation or solve has finished, and
-// cancellations.  Returns false on a device failure.
-bool retire(hm_server* sv) {
+// Advances every occupied slot: feeds chunks, handles a finished
+// factorisation or solve, and cancellations.  Returns false on a device error.
+bool progress(hm_server* sv) {
   for (int k = 0; k < sv->max_active; ++k) {
     Slot& s = sv->slots[k];
     Request* q = s.req;
     if (!q) continue;
     hm_dataset* ds = q->ds;
-    if (q->state == RState::ACTIVE && s.factor_pending) {
+    if (q->state == RState::ACTIVE && q->cancel) {
+      // nothing more is enqueued; the request ends once its stream is idle
+      const int idle = slot_idle(s);
+      if (idle < 0) return false;
+      if (idle) complete(sv, q, HM_ERR_CANCELLED);
+      continue;
+    }
+    if (q->state == RState::ACTIVE && !s.fac_enqueued) {
+      const int w = chunk_window_free(s);
+      if (w < 0) return false;
+      if (w && !enqueue_chunk(sv, k)) return false;
+      continue;
+    }
+    if (q->state == RState::ACTIVE) {
       const hipError_t e = hipEventQuery(s.ev_fac);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) return false;
-      s.factor_pending = false;
       ds->t_assemble = elapsed_s(ds->ev[0], ds->ev[1]);
       ds->t_factor = elapsed_s(ds->ev[1], s.ev_fac);
       ds->t_solve = 0;
       const hm_status fs = decode_factor_status(ds, *s.h_abort, *s.h_key);
       q->max_rank = max_lr_rank(ds, s.h_rank);
-      if (q->cancel) {
-        complete(sv, q, HM_ERR_CANCELLED);
-      } else if (fs == HM_OK) {
+      if (fs == HM_OK) {
         if (!enqueue_solve(sv, k)) return false;
         q->state = RState::SOLVING;
       } else {
@@ -254,7 +295,9 @@ bool retire(hm_server* sv) {
         fill_results(ds, nullptr, q->max_rank, q->res.data());
         complete(sv, q, fs);
       }
-    } else if (q->state == RState::SOLVING) {
+      continue;
+    }
+    if (q->state == RState::SOLVING) {
       const hipError_t e = hipEventQuery(s.ev_sol1);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) return false;
@@ -262,16 +305,12 @@ bool retire(hm_server* sv) {
       q->res.resize(q->r);
       fill_results(ds, s.h_out, q->max_rank, q->res.data());
       complete(sv, q, HM_OK);
-    } else if (q->state == RState::ACTIVE && q->cancel) {
-      // stops between levels; the dataset's factor storage is left partly
-      // factorised and is overwritten by its next assembly
-      complete(sv, q, HM_ERR_CANCELLED);
     }
   }
   return true;
 }
 
-// Host phase part 2: admission in arrival order (see include/hmlik.h).
+// Admission in arrival order (see include/hmlik.h).
 bool admit_queued(hm_server* sv) {
   for (auto it = sv->queue.begin(); it != sv->queue.end();) {
     int k = -1;
@@ -304,81 +343,35 @@ void worker_main(hm_server* sv) {
     fail_all(sv, HM_ERR_DEVICE);
     return;
   }
-  std::vector<int> finishing;
   for (;;) {
-    if (!retire(sv) || !admit_queued(sv)) {
+    if (!progress(sv) || !admit_queued(sv)) {
       (void)hipGetLastError();
       fail_all(sv, HM_ERR_DEVICE);
       return;
     }
-    bool occupied = false, solving = false;
-    int32_t total = 0, members = 0;
-    finishing.clear();
-    for (int k = 0; k < sv->max_active; ++k) {
-      Slot& s = sv->slots[k];
-      sv->hseg[2 * k] = sv->hseg[2 * k + 1] = 0;
-      if (!s.req) continue;
-      occupied = true;
-      Request* q = s.req;
-      if (q->state == RState::SOLVING) solving = true;
-      if (q->state != RState::ACTIVE || s.factor_pending) continue;
-      const std::vector<int32_t>& lb = q->ds->level_begin;
-      const int32_t nlev = (int32_t)lb.size() - 1;
-      if (q->level >= nlev) continue;
-      sv->hseg[2 * k] = lb[q->level];
-      sv->hseg[2 * k + 1] = lb[q->level + 1];
-      total += lb[q->level + 1] - lb[q->level];
-      ++members;
-      if (++q->level == nlev) finishing.push_back(k);
-    }
+    int32_t admitted = 0;
+    for (const Slot& s : sv->slots) admitted += s.req != nullptr;
+    for (Slot& s : sv->slots)
+      if (s.req) s.req->stats.peak_batch = std::max(s.req->stats.peak_batch, admitted);
+    const bool occupied = admitted > 0;
     if (!occupied && sv->queue.empty() && sv->stop) return;
-    if (members == 0) {
-      // nothing to launch: poll a running solve or factorisation record, or
-      // wait for a submission
-      if (solving || occupied)
-        sv->cv_work.wait_for(lk, std::chrono::microseconds(200));
-      else
-        sv->cv_work.wait(lk);
-      continue;
-    }
-    for (int k = 0; k < sv->max_active; ++k) {
-      Request* q = sv->slots[k].req;
-      if (q && sv->hseg[2 * k + 1] > sv->hseg[2 * k]) {
-        ++q->stats.steps;
-        q->stats.peak_batch = std::max(q->stats.peak_batch, members);
-      }
-    }
-    // device phase: the lock is released so that submit, poll and cancel proceed
-    lk.unlock();
-    bool ok = hipMemcpyAsync(sv->dseg, sv->hseg, sizeof(int32_t) * 2 * sv->max_active, hipMemcpyHostToDevice,
-                             sv->st) == hipSuccess &&
-              launch_level_batch(sv->dD, sv->dseg, sv->max_active, total, NSLOTS, sv->st) == hipSuccess;
-    for (int k : finishing) ok = ok && enqueue_factor_end(sv, k);
-    ok = ok && hipStreamSynchronize(sv->st) == hipSuccess;
-    lk.lock();
-    if (!ok) {
-      (void)hipGetLastError();
-      fail_all(sv, HM_ERR_DEVICE);
-      return;
-    }
+    // poll the streams while requests run; otherwise sleep until a submission
+    if (occupied)
+      sv->cv_work.wait_for(lk, std::chrono::microseconds(200));
+    else
+      sv->cv_work.wait(lk);
   }
 }
 
 void free_server(hm_server* sv) {
   (void)hipSetDevice(sv->ctx->device);
-  if (sv->st) (void)hipStreamSynchronize(sv->st);
-  if (sv->st_solve) (void)hipStreamSynchronize(sv->st_solve);
-  for (Slot& s : sv->slots)
-    for (hipEvent_t e : {s.ev_fac, s.ev_sol0, s.ev_sol1})
+  for (Slot& s : sv->slots) {
+    if (s.st) (void)hipStreamSynchronize(s.st);
+    for (hipEvent_t e : {s.ev_chunk[0], s.ev_chunk[1], s.ev_fac, s.ev_sol0, s.ev_sol1})
       if (e) (void)hipEventDestroy(e);
-  if (sv->dD) (void)hipFree(sv->dD);
-  if (sv->dseg) (void)hipFree(sv->dseg);
-  if (sv->solve_ws) (void)hipFree(sv->solve_ws);
-  if (sv->hD) (void)hipHostFree(sv->hD);
-  if (sv->hseg) (void)hipHostFree(sv->hseg);
+    if (s.st) (void)hipStreamDestroy(s.st);
+  }
   if (sv->pinned) (void)hipHostFree(sv->pinned);
-  if (sv->st) (void)hipStreamDestroy(sv->st);
-  if (sv->st_solve) (void)hipStreamDestroy(sv->st_solve);
   (void)hipGetLastError();
   for (auto& kv : sv->reqs) delete kv.second;
   delete sv;
@@ -399,7 +392,7 @@ void server_forget_dataset(hm_server* sv, hm_dataset* ds) {
     }
   }
   for (Slot& s : sv->slots)
-    if (s.req && s.req->ds == ds) s.req->cancel = true;
+    if (s.req && s.req->ds == ds && s.req->state == RState::ACTIVE) s.req->cancel = true;
   sv->cv_work.notify_all();
   sv->cv_done.wait(lk, [&] { return !dataset_in_use(sv, ds) || sv->failed != HM_OK; });
   sv->last_use.erase(ds);
@@ -413,7 +406,7 @@ extern "C" {
 hm_status hm_server_create(hm_ctx* ctx, const hm_server_opts* opts, hm_server** out) {
   if (!ctx || !opts || !out) return HM_ERR_ARG;
   *out = nullptr;
-  if (opts->max_active < 1 || opts->max_active > 64 || opts->hbm_budget < 0) return HM_ERR_ARG;
+  if (opts->max_active < 1 || opts->max_active > 16 || opts->hbm_budget < 0) return HM_ERR_ARG;
   if (ctx->datasets.empty() || !ctx->ws) return HM_ERR_ARG;
   if (ctx->server.load()) return HM_ERR_BUSY;
   if (hipSetDevice(ctx->device) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
@@ -425,6 +418,7 @@ hm_status hm_server_create(hm_ctx* ctx, const hm_server_opts* opts, hm_server** 
   sv->ctx = ctx;
   sv->max_active = opts->max_active;
   sv->budget = opts->hbm_budget;
+  sv->grid = NSLOTS / opts->max_active;
   for (const hm_dataset* d : ctx->datasets) {
     sv->max_nblocks = std::max<int64_t>(sv->max_nblocks, (int64_t)d->tree.bk.size());
     sv->max_r = std::max(sv->max_r, d->r);
@@ -432,29 +426,21 @@ hm_status hm_server_create(hm_ctx* ctx, const hm_server_opts* opts, hm_server** 
   const int A = sv->max_active;
   sv->slots.resize(A);
   // per slot: abort flag, breakdown key, ranks, solve output (8-byte aligned pieces)
-  const size_t per = 16 + 8 * (size_t)((sv->max_nblocks + 1) / 2) + 8 * (size_t)(1 + std::max(sv->max_r, 1));
-  bool ok = hipStreamCreateWithFlags(&sv->st, hipStreamNonBlocking) == hipSuccess &&
-            hipStreamCreateWithFlags(&sv->st_solve, hipStreamNonBlocking) == hipSuccess &&
-            hipMalloc((void**)&sv->dD, sizeof(DevData) * A) == hipSuccess &&
-            hipMalloc((void**)&sv->dseg, sizeof(int32_t) * 2 * A) == hipSuccess &&
-            hipMalloc((void**)&sv->solve_ws, sizeof(double) * ctx->ws_stride) == hipSuccess &&
-            hipHostMalloc((void**)&sv->hD, sizeof(DevData) * A, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&sv->hseg, sizeof(int32_t) * 2 * A, hipHostMallocDefault) == hipSuccess &&
-            hipHostMalloc((void**)&sv->pinned, per * A, hipHostMallocDefault) == hipSuccess;
+  const size_t rank_bytes = 8 * (size_t)((sv->max_nblocks + 1) / 2);
+  const size_t per = 16 + rank_bytes + 8 * (size_t)(1 + std::max(sv->max_r, 1));
+  bool ok = hipHostMalloc((void**)&sv->pinned, per * A, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < A; ++k) {
     Slot& s = sv->slots[k];
     char* base = sv->pinned + per * k;
     s.h_abort = (int32_t*)base;
     s.h_key = (unsigned long long*)(base + 8);
     s.h_rank = (int32_t*)(base + 16);
-    s.h_out = (double*)(base + 16 + 8 * ((sv->max_nblocks + 1) / 2));
-    ok = hipEventCreate(&s.ev_fac) == hipSuccess && hipEventCreate(&s.ev_sol0) == hipSuccess &&
+    s.h_out = (double*)(base + 16 + rank_bytes);
+    s.ws = ctx->ws + (int64_t)k * sv->grid * ctx->ws_stride;
+    ok = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreate(&s.ev_chunk[0]) == hipSuccess && hipEventCreate(&s.ev_chunk[1]) == hipSuccess &&
+         hipEventCreate(&s.ev_fac) == hipSuccess && hipEventCreate(&s.ev_sol0) == hipSuccess &&
          hipEventCreate(&s.ev_sol1) == hipSuccess;
-  }
-  if (ok) {
-    std::memset(sv->hD, 0, sizeof(DevData) * A);
-    std::memset(sv->hseg, 0, sizeof(int32_t) * 2 * A);
-    ok = hipMemcpy(sv->dD, sv->hD, sizeof(DevData) * A, hipMemcpyHostToDevice) == hipSuccess;
   }
   if (!ok) {
     (void)hipGetLastError();
