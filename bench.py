@@ -39,7 +39,7 @@ same generator (seeds 31, 41, ...), each with its schedule tuned (untimed), and
 R requests submitted at once, round-robin over the datasets, at theta values
 perturbed around the workload's theta as a Nelder-Mead simplex would be (seeded).
 The server keeps up to A requests on the device (default: one per dataset), each on a
-stream of its own.
+stream of its own; GPU_MAX_HW_QUEUES defaults to A + 1 (at least 4) for this form.
 value = completed evaluations / wall time from the first submission to the last
 result; latency percentiles are per request (submission to result).
 """
@@ -233,6 +233,12 @@ def main():
 
 def served(args):
     """The served form: continuous batching of evaluations over resident datasets."""
+    if args.max_active <= 0:
+        args.max_active = min(16, args.datasets)
+    # every batch slot's stream needs a hardware queue of its own (plus one for
+    # the default stream); read by the HIP runtime when it initialises, which
+    # happens at the first library call below
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(4, args.max_active + 1)))
     import numpy as np
 
     from paper_1709_04419_amd import hmlik
@@ -253,8 +259,6 @@ def served(args):
     rng = np.random.default_rng(5200)
     base = np.log(np.array(THETA))
     thetas = [tuple(np.exp(base + rng.uniform(-0.1, 0.1, 3))) for _ in range(args.requests)]
-    if args.max_active <= 0:
-        args.max_active = min(16, args.datasets)
     sv = hmlik.Server(ctx, max_active=args.max_active)
     t0 = time.perf_counter()
     tickets = [sv.submit(dss[j % args.datasets], thetas[j], NUGGET, eps, 0) for j in range(args.requests)]
@@ -294,6 +298,7 @@ def served(args):
         "form": "served",
         "config": {"workload": ("basin256k" if n == 256000 else f"basin{n}") + "_served", "n": n,
                    "datasets": args.datasets, "requests": args.requests, "max_active": args.max_active,
+                   "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
                    "points": "basin_clusters(seeds 31, 41, ...)", "eps": eps, "leaf_size": LEAF, "eta": ETA,
                    "theta": "exp(log(1, 0.1, 0.325) + U(-0.1, 0.1)^3), seed 5200", "nugget": NUGGET,
                    "blocks": info["nblocks"], "tasks": info["ntasks"],

@@ -238,6 +238,13 @@ hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const dou
  * datasets that no admitted request uses, least recently used first.  A
  * request that cannot get room waits, and so do the requests after it (no
  * later request overtakes a request held back for memory).
+ *
+ * Overlap needs one hardware queue per stream: the HIP runtime maps streams to
+ * GPU_MAX_HW_QUEUES hardware queues (4 by default) and streams that share a
+ * queue run one after the other.  With the context's stream counted, set
+ * GPU_MAX_HW_QUEUES >= max_active + 1 in the environment before the process
+ * first uses HIP (measured at n = 256k: four requests at once took 72-77 s each
+ * with 8 queues, while two of them took 145 s with 4).
  */
 typedef struct {
   int32_t max_active; /* batch slots (requests on the device at once), 1..16; each slot's
