@@ -39,7 +39,7 @@ same generator (seeds 31, 41, ...), each with its schedule tuned (untimed), and
 R requests submitted at once, round-robin over the datasets, at theta values
 perturbed around the workload's theta as a Nelder-Mead simplex would be (seeded).
 The server keeps up to A requests on the device (default: one per dataset), each on a
-stream of its own; GPU_MAX_HW_QUEUES defaults to A + 1 (at least 4) for this form.
+stream of its own; GPU_MAX_HW_QUEUES is raised to A + 1 (at least 4) for this form.
 value = completed evaluations / wall time from the first submission to the last
 result; latency percentiles are per request (submission to result).
 """
@@ -237,8 +237,14 @@ def served(args):
         args.max_active = min(16, args.datasets)
     # every batch slot's stream needs a hardware queue of its own (plus one for
     # the default stream); read by the HIP runtime when it initialises, which
-    # happens at the first library call below
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(max(4, args.max_active + 1)))
+    # happens at the first library call below.  A larger setting is kept.
+    need = max(4, args.max_active + 1)
+    try:
+        have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+    except ValueError:
+        have = 0
+    if have < need:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(need)
     import numpy as np
 
     from paper_1709_04419_amd import hmlik
