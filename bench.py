@@ -12,6 +12,7 @@ vector (the cost of an evaluation does not depend on Z).
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu-baseline]
                     [--no-tune] [--calib-copy-gib G]
     python bench.py --form served [--datasets D] [--requests R] [--max-active A] [--n N]
+    python bench.py --form batched [--replicates M]
 
 Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
 with the dataset (locations, trees, task schedule, Z) resident on the device
@@ -40,6 +41,12 @@ R requests submitted at once, round-robin over the datasets, at theta values
 perturbed around the workload's theta as a Nelder-Mead simplex would be (seeded).
 The server keeps up to A requests on the device (default: one per dataset), each on a
 stream of its own; GPU_MAX_HW_QUEUES is raised to A + 1 (at least 4) for this form.
+
+--form batched measures one hm_loglik_batch call over M Monte-Carlo replicates
+of uneven size: replicate r has n_r ~ U{4000..64000} points uniform on [0,1]^2
+(seed 4000 + r), theta = (1, 0.1, 0.5), nugget 1e-6, eps 1e-7, leaf 64, and its
+own Z (seeded).  value = replicates / wall time of the call (min(M, 16) on the
+device at once).
 value = completed evaluations / wall time from the first submission to the last
 result; latency percentiles are per request (submission to result).
 """
@@ -121,7 +128,10 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
-    ap.add_argument("--form", choices=("plain", "served"), default="plain")
+    ap.add_argument("--form", choices=("plain", "served", "batched"), default="plain")
+    ap.add_argument("--replicates", type=int, default=16)
+    ap.add_argument("--compare-sequential", action="store_true",
+                    help="batched form: also time the replicates one after another (before the batch)")
     ap.add_argument("--datasets", type=int, default=2)
     ap.add_argument("--requests", type=int, default=4)
     ap.add_argument("--max-active", type=int, default=0, help="batch slots (default: one per dataset)")
@@ -133,6 +143,8 @@ def main():
 
     if args.form == "served":
         return served(args)
+    if args.form == "batched":
+        return batched(args)
 
     import numpy as np
     import torch
@@ -231,20 +243,94 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def served(args):
-    """The served form: continuous batching of evaluations over resident datasets."""
-    if args.max_active <= 0:
-        args.max_active = min(16, args.datasets)
-    # every batch slot's stream needs a hardware queue of its own (plus one for
-    # the default stream); read by the HIP runtime when it initialises, which
-    # happens at the first library call below.  A larger setting is kept.
-    need = max(4, args.max_active + 1)
+def raise_hw_queues(slots: int) -> int:
+    """Every batch slot's stream needs a hardware queue of its own, plus one for
+    the default stream.  The HIP runtime reads GPU_MAX_HW_QUEUES when it
+    initialises (at the first library call); a larger setting is kept."""
+    need = max(4, slots + 1)
     try:
         have = int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
     except ValueError:
         have = 0
     if have < need:
         os.environ["GPU_MAX_HW_QUEUES"] = str(need)
+    return int(os.environ["GPU_MAX_HW_QUEUES"])
+
+
+def batched(args):
+    """The batched form: uneven Monte-Carlo replicates in one hm_loglik_batch call."""
+    m = args.replicates
+    raise_hw_queues(min(16, m))
+    import numpy as np
+
+    from paper_1709_04419_amd import hmlik
+    from paper_1709_04419_amd import workloads as wl
+
+    theta, nug, eps = (1.0, 0.1, 0.5), 1e-6, args.eps
+    ctx = hmlik.Context(0)
+    dss, ns = [], []
+    for r in range(m):
+        n_r = int(np.random.default_rng(4000 + r).integers(4000, 64001))
+        ds = hmlik.Dataset(ctx, wl.uniform_square(n_r, 4000 + r), LEAF, ETA)
+        ds.set_z(wl.standard_normal(n_r, 1, 4200 + r))
+        dss.append(ds)
+        ns.append(n_r)
+    log(f"{m} replicates, n from {min(ns)} to {max(ns)} (sum {sum(ns)})")
+    seq = None
+    if args.compare_sequential:
+        seq_res = []
+        t0 = time.perf_counter()
+        for r, ds in enumerate(dss):
+            seq_res.append(ds.loglik(theta, nug, eps))
+            log(f"replicate {r + 1}/{m} alone: n={ns[r]}, {seq_res[-1]['t_factor'][0]:.2f} s factor")
+        seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = hmlik.loglik_batch(ctx, dss, [theta] * m, [nug] * m, eps)
+    wall = time.perf_counter() - t0
+    fac = [float(r["t_factor"][0]) for r in res]
+    flops = sum(ds.factor_flops() for ds in dss)
+    achieved = flops / wall / 1e12
+    out = {
+        "metric": METRIC,
+        "value": m / wall,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": m,
+        "warmup": 0,
+        "ms_per_step": wall / m * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "form": "batched",
+        "config": {"workload": f"mc_replicates{m}", "replicates": m, "n_min": min(ns), "n_max": max(ns),
+                   "n_sum": sum(ns), "points": "uniform [0,1]^2, replicate r: n_r ~ U{4000..64000} and points "
+                   "from seed 4000 + r", "theta": {"sigma2": 1.0, "ell": 0.1, "nu": 0.5}, "nugget": nug,
+                   "eps": eps, "leaf_size": LEAF, "eta": ETA, "slots": min(16, m),
+                   "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]), "schedule": "longest-path levels"},
+        "batch_wall_s": wall,
+        "sequential_wall_s": seq,
+        "bitwise_equal_to_sequential": (None if seq is None else
+                                        all(np.array_equal(a["loglik"], b["loglik"]) for a, b in zip(res, seq_res))),
+        "replicate_factor_s": {"min": min(fac), "max": max(fac)},
+        "status": [int(r["status"][0]) for r in res],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_level on one stream per replicate (whole-call average: algorithmic flops of "
+                               "all factorisations / wall time)"},
+    }
+    for ds in dss:
+        ds.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def served(args):
+    """The served form: continuous batching of evaluations over resident datasets."""
+    if args.max_active <= 0:
+        args.max_active = min(16, args.datasets)
+    raise_hw_queues(args.max_active)
     import numpy as np
 
     from paper_1709_04419_amd import hmlik
