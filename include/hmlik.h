@@ -291,7 +291,8 @@ hm_status hm_server_poll(hm_server *sv, uint64_t ticket, int32_t wait, hm_result
 hm_status hm_server_cancel(hm_server *sv, uint64_t ticket);
 
 /* Cancels queued requests, lets admitted ones finish, joins the worker and
- * frees the server; the context's direct entry points work again. */
+ * frees the server; the context's direct entry points work again.  Must not
+ * overlap any other call on sv (unretired tickets become invalid). */
 void hm_server_destroy(hm_server *sv);
 
 const char *hm_status_string(hm_status s);
