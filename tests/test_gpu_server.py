@@ -178,3 +178,19 @@ def test_cancel_busy_and_destroy(H):
         assert _same(r, ref[0])
     finally:
         ctx.close()
+
+
+def test_batch_more_datasets_than_slots(H):
+    """hm_loglik_batch with 18 datasets: at most 16 are on the device at once,
+    the rest wait for a slot; every result is bitwise its hm_loglik alone."""
+    ctx = H.Context(0)
+    try:
+        specs = [(300 + 37 * i, ("uniform", 700 + i), 32) for i in range(18)]
+        dss = _datasets(H, ctx, specs, r=1)
+        thetas = [(1.0, 0.05 + 0.01 * i, 0.5 + 0.05 * (i % 5)) for i in range(18)]
+        ref = [ds.loglik(th, 1e-6, 1e-7) for ds, th in zip(dss, thetas)]
+        res = H.loglik_batch(ctx, dss, thetas, [1e-6] * 18, 1e-7)
+        for i, (a, b) in enumerate(zip(res, ref)):
+            assert _same(a, b), i
+    finally:
+        ctx.close()
