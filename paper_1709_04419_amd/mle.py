@@ -1,0 +1,160 @@
+"""Maximum-likelihood estimation of theta = (sigma^2, ell, nu) on top of the
+H-matrix likelihood of eq. (4) (Section 3.1).
+
+The paper maximises L~(theta) with the derivative-free Brent-Dekker method
+(Section 3.1), a one-dimensional search.  For the three Matern parameters
+together this module uses the Nelder-Mead simplex search (Nelder and Mead,
+Computer Journal 7, 1965), also derivative-free, on x = log(theta), which
+keeps every parameter positive.  Coefficients: reflection 1, expansion 2,
+contraction 1/2, shrink 1/2.
+
+The search is written as a generator that yields the point to evaluate and
+receives -L~ there, so that one driver can advance many independent searches
+together: `fit` runs one search with hm_loglik, `fit_many` runs one search
+per dataset (e.g. Monte-Carlo replicates) through a request server, with one
+evaluation of every unfinished search on the device at once.  Every step of
+each evaluation runs in the library's kernels; this module only steers.
+"""
+from __future__ import annotations
+
+import math
+from typing import Callable, Generator, List, Sequence
+
+import numpy as np
+
+ALPHA, GAMMA, RHO, SIGMA = 1.0, 2.0, 0.5, 0.5
+
+
+def nelder_mead(x0: Sequence[float], step: float = 0.1, ftol: float = 1e-7, xtol: float = 1e-5,
+                max_evals: int = 400) -> Generator[np.ndarray, float, dict]:
+    """Minimises f from x0.  Yields points, receives f there; returns
+    dict(x, f, evals, converged).  Stops when the spread of f over the
+    simplex is at most ftol * (1 + |f_best|) and every vertex is within xtol
+    (max norm) of the best one, or after max_evals evaluations.  A
+    non-finite f counts as +infinity (the point is never kept as best)."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    d = x0.size
+    evals = 0
+
+    def value(v):
+        return v if math.isfinite(v) else math.inf
+
+    pts = [x0.copy()]
+    for i in range(d):
+        p = x0.copy()
+        p[i] += step
+        pts.append(p)
+    fs = []
+    for p in pts:
+        fs.append(value((yield p.copy())))
+        evals += 1
+    while True:
+        order = np.argsort(fs, kind="stable")
+        pts = [pts[i] for i in order]
+        fs = [fs[i] for i in order]
+        spread = fs[-1] - fs[0] if math.isfinite(fs[-1]) else math.inf
+        size = max(float(np.max(np.abs(p - pts[0]))) for p in pts[1:])
+        if (spread <= ftol * (1.0 + abs(fs[0])) and size <= xtol) or evals >= max_evals:
+            return dict(x=pts[0], f=fs[0], evals=evals, converged=evals < max_evals)
+        centroid = np.mean(pts[:-1], axis=0)
+        xr = centroid + ALPHA * (centroid - pts[-1])
+        fr = value((yield xr.copy()))
+        evals += 1
+        if fr < fs[0]:
+            xe = centroid + GAMMA * (xr - centroid)
+            fe = value((yield xe.copy()))
+            evals += 1
+            pts[-1], fs[-1] = (xe, fe) if fe < fr else (xr, fr)
+            continue
+        if fr < fs[-2]:
+            pts[-1], fs[-1] = xr, fr
+            continue
+        # contraction: outside if the reflected point beats the worst, else inside
+        if fr < fs[-1]:
+            xc = centroid + RHO * (xr - centroid)
+        else:
+            xc = centroid + RHO * (pts[-1] - centroid)
+        fc = value((yield xc.copy()))
+        evals += 1
+        if fc < min(fr, fs[-1]):
+            pts[-1], fs[-1] = xc, fc
+            continue
+        # shrink towards the best vertex
+        for i in range(1, d + 1):
+            pts[i] = pts[0] + SIGMA * (pts[i] - pts[0])
+            fs[i] = value((yield pts[i].copy()))
+            evals += 1
+
+
+def minimise(f: Callable[[np.ndarray], float], x0, **kw) -> dict:
+    """Runs nelder_mead on a plain function (host objective)."""
+    gen = nelder_mead(x0, **kw)
+    x = next(gen)
+    try:
+        while True:
+            x = gen.send(f(x))
+    except StopIteration as stop:
+        return stop.value
+
+
+def _objective(res) -> float:
+    """-L~ summed over the columns of Z; +inf after a breakdown (not SPD)."""
+    if int(res["status"][0]) != 0:
+        return math.inf
+    return -float(np.sum(res["loglik"]))
+
+
+def _theta(x) -> tuple:
+    """theta = exp(x), or None where the library would reject it (overflow to
+    inf or 0, or nu above the largest order the K_nu routine accepts, 50)."""
+    th = np.exp(np.asarray(x, dtype=np.float64))
+    if not (np.all(np.isfinite(th)) and np.all(th > 0.0) and th[2] <= 50.0):
+        return None
+    return tuple(float(v) for v in th)
+
+
+def fit(ds, theta0, nugget: float, eps: float = 1e-7, rank: int = 0, **kw) -> dict:
+    """Maximum-likelihood estimate of theta for one hmlik.Dataset (with Z set);
+    returns dict(theta, loglik, evals, converged)."""
+    gen = nelder_mead(np.log(np.asarray(theta0, dtype=np.float64)), **kw)
+    x = next(gen)
+    try:
+        while True:
+            th = _theta(x)
+            x = gen.send(math.inf if th is None else _objective(ds.loglik(th, nugget, eps, rank)))
+    except StopIteration as stop:
+        r = stop.value
+    return dict(theta=tuple(np.exp(r["x"])), loglik=-r["f"], evals=r["evals"], converged=r["converged"])
+
+
+def fit_many(server, datasets: List, theta0s, nugget: float,
+             eps: float = 1e-7, rank: int = 0, **kw) -> List[dict]:
+    """One search per hmlik.Dataset, advanced together through an
+    hmlik.Server (give it a slot per dataset): each round submits the
+    pending point of every unfinished search to the server and feeds back the
+    results.  Each search sees exactly the values `fit` would, so the
+    estimates equal those of separate `fit` calls."""
+    gens, pending, out = [], [], [None] * len(datasets)
+    for th in theta0s:
+        g = nelder_mead(np.log(np.asarray(th, dtype=np.float64)), **kw)
+        gens.append(g)
+        pending.append(next(g))
+    live = list(range(len(datasets)))
+    while live:
+        tickets = {}
+        for i in live:
+            th = _theta(pending[i])
+            if th is not None:
+                tickets[i] = server.submit(datasets[i], th, nugget, eps, rank)
+        still = []
+        for i in live:
+            f = _objective(server.poll(tickets[i], wait=True)) if i in tickets else math.inf
+            try:
+                pending[i] = gens[i].send(f)
+                still.append(i)
+            except StopIteration as stop:
+                r = stop.value
+                out[i] = dict(theta=tuple(np.exp(r["x"])), loglik=-r["f"], evals=r["evals"],
+                              converged=r["converged"])
+        live = still
+    return out

@@ -1,0 +1,62 @@
+"""GPU test of the maximum-likelihood driver (paper_1709_04419_amd/mle.py):
+the estimate from the device H-likelihood (eq. 4) agrees with the same
+Nelder-Mead search run on the oracle's dense likelihood (eq. 1), and the
+searches advanced together through a request server give exactly the
+estimates of separate searches."""
+import numpy as np
+import pytest
+
+from oracle.dense import dense_factor, dense_loglik
+from paper_1709_04419_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+THETA_TRUE, NUGGET = (1.0, 0.1, 0.5), 1e-6
+THETA0 = (1.4, 0.07, 0.7)
+KW = dict(step=0.1, ftol=1e-10, xtol=1e-5, max_evals=600)
+
+
+def _data(n, seed):
+    P = wl.uniform_square(n, seed)
+    W = wl.standard_normal(n, 1, seed + 1)
+    return P, dense_factor(P, THETA_TRUE, NUGGET) @ W
+
+
+def test_mle_matches_dense_oracle():
+    from paper_1709_04419_amd import hmlik, mle
+    P, Z = _data(300, 51)
+    ref = mle.minimise(lambda x: -float(dense_loglik(P, Z, tuple(np.exp(x)), NUGGET)[0][0]),
+                       np.log(THETA0), **KW)
+    ctx = hmlik.Context(0)
+    try:
+        ds = hmlik.Dataset(ctx, P, 32, 2.0)
+        ds.set_z(Z)
+        g = mle.fit(ds, THETA0, NUGGET, eps=1e-10, **KW)
+    finally:
+        ctx.close()
+    assert g["converged"] and ref["f"] < np.inf
+    th_ref = np.exp(ref["x"])
+    # the maximised likelihood agrees, and so does the maximiser (flat directions aside)
+    l_at_g = float(dense_loglik(P, Z, g["theta"], NUGGET)[0][0])
+    assert abs(l_at_g - (-ref["f"])) <= 1e-6 * abs(ref["f"])
+    np.testing.assert_allclose(g["theta"], th_ref, rtol=2e-2)
+
+
+def test_fit_many_equals_separate_fits():
+    from paper_1709_04419_amd import hmlik, mle
+    ctx = hmlik.Context(0)
+    try:
+        dss = []
+        for s in (61, 71, 81):
+            P, Z = _data(500, s)
+            ds = hmlik.Dataset(ctx, P, 32, 2.0)
+            ds.set_z(Z)
+            dss.append(ds)
+        kw = dict(KW, max_evals=150)
+        sep = [mle.fit(ds, THETA0, NUGGET, eps=1e-8, **kw) for ds in dss]
+        with hmlik.Server(ctx, max_active=3) as sv:
+            tog = mle.fit_many(sv, dss, [THETA0] * 3, NUGGET, eps=1e-8, **kw)
+        for a, b in zip(sep, tog):
+            assert a["theta"] == b["theta"] and a["loglik"] == b["loglik"] and a["evals"] == b["evals"]
+    finally:
+        ctx.close()
