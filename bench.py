@@ -13,6 +13,7 @@ vector (the cost of an evaluation does not depend on Z).
                     [--no-tune] [--calib-copy-gib G]
     python bench.py --form served [--datasets D] [--requests R] [--max-active A] [--n N]
     python bench.py --form batched [--replicates M]
+    python bench.py --form stream [--datasets D] [--requests R] [--rate L] [--budget-gib B]
 
 Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
 with the dataset (locations, trees, task schedule, Z) resident on the device
@@ -41,14 +42,25 @@ R requests submitted at once, round-robin over the datasets, at theta values
 perturbed around the workload's theta as a Nelder-Mead simplex would be (seeded).
 The server keeps up to A requests on the device (default: one per dataset), each on a
 stream of its own; GPU_MAX_HW_QUEUES is raised to A + 1 (at least 4) for this form.
+value = completed evaluations / wall time from the first submission to the last
+result; latency percentiles are per request (submission to result).
 
 --form batched measures one hm_loglik_batch call over M Monte-Carlo replicates
 of uneven size: replicate r has n_r ~ U{4000..64000} points uniform on [0,1]^2
 (seed 4000 + r), theta = (1, 0.1, 0.5), nugget 1e-6, eps 1e-7, leaf 64, and its
 own Z (seeded).  value = replicates / wall time of the call (min(M, 16) on the
 device at once).
-value = completed evaluations / wall time from the first submission to the last
-result; latency percentiles are per request (submission to result).
+
+--form stream serves an open-loop request stream: D resident datasets of the
+basin generator with n_i = 16000 * 16^(i / (D - 1)) (16k to 256k, seeds
+5000 + i, schedules not tuned); R requests arriving as a Poisson process of
+rate L per second (seed 5100), each for a dataset drawn uniformly (seed 5101)
+at the next theta of that dataset's simulated Nelder-Mead trace (the search of
+the MLE driver run on a quadratic surrogate in log theta around (1, 0.1, 0.5),
+seed 5200 + i); the server holds at most B GiB of factor storage (releasing
+idle datasets' storage to admit others) and one slot per dataset.
+value = completed requests / (last completion - first arrival); latency is
+per request, from arrival to result.
 """
 from __future__ import annotations
 
@@ -128,7 +140,9 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
-    ap.add_argument("--form", choices=("plain", "served", "batched"), default="plain")
+    ap.add_argument("--form", choices=("plain", "served", "batched", "stream"), default="plain")
+    ap.add_argument("--rate", type=float, default=0.25)
+    ap.add_argument("--budget-gib", type=float, default=96.0)
     ap.add_argument("--replicates", type=int, default=16)
     ap.add_argument("--compare-sequential", action="store_true",
                     help="batched form: also time the replicates one after another (before the batch)")
@@ -145,6 +159,8 @@ def main():
         return served(args)
     if args.form == "batched":
         return batched(args)
+    if args.form == "stream":
+        return stream(args)
 
     import numpy as np
     import torch
@@ -319,6 +335,110 @@ def batched(args):
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": "k_level on one stream per replicate (whole-call average: algorithmic flops of "
                                "all factorisations / wall time)"},
+    }
+    for ds in dss:
+        ds.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def nm_trace(seed: int, length: int):
+    """theta values a Nelder-Mead search proposes on a quadratic surrogate in
+    log theta (centre and scales drawn from `seed`), in proposal order."""
+    import numpy as np
+
+    from paper_1709_04419_amd.mle import nelder_mead
+    rng = np.random.default_rng(seed)
+    centre = np.log([1.0, 0.1, 0.5]) + rng.uniform(-0.1, 0.1, 3)
+    scale = rng.uniform(0.3, 1.0, 3)
+    gen = nelder_mead(centre + rng.uniform(-0.2, 0.2, 3), step=0.1, ftol=0.0, xtol=0.0, max_evals=10 ** 6)
+    out, x = [], next(gen)
+    while len(out) < length:
+        out.append(tuple(float(v) for v in np.exp(x)))
+        x = gen.send(float(np.sum(((x - centre) / scale) ** 2)))
+    return out
+
+
+def stream(args):
+    """Open-loop Poisson request stream over resident datasets of different n."""
+    D = max(2, args.datasets)
+    raise_hw_queues(D)
+    import numpy as np
+
+    from paper_1709_04419_amd import hmlik
+    from paper_1709_04419_amd import workloads as wl
+
+    sizes = [int(round(16000 * 16 ** (i / (D - 1)))) for i in range(D)]
+    ctx = hmlik.Context(0)
+    dss = []
+    for i, n_i in enumerate(sizes):
+        ds = hmlik.Dataset(ctx, wl.basin_clusters(n_i, 5000 + i), LEAF, ETA)
+        ds.set_z(wl.standard_normal(n_i, 1, 5050 + i))
+        ds.release()                      # factor storage is attached on admission
+        dss.append(ds)
+    fb = [ds.footprint()["factor_bytes"] for ds in dss]
+    log(f"{D} datasets, n = {sizes}; factor storage {sum(fb) / 2**30:.1f} GiB in all")
+    traces = [nm_trace(5200 + i, args.requests) for i in range(D)]
+    arrivals = np.cumsum(np.random.default_rng(5100).exponential(1.0 / args.rate, args.requests))
+    which = np.random.default_rng(5101).integers(0, D, args.requests)
+    sv = hmlik.Server(ctx, max_active=D, hbm_budget=int(args.budget_gib * 2 ** 30))
+    nxt = [0] * D
+    t0 = time.perf_counter()
+    tickets, res, done_at = [], {}, {}
+    last, j = t0, 0
+    while len(res) < args.requests:
+        now = time.perf_counter() - t0
+        while j < args.requests and arrivals[j] <= now:
+            d = int(which[j])
+            th = traces[d][nxt[d]]
+            nxt[d] += 1
+            tickets.append((j, d, sv.submit(dss[d], th, NUGGET, args.eps, 0)))
+            j += 1
+        for (q, d, t) in tickets:
+            if q not in res:
+                r = sv.poll(t)
+                if r is not None:
+                    res[q] = (d, r)
+                    done_at[q] = time.perf_counter() - t0
+        if time.perf_counter() - last > 30:
+            last = time.perf_counter()
+            log(f"{j} arrived, {len(res)} done, {last - t0:.0f} s")
+        time.sleep(0.005)
+    sv.close()
+    lat = np.array([res[q][1]["t_latency"] for q in range(args.requests)]) * 1e3
+    span = max(done_at.values()) - arrivals[0]
+    ok = sum(1 for q in res if res[q][1]["request_status"] in (hmlik.HM_OK, hmlik.HM_ERR_NOT_SPD))
+    by_n = {}
+    for d in range(D):
+        v = [res[q][1]["t_latency"] * 1e3 for q in res if res[q][0] == d]
+        if v:
+            by_n[str(sizes[d])] = {"requests": len(v), "latency_ms_p50": float(np.median(v))}
+    out = {
+        "metric": METRIC,
+        "value": ok / span,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": 0,
+        "ms_per_step": span / args.requests * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "form": "stream",
+        "config": {"workload": f"basin16k-256k_stream{D}", "sizes": sizes, "requests": args.requests,
+                   "rate_per_s": args.rate, "hbm_budget_gib": args.budget_gib,
+                   "factor_storage_gib": [round(b / 2 ** 30, 2) for b in fb], "slots": D,
+                   "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]), "eps": args.eps, "leaf_size": LEAF,
+                   "eta": ETA, "nugget": NUGGET, "schedule": "longest-path levels",
+                   "theta": "Nelder-Mead proposals on a quadratic surrogate around (1, 0.1, 0.5), seeds 5200+i"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "by_n": by_n,
+        "queue_ms_p50": float(np.percentile([res[q][1]["t_queue"] * 1e3 for q in res], 50)),
+        "peak_batch": int(max(res[q][1]["peak_batch"] for q in res)),
+        "status": sorted({int(res[q][1]["request_status"]) for q in res}),
+        "attached_at_end": [bool(ds.footprint()["attached"]) for ds in dss],
     }
     for ds in dss:
         ds.close()
