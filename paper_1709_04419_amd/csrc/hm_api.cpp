@@ -386,7 +386,10 @@ hm_status hm_dataset_footprint(const hm_dataset* ds, int64_t* resident_bytes, in
     *resident_bytes = s;
   }
   if (factor_bytes) *factor_bytes = (int64_t)ds->store_bytes;
-  if (attached) *attached = ds->store != nullptr;
+  if (attached) {
+    hm_server* sv = ds->ctx->server.load();
+    *attached = sv ? server_store_attached(sv, ds) : ds->store != nullptr;
+  }
   return HM_OK;
 }
 

@@ -91,5 +91,8 @@ void fill_results(const hm_dataset* ds, const double* res, int32_t max_rank, hm_
 // cancels the server's queued requests on `ds` and waits until none of its
 // requests is on the device (before the dataset is destroyed)
 void server_forget_dataset(hm_server* sv, hm_dataset* ds);
+// whether ds has factor storage attached, read under the server's lock (the
+// worker attaches and releases storage while the server runs)
+bool server_store_attached(hm_server* sv, const hm_dataset* ds);
 
 }  // namespace hm_int

@@ -163,10 +163,9 @@ bool make_room(hm_server* sv, const hm_dataset* keep, int64_t need) {
 }
 
 // The dataset's descriptor with the slot's workspace share.
-DevData slot_view(const hm_server* sv, const Slot& s) {
+DevData slot_view(const Slot& s) {
   DevData D = s.req->ds->D;
   D.ws = s.ws;
-  (void)sv;
   return D;
 }
 
@@ -196,7 +195,7 @@ bool enqueue_chunk(hm_server* sv, int k) {
   hm_dataset* ds = s.req->ds;
   const std::vector<int32_t>& lb = ds->level_begin;
   const int32_t nlev = (int32_t)lb.size() - 1;
-  const DevData D = slot_view(sv, s);
+  const DevData D = slot_view(s);
   const int32_t l0 = s.next_level, l1 = std::min(nlev, l0 + CHUNK_LEVELS);
   if (launch_factor_levels(D, lb.data(), l0, l1, l0 == 0, sv->grid, s.st) != hipSuccess) return false;
   s.next_level = l1;
@@ -239,7 +238,7 @@ bool admit(hm_server* sv, Request* q, int k) {
 bool enqueue_solve(hm_server* sv, int k) {
   Slot& s = sv->slots[k];
   hm_dataset* ds = s.req->ds;
-  const DevData D = slot_view(sv, s);
+  const DevData D = slot_view(s);
   return hipEventRecord(s.ev_sol0, s.st) == hipSuccess &&
          launch_solve(D, ds->d_Z, ds->d_perm, ds->r, ds->d_W, ds->d_diag_ids,
                       (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, s.st) == hipSuccess &&
@@ -380,6 +379,11 @@ void free_server(hm_server* sv) {
 }  // namespace
 
 namespace hm_int {
+
+bool server_store_attached(hm_server* sv, const hm_dataset* ds) {
+  std::lock_guard<std::mutex> lk(sv->mu);
+  return ds->store != nullptr;
+}
 
 void server_forget_dataset(hm_server* sv, hm_dataset* ds) {
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -536,9 +540,9 @@ void hm_server_destroy(hm_server* sv) {
     sv->cv_work.notify_all();
   }
   if (sv->worker.joinable()) sv->worker.join();
-  hm_ctx* ctx = sv->ctx;
+  // every request has finished; the context's direct calls may run again
+  sv->ctx->server.store(nullptr);
   free_server(sv);
-  ctx->server.store(nullptr);
 }
 
 }  // extern "C"
