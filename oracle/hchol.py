@@ -42,6 +42,8 @@ Cholesky with deferred updates:
                         -> the product [U, -X_1, ...][V, Y_1, ...]^T is truncated
                            (lowrank.truncate); the accumulation is truncated early
                            whenever its rank would exceed R_ACC.
+  Every truncation reports whether the K_MAX rank cap bound (Stats.capped and
+  the result's rank_capped count).
 
 The forward solve uses the same recursion (dense triangular solves at the
 diagonal leaves, z2 -= L21 v1 through the blocks of L21).  log|C~| sums the
@@ -66,13 +68,24 @@ from .htree import DENSE, LOWRANK, NODE, BlockTree, ClusterTree
 from .lowrank import K_MAX, aca, truncate, truncate_dense
 from .matern import covariance_block
 
-# Largest rank an accumulation of updates may reach before it is truncated.
+# The paper fixes what a flush must produce (the formatted sum, truncated to
+# accuracy eps or rank k: Section 2.1, Remark 2.4) but not when the truncations
+# happen; the two constants below are that choice.  Both only decide how often
+# the sum is re-truncated, so every setting approximates the same matrix within
+# the method's error (tests/test_oracle_hchol.py checks Theorem 1 for other
+# settings too).
+#
+# Largest rank an accumulation of updates may reach before it is truncated: the
+# same cap as a single block (K_MAX), so an accumulation never holds more than
+# two blocks' worth of columns.
 R_ACC = 64
 # A low-rank block whose row and column clusters both hold at most
 # DENSE_FLUSH * n_min points takes its pending updates on the explicit matrix
 # (it is no larger than a 4 x 4 array of dense leaves) and is truncated once:
 # the best approximation of the exact sum (Remark 2.4's truncation applied to
-# the formatted sum as a whole).
+# the formatted sum as a whole).  Such a block receives terms of rank up to
+# n_min (products of dense leaves), for which the factored form would hold more
+# columns than the block has rows.
 DENSE_FLUSH = 4
 
 
@@ -85,7 +98,15 @@ class NotSPD(Exception):
 
 @dataclass
 class Stats:
+    """Counters of one evaluation.  explicit_flushes / factored_flushes /
+    early_truncations count the branches of FLUSH taken for low-rank leaves;
+    capped collects, per truncation and ACA, whether the K_MAX cap bound in the
+    accuracy mode (any True means some block misses eps)."""
     aca_ranks: list = field(default_factory=list)
+    explicit_flushes: int = 0
+    factored_flushes: int = 0
+    early_truncations: int = 0
+    capped: list = field(default_factory=list)
     flush_ranks: list = field(default_factory=list)     # accumulated rank per LR flush
     flush_terms: list = field(default_factory=list)
     final_ranks: list = field(default_factory=list)
@@ -96,7 +117,9 @@ class Stats:
 class HLikelihood:
     """One H-matrix log-likelihood evaluation on CPU, float64 throughout."""
 
-    def __init__(self, P, n_min=32, eta=2.0):
+    def __init__(self, P, n_min=32, eta=2.0, r_acc=R_ACC, dense_flush=DENSE_FLUSH):
+        self.r_acc = int(r_acc)
+        self.dense_flush = int(dense_flush)
         self.P = np.asarray(P, dtype=np.float64)
         self.n = len(self.P)
         self.n_min = n_min
@@ -140,10 +163,12 @@ class HLikelihood:
             return covariance_block(Pp, rows, cols, theta, nugget)
         row_fn = lambda li: covariance_block(Pp, rows[li:li + 1], cols, theta, 0.0)[0]
         col_fn = lambda lj: covariance_block(Pp, rows, cols[lj:lj + 1], theta, 0.0)[:, 0]
-        U, V = aca(row_fn, col_fn, r1 - r0, c1 - c0, eps, kfix if kfix > 0 else K_MAX)
-        if getattr(self, "stats", None) is not None:
-            self.stats.aca_ranks.append(U.shape[1])
-        return truncate(U, V, eps, kfix)
+        st = getattr(self, "stats", None)
+        capped = st.capped if st is not None else None
+        U, V = aca(row_fn, col_fn, r1 - r0, c1 - c0, eps, kfix if kfix > 0 else K_MAX, capped)
+        if st is not None:
+            st.aca_ranks.append(U.shape[1])
+        return truncate(U, V, eps, kfix, capped)
 
     def to_dense(self):
         """Explicit matrix of the current H representation (lower blocks
@@ -266,20 +291,24 @@ class HLikelihood:
         n = self.rng_c[bid][1] - self.rng_c[bid][0]
         C = self.tree.clusters
         b = self.bt.blocks[bid]
-        if max(m, n) <= DENSE_FLUSH * self.n_min:
+        st = self.stats
+        if max(m, n) <= self.dense_flush * self.n_min:
             D = self.U[bid] @ self.V[bid].T
             for (r0, c0, X, Y) in terms:
                 D[r0:r0 + X.shape[0], c0:c0 + Y.shape[0]] -= X @ Y.T
-            self.stats.flush_terms.append(len(terms))
-            self.U[bid], self.V[bid] = truncate_dense(D, self.eps, self.kfix)
+            st.flush_terms.append(len(terms))
+            st.explicit_flushes += 1
+            self.U[bid], self.V[bid] = truncate_dense(D, self.eps, self.kfix, st.capped)
             return
+        st.factored_flushes += 1
         Xs, Ys = [self.U[bid]], [self.V[bid]]
         rank = self.U[bid].shape[1]
         peak = rank
         for (r0, c0, X, Y) in terms:
             r = X.shape[1]
-            if rank > 0 and rank + r > R_ACC:
-                U, V = truncate(np.hstack(Xs), np.hstack(Ys), self.eps, self.kfix)
+            if rank > 0 and rank + r > self.r_acc:
+                st.early_truncations += 1
+                U, V = truncate(np.hstack(Xs), np.hstack(Ys), self.eps, self.kfix, st.capped)
                 Xs, Ys, rank = [U], [V], U.shape[1]
             Xp = np.zeros((m, r))
             Yp = np.zeros((n, r))
@@ -289,9 +318,9 @@ class HLikelihood:
             Ys.append(Yp)
             rank += r
             peak = max(peak, rank)
-        self.stats.flush_ranks.append(peak)
-        self.stats.flush_terms.append(len(terms))
-        self.U[bid], self.V[bid] = truncate(np.hstack(Xs), np.hstack(Ys), self.eps, self.kfix)
+        st.flush_ranks.append(peak)
+        st.flush_terms.append(len(terms))
+        self.U[bid], self.V[bid] = truncate(np.hstack(Xs), np.hstack(Ys), self.eps, self.kfix, st.capped)
 
     def potrf(self, bid):
         L, info = lapack.dpotrf(self.D[bid], lower=1, clean=1)
@@ -386,16 +415,17 @@ class HLikelihood:
         except NotSPD as e:
             nan = np.full(r, np.nan)
             return dict(loglik=nan, logdet=nan, quadform=nan, status="not_spd",
-                        fail_block=e.block, fail_pivot=e.pivot)
+                        fail_block=e.block, fail_pivot=e.pivot, rank_capped=int(sum(self.stats.capped)))
         logdet = self.logdet()
         v = self.solve(Z)
         quad = np.sum(v * v, axis=0)
         ll = -0.5 * self.n * math.log(2.0 * math.pi) - 0.5 * logdet - 0.5 * quad
         return dict(loglik=ll, logdet=np.full(r, logdet), quadform=quad, status="ok",
-                    fail_block=-1, fail_pivot=-1)
+                    fail_block=-1, fail_pivot=-1, rank_capped=int(sum(self.stats.capped)),
+                    max_rank=max((u.shape[1] for u in self.U.values()), default=0))
 
 
-def h_loglik(P, Z, theta, nugget, n_min=32, eta=2.0, eps=0.0, kfix=0):
+def h_loglik(P, Z, theta, nugget, n_min=32, eta=2.0, eps=0.0, kfix=0, **kw):
     """Convenience wrapper: one evaluation of eq. (4) on the CPU."""
-    H = HLikelihood(P, n_min, eta)
+    H = HLikelihood(P, n_min, eta, **kw)
     return H.loglik(theta, nugget, Z, eps, kfix)

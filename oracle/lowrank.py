@@ -19,7 +19,10 @@ recompression:
        Householder QR  X = Qx Rx,  Y = Qy Ry;  SVD  Rx Ry^T = W S Z^T;
        keep k' = #{s_i > eps s_1}   (relative spectral accuracy, Remark 2.4), or
             k' = min(k, #{s_i > 0}) in the fixed-rank mode (Definition 2.1);
-       k' is also capped by K_MAX;
+       k' is also capped by K_MAX.  In the accuracy mode a binding cap means the
+       block misses the requested accuracy; this is never silent: the caller
+       passes a list `capped` and every truncation (and every ACA that stops at
+       the cap before its accuracy test is met) appends whether the cap bound.
        U = Qx W[:, :k'] S[:k'],  V = Qy Z[:, :k'].
 
   TRUNCATE_DENSE(D) for an explicit (small) block: the same rank rule applied
@@ -38,17 +41,26 @@ from __future__ import annotations
 import numpy as np
 
 # Largest rank any low-rank block may carry (assembly, truncation, accumulation
-# of updates).  A named constant of the method shared by every implementation.
+# of updates).  The paper bounds ranks only through eps (Remark 2.4) or k
+# (Definition 2.1); a finite cap is an implementation limit of storage.  64 is
+# the leaf size n_min of the benchmark workloads, so a block at the cap is as
+# expensive as a dense leaf row; the largest rank measured in the benchmark
+# configurations is about half of it.  When the cap binds in the accuracy mode
+# it is reported (see `capped` below), never applied silently.
 K_MAX = 64
 
 
-def aca(row_fn, col_fn, m: int, n: int, eps: float, kmax: int):
+def aca(row_fn, col_fn, m: int, n: int, eps: float, kmax: int, capped=None):
     """Partial-pivoting ACA of an implicitly given m x n block.
 
     row_fn(i) -> M[i, :] (length n);  col_fn(j) -> M[:, j] (length m).
-    Returns U (m x k), V (n x k) with M ~ U V^T.
+    Returns U (m x k), V (n x k) with M ~ U V^T.  If `capped` is a list, it
+    receives True when the iteration stopped at kmax < min(m, n) with its
+    accuracy test (eps > 0) not met, else False.
     """
+    cap_binds = kmax < min(m, n)
     kmax = min(kmax, m, n)
+    converged = False
     Us, Vs = [], []
     used = np.zeros(m, dtype=bool)
     i = 0
@@ -61,6 +73,7 @@ def aca(row_fn, col_fn, m: int, n: int, eps: float, kmax: int):
         j = int(np.argmax(np.abs(r)))
         if r[j] == 0.0:
             if used.all():
+                converged = True
                 break
             i = int(np.argmin(used))     # lowest unused row
             continue
@@ -77,46 +90,56 @@ def aca(row_fn, col_fn, m: int, n: int, eps: float, kmax: int):
         Us.append(u)
         Vs.append(v)
         if np.sqrt(nu2) * np.sqrt(nv2) <= eps * np.sqrt(S2):
+            converged = True
             break
         if used.all():
+            converged = True
             break
         cand = np.where(used, -1.0, np.abs(u))
         i = int(np.argmax(cand))
+    if capped is not None:
+        capped.append(bool(eps > 0 and cap_binds and len(Us) == kmax and not converged))
     if not Us:
         return np.zeros((m, 0)), np.zeros((n, 0))
     return np.stack(Us, axis=1), np.stack(Vs, axis=1)
 
 
-def _keep(s, eps, kfix):
-    if s.size == 0 or s[0] == 0.0:
-        return 0
-    if kfix > 0:
-        k = min(kfix, int(np.count_nonzero(s > 0.0)))
-    else:
-        k = int(np.count_nonzero(s > eps * s[0]))
+def _keep(s, eps, kfix, capped=None):
+    """Rank kept from singular values s (descending); `capped` (a list, or
+    None) receives whether the K_MAX cap lowered it in the accuracy mode."""
+    k = 0
+    if s.size and s[0] != 0.0:
+        if kfix > 0:
+            k = min(kfix, int(np.count_nonzero(s > 0.0)))
+        else:
+            k = int(np.count_nonzero(s > eps * s[0]))
+    if capped is not None:
+        capped.append(bool(kfix <= 0 and k > K_MAX))
     return min(k, K_MAX)
 
 
-def truncate_dense(D: np.ndarray, eps: float, kfix: int):
+def truncate_dense(D: np.ndarray, eps: float, kfix: int, capped=None):
     """Best approximation of an explicit block D at relative accuracy eps
     (kfix == 0) or rank kfix, capped at K_MAX.  Returns (U, V)."""
     m, n = D.shape
     W, s, Zt = np.linalg.svd(D)
-    k = _keep(s, eps, kfix)
+    k = _keep(s, eps, kfix, capped)
     return W[:, :k] * s[:k], Zt[:k, :].T.copy()
 
 
-def truncate(X: np.ndarray, Y: np.ndarray, eps: float, kfix: int):
+def truncate(X: np.ndarray, Y: np.ndarray, eps: float, kfix: int, capped=None):
     """Best approximation of X Y^T at relative accuracy eps (kfix == 0) or
     rank kfix (kfix > 0), capped at K_MAX.  Returns (U, V)."""
     m, r = X.shape
     n = Y.shape[0]
     if r == 0:
+        if capped is not None:
+            capped.append(False)
         return np.zeros((m, 0)), np.zeros((n, 0))
     Qx, Rx = np.linalg.qr(X, mode="reduced")
     Qy, Ry = np.linalg.qr(Y, mode="reduced")
     W, s, Zt = np.linalg.svd(Rx @ Ry.T)
-    k = _keep(s, eps, kfix)
+    k = _keep(s, eps, kfix, capped)
     if k == 0:
         return np.zeros((m, 0)), np.zeros((n, 0))
     U = Qx @ (W[:, :k] * s[:k])
