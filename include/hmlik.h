@@ -43,7 +43,7 @@ typedef enum {
                            accuracy, Tables 6 and 7); outputs are NaN, fail_block/fail_pivot set */
   HM_ERR_OOM = 3,       /* device allocation failed */
   HM_ERR_DEVICE = 4,    /* a HIP runtime call failed */
-  HM_ERR_INTERNAL = 5,  /* the task executor aborted (bounded wait exceeded) */
+  HM_ERR_INTERNAL = 5,  /* an internal invariant failed (planner error on unusual input) */
   HM_ERR_CANCELLED = 6, /* the request was cancelled before it finished */
   HM_ERR_BUSY = 7       /* a request server owns the context (see Conventions) */
 } hm_status;
@@ -66,23 +66,45 @@ typedef struct {
   double eta;
 } hm_tree_opts;
 
+/* Arithmetic of an evaluation.  HM_FP64: every step in FP64.  HM_MIXED: the
+ * low-rank factors U, V of C~ and L~ and the products of the H-Cholesky
+ * updates in FP32, the dense leaves, log-determinant and recompressions in
+ * FP64, and C~^{-1} Z improved by iterative refinement (see hm_result). */
+typedef enum { HM_FP64 = 0, HM_MIXED = 1 } hm_precision;
+
 /* Accuracy (Remark 2.4 / Def. 2.1): exactly one of
  *   fixed_rank > 0 (ranks <= fixed_rank, eps ignored), or
- *   fixed_rank == 0 and eps > 0 (relative spectral accuracy per block). */
+ *   fixed_rank == 0 and eps > 0 (relative spectral accuracy per block).
+ * prec selects the arithmetic (hm_precision).  refine_max_iter >= 0 and
+ * refine_tol >= 0 bound the iterative refinement of x = C~^{-1} Z in the
+ * HM_MIXED form (stop after that many steps or once the relative residual
+ * ||Z - C~ x|| / ||Z|| is at most refine_tol); they must be 0 in HM_FP64. */
 typedef struct {
   int32_t fixed_rank;
   double eps;
+  int32_t prec;            /* hm_precision */
+  int32_t refine_max_iter;
+  double refine_tol;
 } hm_approx;
 
-/* One evaluation: one entry per right-hand side. */
+/* One evaluation: one entry per right-hand side (column of Z). */
 typedef struct {
-  double loglik;    /* eq. (4) */
-  double logdet;    /* log|C~| = 2 sum log L~_ii */
-  double quadform;  /* v^T v = Z^T (L~ L~^T)^{-1} Z */
-  int32_t status;   /* hm_status of the evaluation */
-  int32_t max_rank; /* largest rank of a low-rank block of the factor */
+  double loglik;      /* eq. (4) */
+  double logdet;      /* log|C~| = 2 sum log L~_ii */
+  double quadform;    /* v^T v = Z^T (L~ L~^T)^{-1} Z, L~ v = Z (eq. 4) */
+  int64_t n;          /* number of locations */
+  int32_t max_rank;   /* largest rank of a low-rank block of the factor */
+  int32_t rank_capped; /* ACA runs and truncations (assembly and factorisation) in which the rank
+                           cap of 64 bound in the accuracy mode, so that the block misses eps; 0 = none */
+  int64_t bytes_C;    /* storage of C~ at its actual ranks: 8 (dense entries + sum (m + n) k) */
+  int64_t bytes_L;    /* the same for L~ (0 after a breakdown) */
+  int32_t status;     /* hm_status of the evaluation */
+  int32_t fail_pivot; /* row of the failed pivot inside fail_block, else -1 */
   int64_t fail_block; /* block id of the failed pivot (HM_ERR_NOT_SPD), else -1 */
-  int32_t fail_pivot; /* row of the failed pivot inside that block, else -1 */
+  double refine_quad; /* Z^T x with x the refined C~^{-1} Z (HM_MIXED); equals quadform in HM_FP64 */
+  double refine_resid; /* ||Z - C~ x|| / ||Z|| of that x (HM_MIXED); 0 in HM_FP64 */
+  int32_t refine_iters; /* refinement steps taken (0 in HM_FP64) */
+  int32_t reserved;
   double t_assemble, t_factor, t_solve; /* seconds (device events) */
 } hm_result;
 
@@ -95,11 +117,13 @@ hm_status hm_ctx_create(int device, void *stream, hm_ctx **out);
  * still running on the context is destroyed first (hm_server_destroy). */
 void hm_ctx_destroy(hm_ctx *ctx);
 
-/* Build the cluster tree and block cluster tree for n locations (App. B,
- * Defs. B.1-B.3) and the theta-independent H-Cholesky schedule, and upload
- * them.  coords: host pointer, n x 2 row-major, finite. */
-hm_status hm_dataset_create(hm_ctx *ctx, const double *coords, int64_t n, const hm_tree_opts *opts,
-                            hm_dataset **out);
+/* Build the cluster tree and block cluster tree for n locations s_i (Sect. 2.2,
+ * App. B, Defs. B.1-B.3) and the theta-independent H-Cholesky schedule, and
+ * upload them.  coords: n x d row-major, finite; d must be 2 (the paper's
+ * spatial setting; other d return HM_ERR_ARG).  coords_on_device != 0: coords is
+ * a device pointer on the context's device, read (copied) during the call. */
+hm_status hm_dataset_create(hm_ctx *ctx, const double *coords, int64_t n, int32_t d, const hm_tree_opts *opts,
+                            int32_t coords_on_device, hm_dataset **out);
 /* Frees all of the dataset's device memory.  If a server runs on its context,
  * the server's queued requests on ds are cancelled and the call waits until
  * none of them is on the device. */
@@ -121,7 +145,9 @@ hm_status hm_dataset_footprint(const hm_dataset *ds, int64_t *resident_bytes, in
 hm_status hm_dataset_release(hm_dataset *ds);
 
 /* Data Z: n x r column-major in input (not permuted) order, 1 <= r <= 64.
- * on_device != 0: Z is a device pointer read in stream order during this call. */
+ * on_device != 0: Z is a device pointer (on the context's device, n * r
+ * doubles) read in stream order during this call.  A host Z must be finite.
+ * On any error the dataset keeps its previous Z. */
 hm_status hm_dataset_set_z(hm_dataset *ds, const double *Z, int32_t r, int32_t on_device);
 
 /* Assemble C~(theta): Matern entries of the dense leaves, ACA + truncation of

@@ -192,14 +192,9 @@ hm_status build_device(hm_dataset* ds) {
   TRY(upload(ds, P.deps, const_cast<int32_t**>(&D.deps)));
   TRY(upload(ds, P.task_prog, const_cast<int32_t**>(&D.task_prog)));
   D.ntasks = (int32_t)P.tasks.size();
-  TRY(dev_alloc(ds, sizeof(int32_t) * (P.tasks.size() + 1), &p));
-  D.done = (int32_t*)p;
-  TRY(dev_alloc(ds, sizeof(int32_t) * 4 * NSLOTS, &p));
-  D.dbg = (int32_t*)p;
   TRY(dev_alloc(ds, 256, &p));
-  D.ticket = (int32_t*)p;
-  D.abort_flag = (int32_t*)((char*)p + 64);
-  D.fail_key = (unsigned long long*)((char*)p + 128);
+  D.fail_key = (unsigned long long*)p;
+  D.capped = (int32_t*)((char*)p + 64);
   TRY(upload(ds, P.sub_begin, const_cast<int32_t**>(&D.sub_begin)));
   TRY(upload(ds, P.sub_end, const_cast<int32_t**>(&D.sub_end)));
   TRY(upload(ds, P.sub_leaves, const_cast<int32_t**>(&D.sub_leaves)));
@@ -244,7 +239,6 @@ hm_status build_device(hm_dataset* ds) {
     D.task_times = (int64_t*)p;
     ds->tt_buf = D.task_times;
   }
-  D.spin_limit = getenv("HMLIK_SPIN_LIMIT_S") ? (int64_t)(atof(getenv("HMLIK_SPIN_LIMIT_S")) * 1e8) : 3000000000LL;  // 100 MHz counter; 30 s default
   return HM_OK;
 }
 
@@ -294,16 +288,36 @@ void hm_ctx_destroy(hm_ctx* ctx) {
   delete ctx;
 }
 
-hm_status hm_dataset_create(hm_ctx* ctx, const double* coords, int64_t n, const hm_tree_opts* opts,
-                            hm_dataset** out) {
-  if (!ctx || !coords || !opts || !out || n < 1) return HM_ERR_ARG;
+hm_status hm_dataset_create(hm_ctx* ctx, const double* coords_in, int64_t n, int32_t d, const hm_tree_opts* opts,
+                            int32_t coords_on_device, hm_dataset** out) {
+  if (!ctx || !coords_in || !opts || !out || n < 1 || d != 2) return HM_ERR_ARG;
   *out = nullptr;
   if (busy(ctx)) return HM_ERR_BUSY;
   if (opts->leaf_size < 1 || opts->leaf_size > LEAF_MAX) return HM_ERR_ARG;
   if (!std::isfinite(opts->eta) || opts->eta < 0.0) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ctx->device));
+  // the planner runs on the host: device coordinates are copied over first
+  std::vector<double> host_coords;
+  const double* coords = coords_in;
+  if (coords_on_device) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, coords_in) != hipSuccess || at.type != hipMemoryTypeDevice ||
+        at.device != ctx->device) {
+      (void)hipGetLastError();
+      return HM_ERR_ARG;
+    }
+    try {
+      host_coords.resize(2 * (size_t)n);
+    } catch (const std::bad_alloc&) {
+      return HM_ERR_OOM;
+    }
+    HIPTRY(hipMemcpyAsync(host_coords.data(), coords_in, sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPTRY(hipStreamSynchronize(ctx->stream));
+    coords = host_coords.data();
+  }
   for (int64_t i = 0; i < 2 * n; ++i)
     if (!std::isfinite(coords[i])) return HM_ERR_ARG;
-  HIPTRY(hipSetDevice(ctx->device));
   hm_dataset* ds = new (std::nothrow) hm_dataset;
   if (!ds) return HM_ERR_OOM;
   ds->ctx = ctx;
@@ -363,6 +377,8 @@ void hm_dataset_destroy(hm_dataset* ds) {
   (void)hipSetDevice(ds->ctx->device);
   (void)hipStreamSynchronize(ds->ctx->stream);
   for (auto& b : ds->bufs) (void)hipFree(b.p);
+  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out})
+    if (q) (void)hipFree(q);
   if (ds->store) (void)hipFree(ds->store);
   for (int i = 0; i < 4; ++i)
     if (ds->ev[i]) (void)hipEventDestroy(ds->ev[i]);
@@ -396,24 +412,51 @@ hm_status hm_dataset_footprint(const hm_dataset* ds, int64_t* resident_bytes, in
 hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t on_device) {
   if (!ds || !Z || r < 1 || r > 64) return HM_ERR_ARG;
   if (busy(ds->ctx)) return HM_ERR_BUSY;
-  HIPTRY(hipSetDevice(ds->ctx->device));
   const int64_t n = ds->tree.n;
-  if (r > ds->r) {
-    void* p;
-    TRY(dev_alloc(ds, sizeof(double) * n * r, &p));
-    ds->d_Z = (double*)p;
-    TRY(dev_alloc(ds, sizeof(double) * n * r, &p));
-    ds->d_W = (double*)p;
-    TRY(dev_alloc(ds, sizeof(double) * (1 + r), &p));
-    ds->d_out = (double*)p;
-  }
+  // validate before anything changes: on an error the old Z stays in place
   if (!on_device) {
     for (int64_t i = 0; i < n * (int64_t)r; ++i)
       if (!std::isfinite(Z[i])) return HM_ERR_ARG;
+  } else {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, Z) != hipSuccess || at.type != hipMemoryTypeDevice ||
+        at.device != ds->ctx->device) {
+      (void)hipGetLastError();
+      return HM_ERR_ARG;
+    }
   }
-  HIPTRY(hipMemcpyAsync(ds->d_Z, Z, sizeof(double) * n * r,
-                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, ds->ctx->stream));
-  HIPTRY(hipStreamSynchronize(ds->ctx->stream));
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  double *z = ds->d_Z, *w = ds->d_W, *o = ds->d_out;
+  const bool grow = r > ds->zcap;
+  if (grow) {
+    z = w = o = nullptr;
+    const size_t bz = sizeof(double) * n * r;
+    if (hipMalloc((void**)&z, bz) != hipSuccess || hipMalloc((void**)&w, bz) != hipSuccess ||
+        hipMalloc((void**)&o, sizeof(double) * (1 + r)) != hipSuccess) {
+      (void)hipGetLastError();
+      for (void* q : {(void*)z, (void*)w, (void*)o})
+        if (q) (void)hipFree(q);
+      return HM_ERR_OOM;
+    }
+  }
+  const bool ok = hipMemcpyAsync(z, Z, sizeof(double) * n * r,
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                 ds->ctx->stream) == hipSuccess &&
+                  hipStreamSynchronize(ds->ctx->stream) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (grow)
+      for (void* q : {(void*)z, (void*)w, (void*)o}) (void)hipFree(q);
+    return HM_ERR_DEVICE;
+  }
+  if (grow) {
+    for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out})
+      if (q) (void)hipFree(q);
+    ds->d_Z = z;
+    ds->d_W = w;
+    ds->d_out = o;
+    ds->zcap = r;
+  }
   ds->r = r;
   return HM_OK;
 }
@@ -430,7 +473,22 @@ hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
   if (ap->fixed_rank == 0 && !finite_pos(ap->eps)) return HM_ERR_ARG;
   if (ap->fixed_rank > 0 && !(std::isfinite(ap->eps) && ap->eps >= 0.0)) return HM_ERR_ARG;
   if (th->nu > 50.0) return HM_ERR_ARG;
+  if (ap->refine_max_iter < 0 || !std::isfinite(ap->refine_tol) || ap->refine_tol < 0.0) return HM_ERR_ARG;
+  if (ap->prec == HM_FP64) {
+    if (ap->refine_max_iter != 0 || ap->refine_tol != 0.0) return HM_ERR_ARG;
+  } else {
+    return HM_ERR_ARG;   // HM_MIXED is not available in this build
+  }
   return HM_OK;
+}
+
+int64_t storage_bytes(const hm_dataset* ds, const int32_t* rank) {
+  int64_t e = ds->plan.n_dense_entries;
+  for (int32_t b : ds->plan.lr_ids) {
+    const Block& bk = ds->tree.bk[b];
+    e += (bk.m + bk.n) * (int64_t)rank[b];
+  }
+  return 8 * e;
 }
 
 hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* ap, hipStream_t st, double* ws,
@@ -447,21 +505,18 @@ hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* a
   DevData Dl = D;
   if (ws) Dl.ws = ws;
   HIPTRY(hipEventRecord(ds->ev[0], st));
+  HIPTRY(launch_eval_init(Dl, st));
   HIPTRY(launch_assemble(Dl, st));
   HIPTRY(launch_aca(Dl, ws ? grid : NSLOTS, st));
   HIPTRY(hipEventRecord(ds->ev[1], st));
   return HM_OK;
 }
 
-hm_status decode_factor_status(hm_dataset* ds, int32_t abort_flag, unsigned long long key) {
+hm_status decode_factor_status(hm_dataset* ds, unsigned long long key) {
   ds->assembled = false;
   ds->factored = true;
   ds->fail_block = -1;
   ds->fail_pivot = -1;
-  if (abort_flag) {
-    ds->factor_status = HM_ERR_INTERNAL;
-    return HM_ERR_INTERNAL;
-  }
   if (key != ~0ull) {
     const int64_t prog = (int64_t)(key >> 8);
     ds->fail_pivot = (int32_t)(key & 0xff);
@@ -483,8 +538,13 @@ void fill_results(const hm_dataset* ds, const double* res, int32_t max_rank, hm_
   const double c0 = -0.5 * (double)ds->tree.n * std::log(2.0 * 3.14159265358979323846);
   for (int c = 0; c < ds->r; ++c) {
     hm_result& o = out[c];
+    std::memset(&o, 0, sizeof(o));
     o.status = ds->factor_status;
+    o.n = ds->tree.n;
     o.max_rank = max_rank;
+    o.rank_capped = ds->rank_capped;
+    o.bytes_C = ds->bytes_C;
+    o.bytes_L = ds->factor_status == HM_OK ? ds->bytes_L : 0;
     o.fail_block = ds->fail_block;
     o.fail_pivot = ds->fail_pivot;
     o.t_assemble = ds->t_assemble;
@@ -494,8 +554,9 @@ void fill_results(const hm_dataset* ds, const double* res, int32_t max_rank, hm_
       o.logdet = res[0];
       o.quadform = res[1 + c];
       o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.quadform;
+      o.refine_quad = o.quadform;
     } else {
-      o.logdet = o.quadform = o.loglik = NAN;
+      o.logdet = o.quadform = o.loglik = o.refine_quad = NAN;
     }
   }
 }
@@ -512,6 +573,11 @@ hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
   float ms = 0;
   HIPTRY(hipEventElapsedTime(&ms, ds->ev[0], ds->ev[1]));
   ds->t_assemble = ms * 1e-3;
+  {
+    std::vector<int32_t> rk(ds->tree.bk.size());
+    HIPTRY(hipMemcpy(rk.data(), ds->D.rank, sizeof(int32_t) * rk.size(), hipMemcpyDeviceToHost));
+    ds->bytes_C = storage_bytes(ds, rk.data());
+  }
   ds->assembled = true;
   ds->factored = false;
   return HM_OK;
@@ -519,10 +585,9 @@ hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
 
 static hm_status finish_factor(hm_dataset* ds) {
   DevData& D = ds->D;
-  int32_t flags[2];
   unsigned long long key = 0;
-  HIPTRY(hipMemcpy(&flags[0], D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
   HIPTRY(hipMemcpy(&key, D.fail_key, sizeof(key), hipMemcpyDeviceToHost));
+  HIPTRY(hipMemcpy(&ds->rank_capped, D.capped, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (D.task_times && getenv("HMLIK_TASK_TIMES")) {
     const char* path = getenv("HMLIK_TASK_TIMES");
     std::vector<int64_t> tt(7 * ds->plan.tasks.size());
@@ -539,25 +604,7 @@ static hm_status finish_factor(hm_dataset* ds) {
       }
     }
   }
-  const hm_status fs = decode_factor_status(ds, flags[0], key);
-  if (fs == HM_ERR_INTERNAL) {
-    if (getenv("HMLIK_DUMP_EXECUTOR")) {
-      std::vector<int32_t> dbg(4 * NSLOTS), done(ds->plan.tasks.size());
-      (void)hipMemcpy(dbg.data(), D.dbg, sizeof(int32_t) * dbg.size(), hipMemcpyDeviceToHost);
-      (void)hipMemcpy(done.data(), D.done, sizeof(int32_t) * done.size(), hipMemcpyDeviceToHost);
-      int64_t ndone = 0;
-      for (int32_t v : done) ndone += v != 0;
-      fprintf(stderr, "hmlik executor abort: %lld of %zu tasks done\n", (long long)ndone, done.size());
-      for (int w = 0; w < NSLOTS; ++w) {
-        const int32_t tk = dbg[4 * w], ph = dbg[4 * w + 1], dep = dbg[4 * w + 2];
-        if (ph == 1 || ph == 2)
-          fprintf(stderr, "  wg %d ticket %d kind %d phase %d awaiting %d (done=%d) tasks_done %d\n", w, tk,
-                  (tk >= 0 && tk < (int)done.size()) ? (int)ds->plan.tasks[tk].kind : -1, ph, dep,
-                  (dep >= 0 && dep < (int)done.size()) ? done[dep] : -1, dbg[4 * w + 3]);
-      }
-    }
-  }
-  return fs;
+  return decode_factor_status(ds, key);
 }
 
 hm_status hm_factor(hm_dataset* ds) {
@@ -568,16 +615,7 @@ hm_status hm_factor(hm_dataset* ds) {
   DevData& D = ds->D;
   hipStream_t st = ds->ctx->stream;
   HIPTRY(hipEventRecord(ds->ev[1], st));
-  if (getenv("HMLIK_PERSISTENT_EXECUTOR")) {
-    // persistent ticket scheduler: disabled by default (stalled on the device,
-    // cause not yet established)
-    int grid = NEXEC;
-    if (const char* e = getenv("HMLIK_EXEC_WGS")) {
-      grid = atoi(e);
-      if (grid < 1 || grid > NSLOTS) grid = NEXEC;
-    }
-    HIPTRY(launch_factor(D, grid, st));
-  } else {
+  {
     const int32_t nlev = (int32_t)ds->level_begin.size() - 1;
     // HMLIK_PROGRESS=<levels>: synchronise every <levels> levels and report
     // progress on stderr (for long factorisations; costs a sync per chunk)
@@ -585,7 +623,7 @@ hm_status hm_factor(hm_dataset* ds) {
     if (const char* e = getenv("HMLIK_PROGRESS")) chunk = std::max(1, atoi(e));
     for (int32_t l0 = 0; l0 < nlev; l0 += chunk) {
       const int32_t l1 = std::min(nlev, l0 + chunk);
-      HIPTRY(launch_factor_levels(D, ds->level_begin.data(), l0, l1, l0 == 0, NSLOTS, st));
+      HIPTRY(launch_factor_levels(D, ds->level_begin.data(), l0, l1, NSLOTS, st));
       if (l1 < nlev) {
         HIPTRY(hipStreamSynchronize(st));
         HIPTRY(hipEventRecord(ds->ev[2], st));
@@ -617,6 +655,7 @@ hm_status hm_solve(hm_dataset* ds, hm_result* out) {
     std::vector<int32_t> rk(ds->tree.bk.size());
     HIPTRY(hipMemcpy(rk.data(), D.rank, sizeof(int32_t) * rk.size(), hipMemcpyDeviceToHost));
     max_rank = max_lr_rank(ds, rk.data());
+    ds->bytes_L = storage_bytes(ds, rk.data());
   }
   std::vector<double> res(1 + r, NAN);
   if (ds->factor_status == HM_OK) {

@@ -42,12 +42,9 @@ struct DevData {
   const int32_t* order;       // execution order of the tasks, level by level
   const int32_t* deps;
   int32_t ntasks;
-  int32_t* ticket;
-  int32_t* done;
-  int32_t* abort_flag;
   unsigned long long* fail_key;   // min over (program index << 8 | pivot) of failed pivots
+  int32_t* capped;                // ACA runs / truncations where the rank cap bound in the accuracy mode
   const int32_t* task_prog;       // program-order index of each task
-  int32_t* dbg;                   // 4 ints per executor work-group: ticket, phase, awaited task, #done
   int64_t* task_times;            // optional: start/end real-time stamps per task (nullptr: off)
   double* task_flops;             // algorithmic flops of each factorization task
   // structure helpers
@@ -72,7 +69,6 @@ struct DevData {
   int32_t kfix;
   int32_t kmax;               // rank cap (K_MAX, or kfix)
   int32_t dflush;             // low-rank blocks of at most dflush x dflush take their updates explicitly
-  int64_t spin_limit;         // bounded wait (s_memrealtime ticks)
 };
 
 }  // namespace hm
@@ -82,15 +78,14 @@ struct DevData {
 namespace hm {
 hipError_t launch_assemble(const DevData& D, hipStream_t st);
 hipError_t launch_aca(const DevData& D, int grid, hipStream_t st);
-hipError_t launch_factor(const DevData& D, int grid, hipStream_t st);
 hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
                                 int r, double* U, double* V, int32_t* kout, int64_t* phases, hipStream_t st);
-// Launches levels [l0, l1) of the task DAG, one kernel per level; `init`
-// clears the breakdown flags first (the first chunk of a factorisation).
-hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, bool init,
-                                int max_grid, hipStream_t st);
-// Clears the breakdown flags of one dataset before a batched factorisation.
-hipError_t launch_factor_init(const DevData& D, hipStream_t st);
+// Clears the breakdown record and the rank-cap counter of an evaluation (before
+// its assembly).
+hipError_t launch_eval_init(const DevData& D, hipStream_t st);
+// Launches levels [l0, l1) of the task DAG, one kernel per level.
+hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, int max_grid,
+                                hipStream_t st);
 // One level of several datasets' factorisations in one launch: Ds (device
 // array of nseg DevData), seg (device, 2 nseg ints: the level's task range per
 // dataset), total = the number of tasks over all of them.

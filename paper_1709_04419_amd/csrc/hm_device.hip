@@ -9,9 +9,8 @@
 //   k_aca               adaptive cross approximation of admissible blocks
 //                       (Section 2.1) followed by SVD truncation at relative
 //                       accuracy eps or fixed rank k (Remark 2.4, Definition 2.1).
-//   k_factor            persistent H-Cholesky executor (Section 3.2): work-groups
-//                       take tasks in a topological ticket order and wait on the
-//                       completion flags of their predecessors.
+//   k_level             H-Cholesky (Section 3.2) as a task graph, one launch per
+//                       dependency level, one work-group per task.
 //   k_solve, k_reduce   forward substitution L v = Z, log|C| = 2 sum log L_ii and
 //                       v^T v, assembled into eq. (4) of Section 3.1.
 //
@@ -1100,6 +1099,7 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
       if (k > D.kfix) k = D.kfix;
     } else {
       for (int l = 0; l < r; ++l) if (S.sig[S.ord[l]] > D.eps * s1) ++k;
+      if (k > D.kmax && tid == 0) atomicAdd(D.capped, 1);   // the cap binds: this block misses eps
     }
     if (k > D.kmax) k = D.kmax;
   }
@@ -1230,6 +1230,7 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
     int64_t istar = 0;
     double S2 = 0.0;
     int64_t nused = 0;
+    bool converged = false;
     while (k < kcap) {
       // residual row -> Va[:, k]
       double* v = Va + (int64_t)k * n;
@@ -1249,7 +1250,7 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
       const double piv = v[bj];
       __syncthreads();   // every thread has the pivot before its owner rescales it
       if (piv == 0.0) {
-        if (nused >= m) break;
+        if (nused >= m) { converged = true; break; }
         // lowest unused row
         int64_t lo = m;
         for (int64_t i = tid; i < m; i += NT) if (used[i] == 0.0 && i < lo) lo = i;
@@ -1286,8 +1287,8 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
       }
       S2 = S2 + 2.0 * cross + nu2 * nv2;
       ++k;
-      if (sqrt(nu2) * sqrt(nv2) <= D.eps * sqrt(S2)) break;
-      if (nused >= m) break;
+      if (sqrt(nu2) * sqrt(nv2) <= D.eps * sqrt(S2)) { converged = true; break; }
+      if (nused >= m) { converged = true; break; }
       // next row: largest |u_i| among unused rows
       double bv = -1.0;
       int64_t bi = 0;
@@ -1300,6 +1301,9 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
       __syncthreads();
     }
     __syncthreads();
+    // the rank cap stopped the iteration before its accuracy test was met
+    const int64_t mn = m < n ? m : n;
+    if (tid == 0 && D.kfix <= 0 && D.kmax < mn && k == kcap && !converged) atomicAdd(D.capped, 1);
     double* U = D.lr + D.lr_off[b];
     double* V = U + m * K_MAX;
     const int kt = wg_truncate(D, Ua, m, Va, n, k, U, V, scratch, dyn, 4096, S);
@@ -1683,70 +1687,6 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
 
 // ------------------------------------------------------------------ executor
 
-__device__ __forceinline__ int64_t rtc() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
-
-__global__ void __launch_bounds__(NT) k_factor(DevData D) {
-  extern __shared__ double dyn[];
-  __shared__ Smem S;
-  const int tid = threadIdx.x;
-  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
-  int32_t* dbg = D.dbg + 4 * blockIdx.x;   // executor state, read by the host after an abort
-  while (true) {
-    if (tid == 0) {
-      int t = atomicAdd(D.ticket, 1);
-      if (__hip_atomic_load(D.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) t = D.ntasks;
-      S.task = t;
-      dbg[0] = t;
-      dbg[1] = 1;
-    }
-    __syncthreads();
-    const int32_t t = S.task;
-    __syncthreads();
-    if (t >= D.ntasks) break;
-    const Task tk = D.tasks[t];
-    // wait for predecessors (bounded)
-    int bad = 0;
-    for (int32_t q = tid; q < tk.ndeps; q += NT) {
-      const int32_t d = D.deps[tk.dep_begin + q];
-      const int64_t t0 = rtc();
-      while (__hip_atomic_load(&D.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        dbg[2] = d;
-        if (__hip_atomic_load(D.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { bad = 1; break; }
-        if (rtc() - t0 > D.spin_limit) {
-          __hip_atomic_store(D.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          bad = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      if (bad) break;
-    }
-    if (tid == 0) S.flag = 0;
-    __syncthreads();
-    if (bad) S.flag = 1;
-    __syncthreads();
-    const int stop = S.flag;
-    __syncthreads();
-    if (stop) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (tid == 0) dbg[1] = 2;
-    const int32_t prog = D.task_prog[t];
-    if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
-    else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
-    else task_dense(D, tk, prog, dyn, S);
-    // every wave's stores acknowledged by L2 before the one agent-scope
-    // release (L2 write-back) that publishes the task
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (tid == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(&D.done[t], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      dbg[1] = 3;
-      dbg[3] += 1;
-    }
-  }
-}
-
 // One task of the factorisation (shared by the level executors).
 __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn, Smem& S) {
   const Task tk = D.tasks[t];
@@ -1777,35 +1717,10 @@ __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1)
   for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) run_task(D, D.order[q], slot, dyn, S);
 }
 
-// Level executor over several datasets: seg holds (t0, t1) of this level for
-// each of the nseg datasets; work-group w takes tasks w, w + grid, ... of their
-// concatenation, with workspace slot w (the datasets share one workspace).
-__global__ void __launch_bounds__(NT) k_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg,
-                                                    int32_t total) {
-  extern __shared__ double dyn[];
-  __shared__ Smem S;
-  for (int32_t idx = blockIdx.x; idx < total; idx += gridDim.x) {
-    int32_t s = 0, base = 0;
-    for (; s < nseg - 1; ++s) {
-      const int32_t len = seg[2 * s + 1] - seg[2 * s];
-      if (idx < base + len) break;
-      base += len;
-    }
-    const DevData& D = Ds[s];
-    double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
-    run_task(D, D.order[seg[2 * s] + (idx - base)], slot, dyn, S);
-  }
-}
-
-__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
-__global__ void k_init_sched(int32_t* ticket, int32_t* abort_flag, unsigned long long* fail_key) {
+__global__ void k_eval_init(unsigned long long* fail_key, int32_t* capped) {
   if (threadIdx.x == 0) {
-    *ticket = 0;
-    *abort_flag = 0;
     *fail_key = ~0ull;
+    *capped = 0;
   }
 }
 
@@ -1908,24 +1823,13 @@ hipError_t launch_aca(const DevData& D, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_factor(const DevData& D, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
-  hipLaunchKernelGGL(k_fill_i32, dim3(256), dim3(NT), 0, st, D.done, (int64_t)D.ntasks, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(8), dim3(NT), 0, st, D.dbg, (int64_t)4 * grid, -1);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       LDS_FACTOR * sizeof(double));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  if (D.ntasks > 0) hipLaunchKernelGGL(k_factor, dim3(grid), dim3(NT), LDS_FACTOR * sizeof(double), st, D);
+hipError_t launch_eval_init(const DevData& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_eval_init, dim3(1), dim3(64), 0, st, D.fail_key, D.capped);
   return hipGetLastError();
 }
 
-hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, bool init,
-                                int max_grid, hipStream_t st) {
-  if (init) hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
+hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, int max_grid,
+                                hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_level, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1938,26 +1842,6 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
     const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
     if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_factor_init(const DevData& D, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_sched, dim3(1), dim3(64), 0, st, D.ticket, D.abort_flag, D.fail_key);
-  return hipGetLastError();
-}
-
-hipError_t launch_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg, int32_t total, int max_grid,
-                              hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_level_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       LDS_FACTOR * sizeof(double));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  const int g = total < max_grid ? total : max_grid;
-  if (g > 0)
-    hipLaunchKernelGGL(k_level_batch, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, Ds, seg, nseg, total);
   return hipGetLastError();
 }
 

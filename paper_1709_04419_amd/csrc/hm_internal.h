@@ -29,7 +29,6 @@ struct hm_ctx {
 namespace hm_int {
 
 constexpr int NSLOTS = 512;   // workspace slots (ACA and level-kernel work-groups)
-constexpr int NEXEC = 256;    // persistent-executor work-groups: one per CU
 
 struct DevBuf {
   void* p = nullptr;
@@ -54,11 +53,14 @@ struct hm_dataset {
   double* d_Z = nullptr;
   double* d_W = nullptr;
   double* d_out = nullptr;
-  int32_t r = 0;
+  int32_t r = 0;                      // columns of Z
+  int32_t zcap = 0;                   // columns d_Z, d_W and d_out hold
   bool assembled = false, factored = false;
   hm_status factor_status = HM_OK;
   int64_t fail_block = -1;
   int32_t fail_pivot = -1;
+  int32_t rank_capped = 0;            // rank-cap count of the last evaluation
+  int64_t bytes_C = 0, bytes_L = 0;   // storage of C~ and L~ at the actual ranks
   double t_assemble = 0, t_factor = 0, t_solve = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<int32_t> level_begin;   // position in `order` where each level starts (+ end)
@@ -83,7 +85,9 @@ hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* a
                           int grid);
 // decodes a finished factorisation's breakdown record into ds->factor_status,
 // fail_block and fail_pivot (key: min over failed pivots of program index << 8 | pivot)
-hm_status decode_factor_status(hm_dataset* ds, int32_t abort_flag, unsigned long long key);
+hm_status decode_factor_status(hm_dataset* ds, unsigned long long key);
+// bytes of the dense leaves plus the low-rank factors at the ranks `rank`
+int64_t storage_bytes(const hm_dataset* ds, const int32_t* rank);
 // largest rank among the low-rank leaves, from a host copy of the rank array
 int32_t max_lr_rank(const hm_dataset* ds, const int32_t* rank);
 // fills r results from the solve output (log-det, then v^T v per column)

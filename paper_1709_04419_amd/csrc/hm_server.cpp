@@ -69,9 +69,10 @@ struct Slot {
   bool fac_enqueued = false;     // all levels and the breakdown record enqueued
   hipEvent_t ev_chunk[2] = {nullptr, nullptr};
   hipEvent_t ev_fac = nullptr, ev_sol0 = nullptr, ev_sol1 = nullptr;
-  int32_t* h_abort = nullptr;
+  int32_t* h_capped = nullptr;   // rank-cap count of the evaluation
   unsigned long long* h_key = nullptr;
-  int32_t* h_rank = nullptr;     // rank of every block (max_nblocks entries)
+  int32_t* h_rank = nullptr;     // rank of every block after the factorisation (max_nblocks entries)
+  int32_t* h_rank_C = nullptr;   // the same after the assembly
   double* h_out = nullptr;       // log-det and v^T v per column (1 + max_r entries)
 };
 
@@ -197,7 +198,7 @@ bool enqueue_chunk(hm_server* sv, int k) {
   const int32_t nlev = (int32_t)lb.size() - 1;
   const DevData D = slot_view(s);
   const int32_t l0 = s.next_level, l1 = std::min(nlev, l0 + CHUNK_LEVELS);
-  if (launch_factor_levels(D, lb.data(), l0, l1, l0 == 0, sv->grid, s.st) != hipSuccess) return false;
+  if (launch_factor_levels(D, lb.data(), l0, l1, sv->grid, s.st) != hipSuccess) return false;
   s.next_level = l1;
   if (hipEventRecord(s.ev_chunk[s.chunks % 2], s.st) != hipSuccess) return false;
   ++s.chunks;
@@ -205,7 +206,7 @@ bool enqueue_chunk(hm_server* sv, int k) {
   if (l1 < nlev) return true;
   const size_t nb = ds->tree.bk.size();
   s.fac_enqueued = true;
-  return hipMemcpyAsync(s.h_abort, D.abort_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s.st) == hipSuccess &&
+  return hipMemcpyAsync(s.h_capped, D.capped, sizeof(int32_t), hipMemcpyDeviceToHost, s.st) == hipSuccess &&
          hipMemcpyAsync(s.h_key, D.fail_key, sizeof(unsigned long long), hipMemcpyDeviceToHost, s.st) ==
              hipSuccess &&
          hipMemcpyAsync(s.h_rank, D.rank, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s.st) == hipSuccess &&
@@ -230,7 +231,10 @@ bool admit(hm_server* sv, Request* q, int k) {
     complete(sv, q, a);
     return true;
   }
-  return a == HM_OK && enqueue_chunk(sv, k);
+  return a == HM_OK &&
+         hipMemcpyAsync(s.h_rank_C, ds->D.rank, sizeof(int32_t) * ds->tree.bk.size(), hipMemcpyDeviceToHost,
+                        s.st) == hipSuccess &&
+         enqueue_chunk(sv, k);
 }
 
 // Enqueues the forward solve and log-determinant of slot k's request after
@@ -284,8 +288,11 @@ bool progress(hm_server* sv) {
       ds->t_assemble = elapsed_s(ds->ev[0], ds->ev[1]);
       ds->t_factor = elapsed_s(ds->ev[1], s.ev_fac);
       ds->t_solve = 0;
-      const hm_status fs = decode_factor_status(ds, *s.h_abort, *s.h_key);
+      const hm_status fs = decode_factor_status(ds, *s.h_key);
       q->max_rank = max_lr_rank(ds, s.h_rank);
+      ds->rank_capped = *s.h_capped;
+      ds->bytes_C = storage_bytes(ds, s.h_rank_C);
+      ds->bytes_L = storage_bytes(ds, s.h_rank);
       if (fs == HM_OK) {
         if (!enqueue_solve(sv, k)) return false;
         q->state = RState::SOLVING;
@@ -429,17 +436,19 @@ hm_status hm_server_create(hm_ctx* ctx, const hm_server_opts* opts, hm_server** 
   }
   const int A = sv->max_active;
   sv->slots.resize(A);
-  // per slot: abort flag, breakdown key, ranks, solve output (8-byte aligned pieces)
+  // per slot: rank-cap count, breakdown key, ranks after the factorisation and
+  // after the assembly, solve output (8-byte aligned pieces)
   const size_t rank_bytes = 8 * (size_t)((sv->max_nblocks + 1) / 2);
-  const size_t per = 16 + rank_bytes + 8 * (size_t)(1 + std::max(sv->max_r, 1));
+  const size_t per = 16 + 2 * rank_bytes + 8 * (size_t)(1 + std::max(sv->max_r, 1));
   bool ok = hipHostMalloc((void**)&sv->pinned, per * A, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < A; ++k) {
     Slot& s = sv->slots[k];
     char* base = sv->pinned + per * k;
-    s.h_abort = (int32_t*)base;
+    s.h_capped = (int32_t*)base;
     s.h_key = (unsigned long long*)(base + 8);
     s.h_rank = (int32_t*)(base + 16);
-    s.h_out = (double*)(base + 16 + rank_bytes);
+    s.h_rank_C = (int32_t*)(base + 16 + rank_bytes);
+    s.h_out = (double*)(base + 16 + 2 * rank_bytes);
     s.ws = ctx->ws + (int64_t)k * sv->grid * ctx->ws_stride;
     ok = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreate(&s.ev_chunk[0]) == hipSuccess && hipEventCreate(&s.ev_chunk[1]) == hipSuccess &&

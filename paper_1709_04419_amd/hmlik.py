@@ -25,6 +25,7 @@ _lib = C.CDLL(LIB_PATH)
 
 (HM_OK, HM_ERR_ARG, HM_ERR_NOT_SPD, HM_ERR_OOM, HM_ERR_DEVICE, HM_ERR_INTERNAL, HM_ERR_CANCELLED,
  HM_ERR_BUSY) = range(8)
+HM_FP64, HM_MIXED = 0, 1
 
 
 class hm_theta(C.Structure):
@@ -37,14 +38,17 @@ class hm_tree_opts(C.Structure):
 
 
 class hm_approx(C.Structure):
-    _fields_ = [("fixed_rank", C.c_int32), ("eps", C.c_double)]
+    _fields_ = [("fixed_rank", C.c_int32), ("eps", C.c_double), ("prec", C.c_int32),
+                ("refine_max_iter", C.c_int32), ("refine_tol", C.c_double)]
 
 
 class hm_result(C.Structure):
     _fields_ = [("loglik", C.c_double), ("logdet", C.c_double), ("quadform", C.c_double),
-                ("status", C.c_int32), ("max_rank", C.c_int32), ("fail_block", C.c_int64),
-                ("fail_pivot", C.c_int32), ("t_assemble", C.c_double), ("t_factor", C.c_double),
-                ("t_solve", C.c_double)]
+                ("n", C.c_int64), ("max_rank", C.c_int32), ("rank_capped", C.c_int32),
+                ("bytes_C", C.c_int64), ("bytes_L", C.c_int64), ("status", C.c_int32),
+                ("fail_pivot", C.c_int32), ("fail_block", C.c_int64), ("refine_quad", C.c_double),
+                ("refine_resid", C.c_double), ("refine_iters", C.c_int32), ("reserved", C.c_int32),
+                ("t_assemble", C.c_double), ("t_factor", C.c_double), ("t_solve", C.c_double)]
 
 
 class hm_server_opts(C.Structure):
@@ -60,7 +64,8 @@ _P = C.c_void_p
 _sig = {
     "hm_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "hm_ctx_destroy": (None, [_P]),
-    "hm_dataset_create": (C.c_int, [_P, _P, C.c_int64, C.POINTER(hm_tree_opts), C.POINTER(_P)]),
+    "hm_dataset_create": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(hm_tree_opts), C.c_int32,
+                                    C.POINTER(_P)]),
     "hm_dataset_destroy": (None, [_P]),
     "hm_dataset_set_z": (C.c_int, [_P, _P, C.c_int32, C.c_int32]),
     "hm_assemble": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx)]),
@@ -116,6 +121,19 @@ def _ptr(a):
     return C.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else C.c_void_p(int(a.data_ptr()))
 
 
+def _device_f64(t, ctx, what):
+    """A torch tensor handed to the library as a device pointer must be float64
+    and live on the context's GPU (the library reads 8 bytes per entry there)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a numpy array or a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{what}: torch tensor must be float64, got {t.dtype}")
+    if not t.is_cuda or t.device.index != ctx.device:
+        raise ValueError(f"{what}: torch tensor must be on cuda:{ctx.device}, got {t.device}")
+    return t
+
+
 class Context:
     """hm_ctx_create / hm_ctx_destroy.  stream: a torch.cuda.Stream, a raw
     hipStream_t as int, or None for the default stream."""
@@ -128,6 +146,7 @@ class Context:
         _check(_lib.hm_ctx_create(int(device), C.c_void_p(raw) if raw else None, C.byref(h)),
                "hm_ctx_create")
         self._h = h
+        self.device = int(device)
         self._datasets = weakref.WeakSet()
         self._servers = weakref.WeakSet()
 
@@ -153,14 +172,21 @@ class Dataset:
     """hm_dataset_*: trees, schedule and device storage for one set of locations."""
 
     def __init__(self, ctx: Context, coords, leaf_size: int = 64, eta: float = 2.0):
-        P = np.ascontiguousarray(coords, dtype=np.float64)
+        """coords: (n, 2) float64, a numpy array or a torch CUDA tensor on the
+        context's device."""
+        if isinstance(coords, np.ndarray) or not hasattr(coords, "data_ptr"):
+            P = np.ascontiguousarray(coords, dtype=np.float64)
+            on_dev = 0
+        else:
+            P = _device_f64(coords, ctx, "coords").contiguous()
+            on_dev = 1
         if P.ndim != 2 or P.shape[1] != 2:
             raise ValueError("coords must be (n, 2)")
         self.ctx = ctx
-        self.n = P.shape[0]
+        self.n = int(P.shape[0])
         opts = hm_tree_opts(int(leaf_size), float(eta))
         h = _P()
-        _check(_lib.hm_dataset_create(ctx._h, _ptr(P), C.c_int64(self.n), C.byref(opts), C.byref(h)),
+        _check(_lib.hm_dataset_create(ctx._h, _ptr(P), C.c_int64(self.n), 2, C.byref(opts), on_dev, C.byref(h)),
                "hm_dataset_create")
         self._h = h
         self.r = 0
@@ -180,6 +206,7 @@ class Dataset:
     def set_z(self, Z):
         on_dev = not isinstance(Z, np.ndarray)
         if on_dev:
+            Z = _device_f64(Z, self.ctx, "Z")
             if Z.dim() == 1:
                 Z = Z[:, None]
             Zc = Z.t().contiguous()     # column-major (n, r) == row-major (r, n)
@@ -200,9 +227,10 @@ class Dataset:
         self.r = r
 
     @staticmethod
-    def _args(theta, nugget, eps, rank):
+    def _args(theta, nugget, eps, rank, prec=HM_FP64, refine_max_iter=0, refine_tol=0.0):
         sigma2, ell, nu = theta
-        return hm_theta(sigma2, ell, nu, nugget), hm_approx(int(rank), float(eps))
+        return (hm_theta(sigma2, ell, nu, nugget),
+                hm_approx(int(rank), float(eps), int(prec), int(refine_max_iter), float(refine_tol)))
 
     def assemble(self, theta, nugget, eps=0.0, rank=0):
         th, ap = self._args(theta, nugget, eps, rank)
@@ -419,6 +447,7 @@ class Server:
 
 
 def _results(out):
-    keys = ("loglik", "logdet", "quadform", "status", "max_rank", "fail_block", "fail_pivot",
-            "t_assemble", "t_factor", "t_solve")
+    keys = ("loglik", "logdet", "quadform", "n", "max_rank", "rank_capped", "bytes_C", "bytes_L", "status",
+            "fail_pivot", "fail_block", "refine_quad", "refine_resid", "refine_iters", "t_assemble", "t_factor",
+            "t_solve")
     return {k: np.array([getattr(o, k) for o in out]) for k in keys}
