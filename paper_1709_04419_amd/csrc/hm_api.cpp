@@ -124,15 +124,17 @@ size_t store_layout(const Plan& P, void* base, DevData& D) {
   const size_t a = up(sizeof(double) * (size_t)P.dense_pool);
   const size_t b = up(sizeof(double) * (size_t)P.lr_pool);
   const size_t c = up(sizeof(double) * (size_t)P.term_pool);
+  const size_t d = up(sizeof(double) * (size_t)P.stage_pool);
   if (base) {
     char* q = static_cast<char*>(base);
     D.dense = (double*)q;
     D.lr = (double*)(q + a);
     D.termbuf = (double*)(q + a + b);
+    D.stage = (double*)(q + a + b + c);
   } else {
-    D.dense = D.lr = D.termbuf = nullptr;
+    D.dense = D.lr = D.termbuf = D.stage = nullptr;
   }
-  return a + b + c + 256;
+  return a + b + c + d + 256;
 }
 
 }  // namespace
@@ -178,6 +180,13 @@ hm_status build_device(hm_dataset* ds) {
   void* p;
   TRY(upload(ds, P.dense_off, const_cast<int64_t**>(&D.dense_off)));
   TRY(upload(ds, P.lr_off, const_cast<int64_t**>(&D.lr_off)));
+  TRY(upload(ds, P.lr_voff, const_cast<int64_t**>(&D.lr_voff)));
+  TRY(upload(ds, P.lr_cap, const_cast<int32_t**>(&D.lr_cap)));
+  TRY(upload(ds, P.stage_off, const_cast<int64_t**>(&D.stage_off)));
+  {
+    std::vector<int32_t> z(2 * T.bk.size(), 0);
+    TRY(upload(ds, z, &D.ts_app));
+  }
   {
     std::vector<int32_t> rk(T.bk.size(), 0);
     TRY(upload(ds, rk, &D.rank));
@@ -198,6 +207,7 @@ hm_status build_device(hm_dataset* ds) {
   TRY(upload(ds, P.sub_begin, const_cast<int32_t**>(&D.sub_begin)));
   TRY(upload(ds, P.sub_end, const_cast<int32_t**>(&D.sub_end)));
   TRY(upload(ds, P.sub_leaves, const_cast<int32_t**>(&D.sub_leaves)));
+  TRY(upload(ds, P.stasks, const_cast<Task**>(&D.stasks)));
   TRY(upload(ds, P.sop_begin, const_cast<int32_t**>(&D.sop_begin)));
   TRY(upload(ds, P.sops, const_cast<SolveOp**>(&D.sops)));
   TRY(dev_alloc(ds, sizeof(double) * T.bk.size(), &p));
@@ -208,14 +218,30 @@ hm_status build_device(hm_dataset* ds) {
   D.nlr = (int32_t)P.lr_ids.size();
   TRY(upload(ds, P.diag_leaf_ids, &ds->d_diag_ids));
   TRY(upload(ds, T.perm, &ds->d_perm));
-  // workspace slots: truncation of (m + n) x 2 K_MAX factors plus small
-  // scratch, or an explicit block of at most dflush x dflush with the
-  // transposed triangular factor of its pivoted QR
+  // workspace slots (one per resident work-group): the largest of
+  //   - the single-task flush of a block of at most max_lr_rows rows and
+  //     columns: (m + n) x 2 K_MAX accumulated factors plus truncation scratch
+  //     (also covers ACA's m x K_MAX and n x K_MAX factors of such blocks);
+  //   - an explicit block of at most dflush x dflush with the transposed
+  //     triangular factor of its pivoted QR;
+  //   - the big blocks' steps: stacked R factors (TS_GMAX p x p per factor,
+  //     p <= 2 K_MAX) plus the core truncation's scratch, or a row block of
+  //     the truncated factor (ts_rows x K_MAX), or ACA's used flags.
   const int64_t mr = P.max_lr_rows > 64 ? P.max_lr_rows : 64;
   D.dflush = DENSE_FLUSH * T.leaf_size;
   const int64_t df = D.dflush;
   int64_t stride = 2 * mr * (2 * K_MAX) + mr + 2 * (2 * K_MAX + 1) * (2 * K_MAX) + 4096;
   if (stride < df * df + (df + 1) * df + 64) stride = df * df + (df + 1) * df + 64;
+  int64_t big_rows = 0;
+  for (int32_t b : P.lr_ids)
+    if (P.lr_cap[b] == 2 * K_MAX) big_rows = std::max(big_rows, std::max(T.bk[b].m, T.bk[b].n));
+  if (big_rows > 0) {
+    const int64_t p = 2 * K_MAX;
+    const int64_t ts = 2 * TS_GMAX * p * p + (p + 1) * p + 4096;
+    stride = std::max(stride, ts);
+    stride = std::max(stride, ts_rows(big_rows) * K_MAX + 64);
+    stride = std::max(stride, big_rows + 2 * (K_MAX + 1) * K_MAX + 64);
+  }
   stride = (stride + 63) & ~(int64_t)63;
   hm_ctx* c = ds->ctx;
   if (c->ws_stride < stride) {
@@ -660,7 +686,11 @@ hm_status hm_solve(hm_dataset* ds, hm_result* out) {
   std::vector<double> res(1 + r, NAN);
   if (ds->factor_status == HM_OK) {
     HIPTRY(hipEventRecord(ds->ev[2], st));
-    HIPTRY(launch_solve(D, ds->d_Z, ds->d_perm, r, ds->d_W, ds->d_diag_ids,
+    DevData Ds = D;
+    Ds.W = ds->d_W;
+    Ds.r = r;
+    HIPTRY(launch_solve(Ds, ds->d_Z, ds->d_perm, ds->plan.slevel_begin.data(),
+                        (int32_t)ds->plan.slevel_begin.size() - 1, NSLOTS, ds->d_diag_ids,
                         (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, st));
     HIPTRY(hipEventRecord(ds->ev[3], st));
     HIPTRY(hipEventSynchronize(ds->ev[3]));
@@ -857,8 +887,9 @@ hm_status hm_get_block(hm_dataset* ds, int64_t block, double* data, int32_t* ran
     int32_t k = 0;
     HIPTRY(hipMemcpy(&k, ds->D.rank + block, sizeof(int32_t), hipMemcpyDeviceToHost));
     const double* U = ds->D.lr + ds->plan.lr_off[block];
+    const double* V = ds->D.lr + ds->plan.lr_voff[block];
     HIPTRY(hipMemcpy(data, U, sizeof(double) * b.m * k, hipMemcpyDeviceToHost));
-    HIPTRY(hipMemcpy(data + b.m * k, U + b.m * K_MAX, sizeof(double) * b.n * k, hipMemcpyDeviceToHost));
+    HIPTRY(hipMemcpy(data + b.m * k, V, sizeof(double) * b.n * k, hipMemcpyDeviceToHost));
     *rank = k;
     return HM_OK;
   }

@@ -32,11 +32,20 @@ struct DevData {
   double* dense;
   const int64_t* dense_off;
   double* lr;
-  const int64_t* lr_off;
+  const int64_t* lr_off;      // U of a low-rank block (m x cap, ld m)
+  const int64_t* lr_voff;     // V (n x cap, ld n)
+  const int32_t* lr_cap;      // cap: K_MAX, or 2 K_MAX for big blocks (flush in place, TASK_TS_*)
+  double* stage;              // staging of the big blocks' flush steps
+  const int64_t* stage_off;
+  int32_t* ts_app;            // big block: column where the current step appends its term
   int32_t* rank;              // per block (low-rank leaves)
   double* termbuf;
   const TermDef* terms;
   const TermInst* insts;
+  // the final forward solve: its tasks (level order) and the permuted data
+  const Task* stasks;
+  double* W;                  // n x r, leading dimension n
+  int32_t r;
   // schedule
   const Task* tasks;
   const int32_t* order;       // execution order of the tasks, level by level
@@ -91,6 +100,9 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
 // dataset), total = the number of tasks over all of them.
 hipError_t launch_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg, int32_t total, int max_grid,
                               hipStream_t st);
-hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,
-                        const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st);
+// Forward solve L v = Z (Z permuted into W, then the solve task levels
+// slevel_begin[0 .. nslev]), log-determinant and v^T v into out.
+hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, const int32_t* slevel_begin,
+                        int32_t nslev, int max_grid, const int32_t* diag_ids, int32_t ndiag, double* out,
+                        hipStream_t st);
 }  // namespace hm

@@ -11,7 +11,8 @@
 //                       accuracy eps or fixed rank k (Remark 2.4, Definition 2.1).
 //   k_level             H-Cholesky (Section 3.2) as a task graph, one launch per
 //                       dependency level, one work-group per task.
-//   k_solve, k_reduce   forward substitution L v = Z, log|C| = 2 sum log L_ii and
+//   k_level_solve       forward substitution L v = Z as a task graph of cluster
+//   k_reduce            solves and row-chunk products; log|C| = 2 sum log L_ii and
 //                       v^T v, assembled into eq. (4) of Section 3.1.
 //
 // One work-group = 256 threads = 4 wavefronts of 64.  All floating point is FP64.
@@ -31,8 +32,6 @@ namespace hm {
 #endif
 #define NT HM_NT
 #define NW (NT / 64)
-// Register tile of a dense leaf: entry e = tid + q NT, q < NQ.
-#define NQ ((LEAF_MAX * LEAF_MAX + NT - 1) / NT)
 // Most columns of a matrix that is truncated in explicit form.
 #define CMAX (4 * LEAF_MAX)
 // Reflectors per block in the compact WY (I - V T V^T) paths for tall panels.
@@ -40,8 +39,6 @@ namespace hm {
 __device__ __forceinline__ int64_t clk() { return (int64_t)__builtin_amdgcn_s_memrealtime(); }
 // LDS arena (doubles) of the executor work-groups: one per CU.
 #define LDS_FACTOR 17408
-// LDS arena of the solve kernel: a diagonal leaf and a 64-column panel.
-#define LDS_SOLVE (LEAF_MAX * LEAF_MAX + (LEAF_MAX + 1) * LEAF_MAX)
 
 // ------------------------------------------------------------------ reductions
 
@@ -187,6 +184,9 @@ __device__ __forceinline__ double entry(const DevData& D, int64_t i, int64_t j) 
   if (i == j) v += D.mc.nugget;
   return v;
 }
+
+__device__ __forceinline__ double* lr_U(const DevData& D, int32_t b) { return D.lr + D.lr_off[b]; }
+__device__ __forceinline__ double* lr_V(const DevData& D, int32_t b) { return D.lr + D.lr_voff[b]; }
 
 // ------------------------------------------------------------------ dense leaves
 
@@ -1208,8 +1208,10 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
 
 // ------------------------------------------------------------------ ACA
 
-// Workspace slot layout for ACA: Ua (m x kmax), Va (n x kmax), row (n),
-// used flags (m as doubles), scratch for truncation.
+// ACA factors Ua (m x kmax), Va (n x kmax): in the workspace slot, or for a
+// big block (storage of 2 K_MAX columns) in the upper half of its own storage,
+// so that the truncation writes U, V into the lower half.  Then used flags (m
+// as doubles) and scratch for the truncation in the slot.
 __global__ void __launch_bounds__(NT) k_aca(DevData D) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
@@ -1220,9 +1222,10 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
     const Block bk = D.bk[b];
     const int64_t m = bk.m, n = bk.n;
     const int kcap = (int)((D.kmax < m) ? ((D.kmax < n) ? D.kmax : n) : ((m < n) ? m : n));
-    double* Ua = slot;
-    double* Va = Ua + m * K_MAX;
-    double* used = Va + n * K_MAX;
+    const bool big = D.lr_cap[b] == 2 * K_MAX;
+    double* Ua = big ? lr_U(D, b) + m * K_MAX : slot;
+    double* Va = big ? lr_V(D, b) + n * K_MAX : Ua + m * K_MAX;
+    double* used = big ? slot : Va + n * K_MAX;
     double* scratch = used + m;
     for (int64_t i = tid; i < m; i += NT) used[i] = 0.0;
     __syncthreads();
@@ -1304,8 +1307,8 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
     // the rank cap stopped the iteration before its accuracy test was met
     const int64_t mn = m < n ? m : n;
     if (tid == 0 && D.kfix <= 0 && D.kmax < mn && k == kcap && !converged) atomicAdd(D.capped, 1);
-    double* U = D.lr + D.lr_off[b];
-    double* V = U + m * K_MAX;
+    double* U = lr_U(D, b);
+    double* V = lr_V(D, b);
     const int kt = wg_truncate(D, Ua, m, Va, n, k, U, V, scratch, dyn, 4096, S);
     if (tid == 0) D.rank[b] = kt;
     __syncthreads();
@@ -1328,34 +1331,37 @@ __device__ __forceinline__ void term_factors(const DevData& D, const TermDef& t,
     X = D.dense + D.dense_off[t.A]; ldx = A.m;
     Y = D.dense + D.dense_off[t.B]; ldy = B.m;
   } else if (t.kind == TK_LRA) {
-    X = D.lr + D.lr_off[t.A]; ldx = A.m;
+    X = lr_U(D, t.A); ldx = A.m;
     Y = D.termbuf + t.buf; ldy = t.rows;
   } else {
     X = D.termbuf + t.buf; ldx = t.rows;
-    Y = D.lr + D.lr_off[t.B]; ldy = B.m;
+    Y = lr_U(D, t.B); ldy = B.m;
   }
 }
 
-// Y += L_blk W for one leaf of the factor: W (ncols(blk) x k, ldw), Y (ldy).
-// tmp: k_blk x k doubles (global or shared).
-__device__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k,
-                            double* Y, int64_t ldy, double sign, double* tmp, Smem& S) {
+// Y(i0:i1, :) += sign L_blk(i0:i1, :) W for one leaf of the factor (rows
+// local to the leaf): W (ncols(blk) x k, ldw), Y (ldy, row 0 = the leaf's
+// first row).  tmp: k_blk x k doubles (global or shared).
+__device__ void leaf_matvec_rows(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k, double* Y,
+                                 int64_t ldy, double sign, double* tmp, Smem& S, int64_t i0, int64_t i1) {
   const Block L = D.bk[blk];
   const int tid = threadIdx.x;
+  const int64_t mr = i1 - i0;
   if (tid == 0)
-    S.flops += (L.kind == BK_DENSE) ? 2.0 * L.m * L.n * k : 2.0 * (double)(L.m + L.n) * D.rank[blk] * k;
+    S.flops += (L.kind == BK_DENSE) ? 2.0 * mr * L.n * k
+                                    : 2.0 * (double)(mr + L.n) * D.rank[blk] * k;
   if (L.kind == BK_DENSE) {
     const double* A = D.dense + D.dense_off[blk];
-    for (int64_t e = tid; e < L.m * (int64_t)k; e += NT) {
-      const int64_t i = e % L.m;
-      const int c = (int)(e / L.m);
+    for (int64_t e = tid; e < mr * (int64_t)k; e += NT) {
+      const int64_t i = i0 + e % mr;
+      const int c = (int)(e / mr);
       double acc = 0.0;
       for (int64_t l = 0; l < L.n; ++l) acc += A[i + l * L.m] * W[l + c * ldw];
       Y[i + c * ldy] += sign * acc;
     }
   } else {
-    const double* U = D.lr + D.lr_off[blk];
-    const double* V = U + L.m * K_MAX;
+    const double* U = lr_U(D, blk);
+    const double* V = lr_V(D, blk);
     const int kb = D.rank[blk];
     // tmp = V^T W  (kb x k)
     const int w = tid >> 6, lane = tid & 63;
@@ -1367,15 +1373,20 @@ __device__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int6
       if (lane == 0) tmp[e] = acc;
     }
     __syncthreads();
-    for (int64_t e = tid; e < L.m * (int64_t)k; e += NT) {
-      const int64_t i = e % L.m;
-      const int c = (int)(e / L.m);
+    for (int64_t e = tid; e < mr * (int64_t)k; e += NT) {
+      const int64_t i = i0 + e % mr;
+      const int c = (int)(e / mr);
       double acc = 0.0;
       for (int a = 0; a < kb; ++a) acc += U[i + (int64_t)a * L.m] * tmp[a + c * kb];
       Y[i + c * ldy] += sign * acc;
     }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k,
+                                            double* Y, int64_t ldy, double sign, double* tmp, Smem& S) {
+  leaf_matvec_rows(D, blk, W, ldw, k, Y, ldy, sign, tmp, S, 0, D.bk[blk].m);
 }
 
 // W <- L_cc^{-1} W over cluster c (W: |c| x k, ldw) by the solve program.
@@ -1422,7 +1433,7 @@ __device__ void task_term(const DevData& D, int32_t tid_term, double* tmp, Smem&
   const int32_t R = (t.kind == TK_LRA) ? t.A : t.B;      // low-rank block providing V
   const Block HB = D.bk[H], RB = D.bk[R];
   const int k = D.rank[R];
-  const double* Vr = D.lr + D.lr_off[R] + RB.m * K_MAX;   // n(R) x k, ld n(R)
+  const double* Vr = lr_V(D, R);   // n(R) x k, ld n(R)
   double* out = D.termbuf + t.buf;                        // rows x k, ld rows
   for (int64_t e = threadIdx.x; e < t.rows * (int64_t)k; e += NT) out[e] = 0.0;
   __syncthreads();
@@ -1433,16 +1444,167 @@ __device__ void task_term(const DevData& D, int32_t tid_term, double* tmp, Smem&
   }
 }
 
+// Rows of chunk cluster q (tk.a1) of a term product (see task_term): the
+// leaves of the H-block in pre-order, each restricted to those rows.
+__device__ void task_term_rows(const DevData& D, const Task& tk, double* tmp, Smem& S) {
+  const TermDef t = D.terms[tk.obj];
+  const int32_t H = (t.kind == TK_LRA) ? t.B : t.A;
+  const int32_t R = (t.kind == TK_LRA) ? t.A : t.B;
+  const Block HB = D.bk[H], RB = D.bk[R];
+  const Cluster q = D.cl[tk.a1];
+  const int k = D.rank[R];
+  const double* Vr = lr_V(D, R);
+  double* out = D.termbuf + t.buf;
+  const int64_t q0 = q.begin - HB.r0, q1 = q.end - HB.r0;
+  for (int64_t e = threadIdx.x; e < (q1 - q0) * (int64_t)k; e += NT) {
+    const int64_t i = q0 + e % (q1 - q0);
+    out[i + (e / (q1 - q0)) * t.rows] = 0.0;
+  }
+  __syncthreads();
+  for (int32_t s = D.sub_begin[H]; s < D.sub_end[H]; ++s) {
+    const int32_t lf = D.sub_leaves[s];
+    const Block L = D.bk[lf];
+    const int64_t a = (q.begin > L.r0 ? q.begin : L.r0), b = (q.end < L.r0 + L.m ? q.end : L.r0 + L.m);
+    if (a >= b) continue;
+    leaf_matvec_rows(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp, S,
+                     a - L.r0, b - L.r0);
+  }
+}
+
+// Target of a solve task: a low-rank block's V (rows relative to its column
+// cluster, rank columns) or the permuted data W of the final solve.
+__device__ __forceinline__ void solve_target(const DevData& D, int32_t obj, double*& W, int64_t& ld, int& k,
+                                             int64_t& base) {
+  if (obj >= 0) {
+    const Block b = D.bk[obj];
+    W = lr_V(D, obj);
+    ld = b.n;
+    k = D.rank[obj];
+    base = b.c0;
+  } else {
+    W = D.W;
+    ld = D.n;
+    k = D.r;
+    base = 0;
+  }
+}
+
+// W(rows of cluster tk.a0) <- L^{-1} W(same rows): the cluster's solve program.
+__device__ void task_solve_seq(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
+  double* W;
+  int64_t ld, base;
+  int k;
+  solve_target(D, tk.obj, W, ld, k, base);
+  if (k <= 0) return;
+  run_solve(D, tk.a0, W + (D.cl[tk.a0].begin - base), ld, k, slot, lds, S);
+}
+
+// W(rows of cluster q = tk.a1) -= L_blk(those rows, :) W(cols of blk), blk =
+// tk.a0, over blk's leaves in pre-order (the order of the solve program).
+__device__ void task_solve_mv(const DevData& D, const Task& tk, double* tmp, Smem& S) {
+  double* W;
+  int64_t ld, base;
+  int k;
+  solve_target(D, tk.obj, W, ld, k, base);
+  if (k <= 0) return;
+  const int32_t blk = tk.a0;
+  const Cluster q = D.cl[tk.a1];
+  for (int32_t s = D.sub_begin[blk]; s < D.sub_end[blk]; ++s) {
+    const int32_t lf = D.sub_leaves[s];
+    const Block L = D.bk[lf];
+    const int64_t a = (q.begin > L.r0 ? q.begin : L.r0), b = (q.end < L.r0 + L.m ? q.end : L.r0 + L.m);
+    if (a >= b) continue;
+    leaf_matvec_rows(D, lf, W + (L.c0 - base), ld, k, W + (L.r0 - base), ld, -1.0, tmp, S, a - L.r0, b - L.r0);
+  }
+}
+
+// ------------------------------------------------------------------ MFMA tiles
+//
+// A dense tile of at most 64 x 64 entries lives in the accumulators of the
+// FP64 matrix instruction v_mfma_f64_16x16x4f64 (D = A B + C, A 16 x 4,
+// B 4 x 16): wavefront w owns tile rows 16 w .. 16 w + 15 and holds them as
+// four 16 x 16 sub-tiles acc[c] (tile columns 16 c .. 16 c + 15).  Lane l of
+// wavefront w holds, in acc[c][q], the entry (16 w + mrow(l, q), 16 c + (l & 15));
+// as an operand, lane l supplies A(l & 15, l >> 4) and B(l >> 4, l & 15).
+// (Accumulator rows (l >> 4) + 4 q: measured on gfx950 with known operands.)
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int mrow(int lane, int q) { return (lane >> 4) + 4 * q; }
+
+struct Tile {
+  dvec4 acc[4];
+};
+
+// acc = src (tm x tn, column-major, ld), zero outside.
+__device__ __forceinline__ void tile_load(Tile& T, const double* src, int64_t ld, int tm, int tn) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * w + mrow(lane, q), j = 16 * c + (lane & 15);
+      T.acc[c][q] = (i < tm && j < tn) ? src[i + (int64_t)j * ld] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void tile_zero(Tile& T) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) T.acc[c] = dvec4{0.0, 0.0, 0.0, 0.0};
+}
+
+__device__ __forceinline__ void tile_store(const Tile& T, double* dst, int64_t ld, int tm, int tn) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * w + mrow(lane, q), j = 16 * c + (lane & 15);
+      if (i < tm && j < tn) dst[i + (int64_t)j * ld] = T.acc[c][q];
+    }
+}
+
+// Tile += sign X Y^T over tile rows [i0, i1) and columns [j0, j1): row i uses
+// X row xr + (i - i0), column j uses Y row yr + (j - j0), r columns each.
+// Entries outside the rectangle are left exactly as they are (their products
+// are formed from zero operands).
+__device__ __forceinline__ void tile_xyT(Tile& T, double sign, const double* X, int64_t ldx, int64_t xr,
+                                         const double* Y, int64_t ldy, int64_t yr, int r, int i0, int i1, int j0,
+                                         int j1) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr0 = 16 * w;
+  if (wr0 >= i1 || wr0 + 16 <= i0) return;          // no row of this wavefront is touched
+  const int i = wr0 + (lane & 15);
+  const bool rowin = i >= i0 && i < i1;
+  const double* xp = X + xr + (rowin ? i - i0 : 0);
+  const int kl = lane >> 4;
+  bool colin[4];
+  const double* yp[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = 16 * c + (lane & 15);
+    colin[c] = j >= j0 && j < j1;
+    yp[c] = Y + yr + (colin[c] ? j - j0 : 0);
+  }
+  const bool cact[4] = {16 * 0 < j1 && 16 * 0 + 16 > j0, 16 * 1 < j1 && 16 * 1 + 16 > j0,
+                        16 * 2 < j1 && 16 * 2 + 16 > j0, 16 * 3 < j1 && 16 * 3 + 16 > j0};
+  for (int k0 = 0; k0 < r; k0 += 4) {
+    const int k = k0 + kl;
+    const bool kin = k < r;
+    const double a = (kin && rowin) ? sign * xp[(int64_t)k * ldx] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (!cact[c]) continue;
+      const double bv = (kin && colin[c]) ? yp[c][(int64_t)k * ldy] : 0.0;
+      T.acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, T.acc[c], 0, 0, 0);
+    }
+  }
+}
+
 // Subtracts a leaf's restricted update terms, in order, from the tm x tn tile
-// at (ti0, tj0) of the block, held in registers (entry e = tid + q NT of the
-// column-major tile in dreg[q]).  Term factors are staged through LDS 32
-// columns at a time.
-__device__ void apply_terms(const DevData& D, const Task& tk, int ti0, int tj0, int tm, int tn, double (&dreg)[NQ],
-                            double* lds, Smem& S) {
+// at (ti0, tj0) of the block (FP64 matrix instructions, factors read from
+// global memory).
+__device__ void apply_terms(const DevData& D, const Task& tk, int ti0, int tj0, int tm, int tn, Tile& T, Smem& S) {
   const int tid = threadIdx.x;
-  const int cnt = tm * tn;
-  double* Xs = lds;                 // 64 x 32 chunk, row stride 33
-  double* Ys = lds + 64 * 33;       // 64 x 32 chunk, row stride 33
   for (int32_t ii = 0; ii < tk.ninst; ++ii) {
     const TermInst in = D.insts[tk.inst_begin + ii];
     // the term's rectangle, clipped to the tile (block coordinates)
@@ -1451,39 +1613,15 @@ __device__ void apply_terms(const DevData& D, const Task& tk, int ti0, int tj0, 
     const int c0 = in.lc0 > tj0 ? in.lc0 : tj0;
     const int c1 = (in.lc0 + in.ny < tj0 + tn) ? in.lc0 + in.ny : tj0 + tn;
     if (r0 >= r1 || c0 >= c1) continue;
-    const int mx = r1 - r0, ny = c1 - c0;
     const TermDef t = D.terms[in.term];
     const int r = term_rank(D, t);
+    if (r == 0) continue;
     const double *X, *Y;
     int64_t ldx, ldy;
     term_factors(D, t, X, ldx, Y, ldy);
-    const int64_t xr = in.xr0 + (r0 - in.lr0), yr = in.yr0 + (c0 - in.lc0);
-    if (tid == 0) S.flops += 2.0 * mx * ny * r;
-    for (int l0 = 0; l0 < r; l0 += 32) {
-      const int lc = (r - l0 < 32) ? (r - l0) : 32;
-      __syncthreads();
-      for (int e = tid; e < mx * lc; e += NT) {
-        const int i = e % mx, l = e / mx;
-        Xs[i * 33 + l] = X[xr + i + (int64_t)(l0 + l) * ldx];
-      }
-      for (int e = tid; e < ny * lc; e += NT) {
-        const int j = e % ny, l = e / ny;
-        Ys[j * 33 + l] = Y[yr + j + (int64_t)(l0 + l) * ldy];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int e = tid + q * NT;
-        if (e < cnt) {
-          const int i = ti0 + e % tm - r0, j = tj0 + e / tm - c0;
-          if (i >= 0 && i < mx && j >= 0 && j < ny) {
-            double acc = 0.0;
-            for (int l = 0; l < lc; ++l) acc += Xs[i * 33 + l] * Ys[j * 33 + l];
-            dreg[q] -= acc;
-          }
-        }
-      }
-    }
+    if (tid == 0) S.flops += 2.0 * (r1 - r0) * (c1 - c0) * r;
+    tile_xyT(T, -1.0, X, ldx, in.xr0 + (r0 - in.lr0), Y, ldy, in.yr0 + (c0 - in.lc0), r, r0 - ti0, r1 - ti0,
+             c0 - tj0, c1 - tj0);
   }
 }
 
@@ -1494,21 +1632,12 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
   const Block bk = D.bk[b];
   const int m = (int)bk.m, n = (int)bk.n;
   double* Dg = D.dense + D.dense_off[b];
-  double dreg[NQ];
   const int cnt = m * n;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = tid + q * NT;
-    dreg[q] = (e < cnt) ? Dg[e] : 0.0;
-  }
-  apply_terms(D, tk, 0, 0, m, n, dreg, lds, S);
-  __syncthreads();
+  Tile T;
+  tile_load(T, Dg, m, m, n);
+  apply_terms(D, tk, 0, 0, m, n, T, S);
   double* A = lds;                  // m x n tile, column-major
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = tid + q * NT;
-    if (e < cnt) A[e] = dreg[q];
-  }
+  tile_store(T, A, m, m, n);
   __syncthreads();
   if (tid == 0) S.flops += (tk.kind == TASK_DIAG) ? (double)m * m * m / 3.0 : (double)m * n * n;
   if (tk.kind == TASK_DIAG) {
@@ -1569,46 +1698,33 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
   const int32_t b = tk.obj;
   const Block bk = D.bk[b];
   const int m = (int)bk.m, n = (int)bk.n;
-  double* U = D.lr + D.lr_off[b];
-  double* V = U + (int64_t)m * K_MAX;
+  double* U = lr_U(D, b);
+  double* V = lr_V(D, b);
   const int k0 = D.rank[b];
   const int64_t c0 = (tid == 0) ? clk() : 0;
   const bool small = m <= LEAF_MAX && n <= LEAF_MAX;
-  const int stage = 2 * 64 * 33;                 // apply_terms staging
   const int lda = small ? (m | 1) : m;
-  double* A = small ? lds + stage : slot;
+  double* A = small ? lds : slot;
   for (int tj0 = 0; tj0 < n; tj0 += LEAF_MAX) {
     for (int ti0 = 0; ti0 < m; ti0 += LEAF_MAX) {
       const int tm = (m - ti0 < LEAF_MAX) ? m - ti0 : LEAF_MAX;
       const int tn = (n - tj0 < LEAF_MAX) ? n - tj0 : LEAF_MAX;
-      const int cnt = tm * tn;
-      double dreg[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int e = tid + q * NT;
-        double acc = 0.0;
-        if (e < cnt) {
-          const int i = ti0 + e % tm, j = tj0 + e / tm;
-          for (int l = 0; l < k0; ++l) acc += U[i + (int64_t)l * m] * V[j + (int64_t)l * n];
-        }
-        dreg[q] = acc;
-      }
-      apply_terms(D, tk, ti0, tj0, tm, tn, dreg, lds, S);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int e = tid + q * NT;
-        if (e < cnt) A[(ti0 + e % tm) + (int64_t)(tj0 + e / tm) * lda] = dreg[q];
-      }
+      Tile T;
+      tile_zero(T);
+      if (k0 > 0) tile_xyT(T, 1.0, U, m, ti0, V, n, tj0, k0, 0, tm, 0, tn);
+      apply_terms(D, tk, ti0, tj0, tm, tn, T, S);
+      tile_store(T, A + ti0 + (int64_t)tj0 * lda, lda, tm, tn);
     }
   }
+  __syncthreads();
   if (tid == 0) {
     S.flops += 2.0 * m * n * k0;
     S.ph[4] += clk() - c0;     // explicit formation
   }
   __syncthreads();
   // R^T of the pivoted QR: after the block in LDS, else from the start of LDS
-  double* glds = small ? lds + stage + lda * n : lds;
-  const int gcap = small ? LDS_FACTOR - stage - lda * n : LDS_FACTOR;
+  double* glds = small ? lds + lda * n : lds;
+  const int gcap = small ? LDS_FACTOR - lda * n : LDS_FACTOR;
   double* gws = slot + (small ? 0 : (int64_t)m * n);
   const int k = wg_svd_explicit(D, A, m, n, lda, U, m, m, V, n, n, gws, glds, gcap, S, true);
   if (tid == 0) D.rank[b] = k;
@@ -1625,8 +1741,8 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   const Block bk = D.bk[b];
   const int64_t m = bk.m, n = bk.n;
   const int RW = 2 * K_MAX;
-  double* U = D.lr + D.lr_off[b];
-  double* V = U + m * K_MAX;
+  double* U = lr_U(D, b);
+  double* V = lr_V(D, b);
   const bool explicit_sum = m <= D.dflush && n <= D.dflush;
   if (tk.ninst > 0 && explicit_sum) {
     const int kk = lr_dense_flush(D, tk, slot, lds, S);
@@ -1644,7 +1760,6 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
       const TermInst in = D.insts[tk.inst_begin + ii];
       const TermDef t = D.terms[in.term];
       const int r = term_rank(D, t);
-      if (r == 0) continue;
       if (rank > 0 && rank + r > R_ACC) {
         const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, scratch, lds, LDS_FACTOR, S);
         for (int64_t e = tid; e < m * kk; e += NT) Xa[e] = U[e];
@@ -1680,23 +1795,225 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   }
   const int k = S.ival[0];
   __syncthreads();
+  if (tk.a0 == 0) return;   // the solve runs as tasks of its own
   int64_t c0 = (tid == 0) ? clk() : 0;
   if (k > 0) run_solve(D, tk.diag, V, n, k, slot, lds, S);
   if (tid == 0) S.ph[3] += clk() - c0;
 }
 
+// ------------------------------------------------------------------ big blocks
+//
+// The factored flush of a big low-rank block (storage of 2 K_MAX columns, the
+// accumulation [U, -X_1, ...] / [V, Y_1, ...] in place) as steps i = 1 .. T+1:
+// if step i truncates (rank > 0 and rank + rank(term i) > R_ACC, or i = T + 1),
+// each row block of both factors is Householder-factorised by its own task
+// (TS_A), one task factorises the stacked R factors, truncates the core and
+// maps the kept singular vectors back through the stacked Q (TS_B), and each
+// row block applies its own Q to its part of them (TS_C); TS_C then appends
+// term i's columns.  Same reflector algebra as a single QR of the whole factor
+// (tall-skinny QR), so the truncation is that of the oracle up to rounding.
+
+// Row block q of a big block: side 0 = U (m rows), 1 = V (n rows); its rows
+// [r0, r1) and the number gs of row blocks of that side.  Same formula as the
+// planner's ts_blocks / ts_rows.
+__device__ __forceinline__ int ts_nblk(int64_t rows) {
+  int64_t g = (rows + TS_MINROWS - 1) / TS_MINROWS;
+  if (g > TS_GMAX) g = TS_GMAX;
+  return g < 1 ? 1 : (int)g;
+}
+
+__device__ __forceinline__ void ts_geom(const Block& bk, int q, int& side, int& g, int& gs, int64_t& r0,
+                                        int64_t& r1) {
+  const int gx = ts_nblk(bk.m);
+  side = q < gx ? 0 : 1;
+  g = side ? q - gx : q;
+  const int64_t rows = side ? bk.n : bk.m;
+  gs = ts_nblk(rows);
+  const int64_t h = (rows + gs - 1) / gs;
+  r0 = g * h;
+  r1 = (r0 + h < rows) ? r0 + h : rows;
+}
+
+// Whether step tk.a0 truncates, given the accumulated rank; r_i = the rank of
+// the step's term (0 for the final step).
+__device__ __forceinline__ bool ts_truncates(const DevData& D, const Task& tk, int rank, int& r_i) {
+  if (tk.a0 > tk.ninst) {
+    r_i = 0;
+    return true;
+  }
+  const TermInst in = D.insts[tk.inst_begin + tk.a0 - 1];
+  r_i = term_rank(D, D.terms[in.term]);
+  return rank > 0 && rank + r_i > R_ACC;
+}
+
+// Householder QR of A (rows x p, ld) in place, through LDS when it fits.
+__device__ void qr_any(double* A, int64_t rows, int p, int64_t ld, double* tau, double* lds, int lds_cap, Smem& S) {
+  const int tid = threadIdx.x;
+  const int64_t lo = odd_ld(rows);
+  if (lo * (int64_t)p <= lds_cap) {
+    for (int64_t e = tid; e < rows * p; e += NT) lds[(e % rows) + (e / rows) * lo] = A[(e % rows) + (e / rows) * ld];
+    __syncthreads();
+    wg_qr(lds, rows, p, lo, tau, S);
+    for (int64_t e = tid; e < rows * p; e += NT) A[(e % rows) + (e / rows) * ld] = lds[(e % rows) + (e / rows) * lo];
+    __syncthreads();
+  } else if (rows > TALL_QR_ROWS) {
+    wg_qr_blocked(A, rows, p, ld, tau, S);
+  } else {
+    wg_qr(A, rows, p, ld, tau, S);
+  }
+}
+
+__device__ void task_ts_a(const DevData& D, const Task& tk, double* lds, Smem& S) {
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int rank = D.rank[b];
+  int ri;
+  if (!ts_truncates(D, tk, rank, ri) || rank == 0) return;
+  int side, g, gs;
+  int64_t r0, r1;
+  ts_geom(bk, tk.a1, side, g, gs, r0, r1);
+  const int64_t ld = side ? bk.n : bk.m;
+  double* A = (side ? lr_V(D, b) : lr_U(D, b)) + r0;
+  double* tau = D.stage + D.stage_off[b] + (int64_t)tk.a1 * 2 * K_MAX;
+  qr_any(A, r1 - r0, rank, ld, tau, lds, LDS_FACTOR, S);
+}
+
+__device__ void task_ts_b(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
+  const int tid = threadIdx.x;
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int p = D.rank[b];
+  int ri;
+  const bool trunc = ts_truncates(D, tk, p, ri);
+  if (!trunc || p == 0) {
+    // no truncation: the term is appended after the current columns
+    if (tid == 0) {
+      D.ts_app[2 * b] = p;
+      D.ts_app[2 * b + 1] = 0;
+      D.rank[b] = p + ri;
+    }
+    return;
+  }
+  const int gx = ts_nblk(bk.m), gy = ts_nblk(bk.n);
+  const int64_t mx = (int64_t)gx * p, my = (int64_t)gy * p;
+  double* Xs = slot;                     // stacked R factors of the U side (mx x p)
+  double* Ys = Xs + mx * p;              // and of the V side (my x p)
+  double* scratch = Ys + my * p;
+  for (int side = 0; side < 2; ++side) {
+    const int gs = side ? gy : gx;
+    const int64_t ms = side ? my : mx;
+    double* St = side ? Ys : Xs;
+    const int64_t rows = side ? bk.n : bk.m;
+    const int64_t h = (rows + gs - 1) / gs;
+    const double* F = side ? lr_V(D, b) : lr_U(D, b);
+    for (int64_t e = tid; e < ms * p; e += NT) {
+      const int64_t i = e % ms;
+      const int j = (int)(e / ms);
+      const int g = (int)(i / p), ii = (int)(i % p);
+      St[e] = (ii <= j) ? F[g * h + ii + (int64_t)j * rows] : 0.0;
+    }
+  }
+  __syncthreads();
+  qr_any(Xs, mx, p, mx, S.tau_x, lds, LDS_FACTOR, S);
+  qr_any(Ys, my, p, my, S.tau_y, lds, LDS_FACTOR, S);
+  // core M = Rx Ry^T (p x p), in LDS
+  const int ldm = (int)odd_ld(p);
+  double* M = lds;
+  for (int e = tid; e < p * p; e += NT) {
+    const int i = e % p, j = e / p;
+    const int l0 = i > j ? i : j;
+    double acc = 0.0;
+    for (int l = l0; l < p; ++l) acc += Xs[i + (int64_t)l * mx] * Ys[j + (int64_t)l * my];
+    M[i + j * ldm] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) S.flops += 2.0 * p * p * p / 3.0;
+  double* Wx = D.stage + D.stage_off[b] + (int64_t)(gx + gy) * 2 * K_MAX;
+  double* Wy = Wx + (int64_t)gx * 2 * K_MAX * K_MAX;
+  const int k = wg_svd_explicit(D, M, p, p, ldm, Wx, mx, mx, Wy, my, my, scratch, lds + ldm * p,
+                                LDS_FACTOR - ldm * p, S);
+  __syncthreads();
+  wg_apply_q(Xs, mx, p, mx, S.tau_x, Wx, k, mx, S);
+  wg_apply_q(Ys, my, p, my, S.tau_y, Wy, k, my, S);
+  if (tid == 0) {
+    D.ts_app[2 * b] = k;
+    D.ts_app[2 * b + 1] = p;
+    D.rank[b] = k + ri;
+  }
+}
+
+__device__ void task_ts_c(const DevData& D, const Task& tk, double* slot, Smem& S) {
+  const int tid = threadIdx.x;
+  const int32_t b = tk.obj;
+  const Block bk = D.bk[b];
+  const int app = D.ts_app[2 * b], p = D.ts_app[2 * b + 1];
+  int side, g, gs;
+  int64_t r0, r1;
+  ts_geom(bk, tk.a1, side, g, gs, r0, r1);
+  const int64_t ld = side ? bk.n : bk.m, rows = r1 - r0;
+  double* A = (side ? lr_V(D, b) : lr_U(D, b)) + r0;
+  if (p > 0 && app > 0) {
+    // rows of the truncated factor: Q_g [W_g; 0], W_g = rows g p .. g p + p - 1 of the small factor
+    const int gx = ts_nblk(bk.m);
+    const int64_t ms = (int64_t)gs * p;
+    const double* W = D.stage + D.stage_off[b] + (int64_t)(gx + ts_nblk(bk.n)) * 2 * K_MAX +
+                      (side ? (int64_t)gx * 2 * K_MAX * K_MAX : 0) + (int64_t)g * p;
+    const double* tau = D.stage + D.stage_off[b] + (int64_t)tk.a1 * 2 * K_MAX;
+    double* tmp = slot;                 // rows x app
+    for (int64_t e = tid; e < rows * app; e += NT) {
+      const int64_t i = e % rows;
+      const int c = (int)(e / rows);
+      tmp[e] = (i < p) ? W[i + (int64_t)c * ms] : 0.0;
+    }
+    __syncthreads();
+    wg_apply_q(A, rows, p, ld, tau, tmp, app, rows, S);
+    __syncthreads();
+    for (int64_t e = tid; e < rows * app; e += NT) A[(e % rows) + (e / rows) * ld] = tmp[e];
+    __syncthreads();
+  }
+  if (tk.a0 > tk.ninst) return;        // the final step appends nothing
+  const TermInst in = D.insts[tk.inst_begin + tk.a0 - 1];
+  const TermDef t = D.terms[in.term];
+  const int r = term_rank(D, t);
+  const double *X, *Y;
+  int64_t ldx, ldy;
+  term_factors(D, t, X, ldx, Y, ldy);
+  const int64_t lo = side ? in.lc0 : in.lr0, len = side ? in.ny : in.mx, f0 = side ? in.yr0 : in.xr0;
+  const double* F = side ? Y : X;
+  const int64_t ldf = side ? ldy : ldx;
+  const double sg = side ? 1.0 : -1.0;
+  for (int64_t e = tid; e < rows * r; e += NT) {
+    const int64_t i = e % rows;
+    const int l = (int)(e / rows);
+    const int64_t li = r0 + i - lo;
+    A[i + (int64_t)(app + l) * ld] = (li >= 0 && li < len) ? sg * F[f0 + li + l * ldf] : 0.0;
+  }
+}
+
 // ------------------------------------------------------------------ executor
 
 // One task of the factorisation (shared by the level executors).
+__device__ void dispatch(const DevData& D, const Task& tk, int32_t prog, double* slot, double* dyn, Smem& S) {
+  switch (tk.kind) {
+    case TASK_TERM: task_term(D, tk.obj, slot, S); break;
+    case TASK_TERM_ROWS: task_term_rows(D, tk, slot, S); break;
+    case TASK_LR: task_lr(D, tk, slot, dyn, S); break;
+    case TASK_SOLVE_SEQ: task_solve_seq(D, tk, slot, dyn, S); break;
+    case TASK_SOLVE_MV: task_solve_mv(D, tk, slot, S); break;
+    case TASK_TS_A: task_ts_a(D, tk, dyn, S); break;
+    case TASK_TS_B: task_ts_b(D, tk, slot, dyn, S); break;
+    case TASK_TS_C: task_ts_c(D, tk, slot, S); break;
+    default: task_dense(D, tk, prog, dyn, S); break;
+  }
+}
+
 __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn, Smem& S) {
   const Task tk = D.tasks[t];
   const int32_t prog = D.task_prog[t];
   int64_t ts = 0;
   if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0; }
   if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
-  if (tk.kind == TASK_TERM) task_term(D, tk.obj, slot, S);
-  else if (tk.kind == TASK_LR) task_lr(D, tk, slot, dyn, S);
-  else task_dense(D, tk, prog, dyn, S);
+  dispatch(D, tk, prog, slot, dyn, S);
   __syncthreads();
   if (D.task_times && threadIdx.x == 0) {
     D.task_times[7 * t] = ts;
@@ -1726,12 +2043,16 @@ __global__ void k_eval_init(unsigned long long* fail_key, int32_t* capped) {
 
 // ------------------------------------------------------------------ solve
 
-// W (n x r, permuted Z) <- L^{-1} W over the whole index set.
-__global__ void __launch_bounds__(NT) k_solve(DevData D, double* W, int r) {
+// One level [t0, t1) of the final forward solve's tasks (stasks, level order).
+__global__ void __launch_bounds__(NT) k_level_solve(DevData D, int32_t t0, int32_t t1) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
-  double* slot = D.ws;
-  run_solve(D, 0, W, D.n, r, slot, dyn, S);
+  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) {
+    const Task tk = D.stasks[q];
+    dispatch(D, tk, -1, slot, dyn, S);
+    __syncthreads();
+  }
 }
 
 // Gather Z into permuted order: W[i, c] = Z[perm[i], c].
@@ -1845,18 +2166,23 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
   return hipGetLastError();
 }
 
-hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, int r, double* W,
-                        const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_permute, dim3(1024), dim3(NT), 0, st, Z, perm, D.n, r, W);
+hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, const int32_t* slevel_begin,
+                        int32_t nslev, int max_grid, const int32_t* diag_ids, int32_t ndiag, double* out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_permute, dim3(1024), dim3(NT), 0, st, Z, perm, D.n, D.r, D.W);
   static bool solve_attr = false;
   if (!solve_attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       LDS_SOLVE * sizeof(double));
+    hipError_t e = hipFuncSetAttribute((const void*)k_level_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_FACTOR * sizeof(double));
     if (e != hipSuccess) return e;
     solve_attr = true;
   }
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(NT), LDS_SOLVE * sizeof(double), st, D, W, r);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, st, D, diag_ids, ndiag, W, r, out);
+  for (int32_t l = 0; l < nslev; ++l) {
+    const int32_t t0 = slevel_begin[l], t1 = slevel_begin[l + 1];
+    const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
+    if (g > 0) hipLaunchKernelGGL(k_level_solve, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);
+  }
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, st, D, diag_ids, ndiag, D.W, D.r, out);
   return hipGetLastError();
 }
 

@@ -182,7 +182,7 @@ struct Planner {
   std::vector<std::vector<TermInst>> leaf_insts;    // block -> ordered instances
   std::vector<Task> tasks;                          // program order
   std::vector<std::vector<int32_t>> tdeps;
-  std::vector<int32_t> term_task;                   // term -> task (-1 for TK_DD)
+  std::vector<std::vector<int32_t>> term_tasks;     // term -> tasks computing its factor (none for TK_DD)
   std::vector<int32_t> sub_end;                     // block -> one past its pre-order subtree
   std::vector<int32_t> leaf_rank;                   // block -> #leaves with smaller id
 
@@ -204,7 +204,7 @@ struct Planner {
     for (int32_t i = leaf_rank[b]; i < leaf_rank[sub_end[b]]; ++i) out.push_back(P.sub_leaves[i]);
   }
 
-  int32_t new_task(int8_t kind, int32_t obj, std::vector<int32_t> deps) {
+  int32_t new_task(int8_t kind, int32_t obj, std::vector<int32_t> deps, int32_t a0 = 0, int32_t a1 = 0) {
     std::sort(deps.begin(), deps.end());
     deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
     if (!deps.empty() && deps.front() < 0) throw std::logic_error("dependency on an unfinished block");
@@ -212,9 +212,68 @@ struct Planner {
     t.kind = kind;
     t.obj = obj;
     t.diag = -1;
+    t.a0 = a0;
+    t.a1 = a1;
     tasks.push_back(t);
     tdeps.push_back(std::move(deps));
     return (int32_t)tasks.size() - 1;
+  }
+
+  // Clusters below x (x itself if small enough) of at most `limit` points
+  // (or leaves), left to right.
+  void chunks_of(int32_t x, int64_t limit, std::vector<int32_t>& out) const {
+    if (C(x).end - C(x).begin <= limit || is_leaf(C(x))) {
+      out.push_back(x);
+      return;
+    }
+    chunks_of(C(x).son[0], limit, out);
+    chunks_of(C(x).son[1], limit, out);
+  }
+
+  // Leaves of block b whose rows meet the rows of cluster q, in pre-order.
+  void leaves_in_rows(int32_t b, int32_t q, std::vector<int32_t>& out) const {
+    for (int32_t i = leaf_rank[b]; i < leaf_rank[sub_end[b]]; ++i) {
+      const int32_t l = P.sub_leaves[i];
+      if (B(l).r0 < C(q).end && B(l).r0 + B(l).m > C(q).begin) out.push_back(l);
+    }
+  }
+
+  // The forward substitution W(c) <- L_cc^{-1} W(c) of target `tgt` (a
+  // low-rank block's V, or -1 for the data) as tasks: clusters of at most
+  // SOLVE_SEQ points in one task by their solve program; larger ones as
+  // W(c1) solve, W(c2) -= L21 W(c1) in row chunks, W(c2) solve.  Every row
+  // receives the same operations in the same order as the cluster's solve
+  // program.  `deps` must precede every task; with factor_deps the tasks also
+  // wait for the factor leaves they read.  Returns the task after which all of
+  // W(c) is final.
+  int32_t emit_solve(int32_t tgt, int32_t c, const std::vector<int32_t>& deps, bool factor_deps) {
+    const int32_t d = T.diag_of[c];
+    if (C(c).end - C(c).begin <= SOLVE_SEQ || is_leaf(C(c))) {
+      std::vector<int32_t> dp = deps;
+      if (factor_deps) {
+        std::vector<int32_t> lv;
+        leaves_of(d, lv);
+        for (int32_t l : lv) dp.push_back(final_task[l]);
+      }
+      return new_task(TASK_SOLVE_SEQ, tgt, dp, c, 0);
+    }
+    const int32_t c1 = C(c).son[0], c2 = C(c).son[1];
+    const int32_t t1 = emit_solve(tgt, c1, deps, factor_deps);
+    const int32_t b21 = son(d, c2, c1);
+    std::vector<int32_t> qs;
+    chunks_of(c2, SOLVE_CHUNK, qs);
+    std::vector<int32_t> mv = deps;
+    for (int32_t q : qs) {
+      std::vector<int32_t> dp = deps;
+      dp.push_back(t1);
+      if (factor_deps) {
+        std::vector<int32_t> lv;
+        leaves_in_rows(b21, q, lv);
+        for (int32_t l : lv) dp.push_back(final_task[l]);
+      }
+      mv.push_back(new_task(TASK_SOLVE_MV, tgt, dp, b21, q));
+    }
+    return emit_solve(tgt, c2, mv, factor_deps);
   }
 
   void push(int32_t bid, int64_t R0, int64_t C0, int32_t term, int64_t xoff, int64_t yoff,
@@ -280,12 +339,19 @@ struct Planner {
         d.rows = 0;
       }
       d.buf = -1;
+      term_tasks.emplace_back();
       if (d.rows > 0) {
         d.buf = P.term_pool;
         P.term_pool += d.rows * K_MAX;
-        term_task.push_back(new_task(TASK_TERM, tid, deps));
-      } else {
-        term_task.push_back(-1);
+        // rows of the computed factor = rows of the H-block applied
+        const int32_t hrow = (d.kind == TK_LRA) ? B(Bb).row : B(A).row;
+        if (d.rows > TERM_SPLIT) {
+          std::vector<int32_t> qs;
+          chunks_of(hrow, SOLVE_CHUNK, qs);
+          for (int32_t q : qs) term_tasks[tid].push_back(new_task(TASK_TERM_ROWS, tid, deps, 0, q));
+        } else {
+          term_tasks[tid].push_back(new_task(TASK_TERM, tid, deps));
+        }
       }
       P.terms.push_back(d);
       push(tg.bid, tg.R0, tg.C0, tid, 0, 0, mx, ny);
@@ -313,18 +379,47 @@ struct Planner {
       }
   }
 
+  void inst_deps_one(const TermInst& in, std::vector<int32_t>& deps) const {
+    const TermDef& d = P.terms[in.term];
+    if (d.kind == TK_DD) {
+      deps.push_back(final_task[d.A]);
+      deps.push_back(final_task[d.B]);
+    } else {
+      for (int32_t q : term_tasks[in.term]) deps.push_back(q);
+    }
+  }
+
   std::vector<int32_t> inst_deps(int32_t bid) const {
     std::vector<int32_t> deps;
-    for (const TermInst& in : leaf_insts[bid]) {
-      const TermDef& d = P.terms[in.term];
-      if (d.kind == TK_DD) {
-        deps.push_back(final_task[d.A]);
-        deps.push_back(final_task[d.B]);
-      } else {
-        deps.push_back(term_task[in.term]);
-      }
-    }
+    for (const TermInst& in : leaf_insts[bid]) inst_deps_one(in, deps);
     return deps;
+  }
+
+  // Factored flush of a big low-rank block (T >= 1 pending terms) as steps
+  // 1 .. T + 1 of TASK_TS_A (per row block), TASK_TS_B, TASK_TS_C (per row
+  // block); `extra` must precede the final truncation.  Returns the final
+  // step's row-block tasks.
+  std::vector<int32_t> emit_ts(int32_t bid, const std::vector<int32_t>& extra) {
+    const Block& b = B(bid);
+    const int gx = ts_blocks(b.m), gy = ts_blocks(b.n), g = gx + gy;
+    const int32_t T1 = (int32_t)leaf_insts[bid].size() + 1;
+    std::vector<int32_t> prevC;   // C tasks of the previous step, by row block
+    for (int32_t i = 1; i <= T1; ++i) {
+      std::vector<int32_t> as;
+      for (int q = 0; q < g; ++q) {
+        std::vector<int32_t> dp;
+        if (!prevC.empty()) dp.push_back(prevC[q]);
+        as.push_back(new_task(TASK_TS_A, bid, dp, i, q));
+      }
+      std::vector<int32_t> bd = as;
+      if (i == T1) bd.insert(bd.end(), extra.begin(), extra.end());
+      const int32_t tb = new_task(TASK_TS_B, bid, bd, i, 0);
+      std::vector<int32_t> cd{tb};
+      if (i < T1) inst_deps_one(leaf_insts[bid][i - 1], cd);
+      prevC.clear();
+      for (int q = 0; q < g; ++q) prevC.push_back(new_task(TASK_TS_C, bid, cd, i, q));
+    }
+    return prevC;
   }
 
   void htrsm(int32_t bid) {
@@ -340,13 +435,29 @@ struct Planner {
       return;
     }
     if (b.kind == BK_LR) {
-      std::vector<int32_t> deps = inst_deps(bid);
       std::vector<int32_t> lv;
       leaves_of(T.diag_of[sig], lv);
-      for (int32_t l : lv) deps.push_back(final_task[l]);
+      std::vector<int32_t> lfin;
+      for (int32_t l : lv) lfin.push_back(final_task[l]);
+      if (std::max(b.m, b.n) > TS_BIG && !leaf_insts[bid].empty()) {
+        // the flush as parallel steps, then V <- L^{-1} V as solve tasks
+        const std::vector<int32_t> fin = emit_ts(bid, lfin);
+        final_task[bid] = emit_solve(bid, sig, fin, false);
+        return;
+      }
+      std::vector<int32_t> deps = inst_deps(bid);
+      deps.insert(deps.end(), lfin.begin(), lfin.end());
       int32_t t = new_task(TASK_LR, bid, deps);
       tasks[t].diag = sig;
-      final_task[bid] = t;
+      if (b.n > SOLVE_SEQ && !is_leaf(C(sig))) {
+        // V <- L_{sigma sigma}^{-1} V as a chain of solve tasks (the flush task
+        // already waits for every leaf of L_{sigma sigma})
+        tasks[t].a0 = 0;
+        final_task[bid] = emit_solve(bid, sig, {t}, false);
+      } else {
+        tasks[t].a0 = 1;
+        final_task[bid] = t;
+      }
       return;
     }
     int32_t rho = b.row;
@@ -436,6 +547,10 @@ struct Planner {
     // storage
     P.dense_off.assign(nb, -1);
     P.lr_off.assign(nb, -1);
+    P.lr_voff.assign(nb, -1);
+    P.lr_cap.assign(nb, 0);
+    P.stage_off.assign(nb, -1);
+    P.stage_pool = 0;
     P.dense_pool = P.lr_pool = P.term_pool = 0;
     P.n_dense_entries = 0;
     P.max_lr_rows = 0;
@@ -448,10 +563,20 @@ struct Planner {
         P.dense_ids.push_back(b);
         if (bb.row == bb.col) P.diag_leaf_ids.push_back(b);
       } else if (bb.kind == BK_LR) {
+        const bool big = std::max(bb.m, bb.n) > TS_BIG;
+        const int32_t cap = big ? 2 * K_MAX : K_MAX;
+        P.lr_cap[b] = cap;
         P.lr_off[b] = P.lr_pool;
-        P.lr_pool += (bb.m + bb.n) * (int64_t)K_MAX;
+        P.lr_voff[b] = P.lr_pool + bb.m * cap;
+        P.lr_pool += (bb.m + bb.n) * (int64_t)cap;
         P.lr_ids.push_back(b);
-        P.max_lr_rows = std::max(P.max_lr_rows, std::max(bb.m, bb.n));
+        if (big) {
+          P.stage_off[b] = P.stage_pool;
+          const int64_t g = ts_blocks(bb.m) + ts_blocks(bb.n);
+          P.stage_pool += g * 2 * K_MAX * (1 + K_MAX);
+        } else {
+          P.max_lr_rows = std::max(P.max_lr_rows, std::max(bb.m, bb.n));
+        }
       }
     }
     // symbolic factorisation in program order
@@ -478,6 +603,7 @@ struct Planner {
     P.deps.clear();
     P.insts.clear();
     P.max_level = 0;
+    std::vector<int32_t> ts_inst(nb, -1);   // big block -> first of its instances in P.insts
     for (int32_t k = 0; k < nt; ++k) {
       int32_t i = order[k];
       Task t = tasks[i];
@@ -488,8 +614,15 @@ struct Planner {
       t.ndeps = (int32_t)tdeps[i].size();
       t.inst_begin = (int32_t)P.insts.size();
       t.ninst = 0;
-      if (t.kind != TASK_TERM) {
+      if (t.kind == TASK_DIAG || t.kind == TASK_OFFD || t.kind == TASK_LR) {
         for (const TermInst& in : leaf_insts[t.obj]) P.insts.push_back(in);
+        t.ninst = (int32_t)leaf_insts[t.obj].size();
+      } else if (t.kind == TASK_TS_A || t.kind == TASK_TS_B || t.kind == TASK_TS_C) {
+        if (ts_inst[t.obj] < 0) {
+          ts_inst[t.obj] = (int32_t)P.insts.size();
+          for (const TermInst& in : leaf_insts[t.obj]) P.insts.push_back(in);
+        }
+        t.inst_begin = ts_inst[t.obj];
         t.ninst = (int32_t)leaf_insts[t.obj].size();
       }
       P.tasks.push_back(t);
@@ -506,10 +639,66 @@ struct Planner {
       solve_prog(c, C(c).begin, P.sops);
     }
     P.sop_begin[nc] = (int32_t)P.sops.size();
+    // the final forward solve as a task graph of its own (it runs after the
+    // whole factorisation, so it needs no dependencies on factor tasks)
+    tasks.clear();
+    tdeps.clear();
+    emit_solve(-1, 0, {}, false);
+    const int32_t ns = (int32_t)tasks.size();
+    std::vector<int32_t> slev(ns, 0);
+    for (int32_t i = 0; i < ns; ++i)
+      for (int32_t d : tdeps[i]) {
+        if (d >= i) throw std::logic_error("solve dependency not earlier in program order");
+        slev[i] = std::max(slev[i], slev[d] + 1);
+      }
+    std::vector<int32_t> sorder(ns);
+    for (int32_t i = 0; i < ns; ++i) sorder[i] = i;
+    std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t a, int32_t b) { return slev[a] < slev[b]; });
+    std::vector<int32_t> srank(ns);
+    for (int32_t i = 0; i < ns; ++i) srank[sorder[i]] = i;
+    P.stasks.clear();
+    P.sdeps.clear();
+    P.slevel_begin.clear();
+    for (int32_t k = 0; k < ns; ++k) {
+      const int32_t i = sorder[k];
+      Task t = tasks[i];
+      t.level = slev[i];
+      if (P.slevel_begin.size() <= (size_t)t.level) P.slevel_begin.push_back(k);
+      t.dep_begin = (int32_t)P.sdeps.size();
+      for (int32_t d : tdeps[i]) P.sdeps.push_back(srank[d]);
+      t.ndeps = (int32_t)tdeps[i].size();
+      t.inst_begin = t.ninst = 0;
+      P.stasks.push_back(t);
+    }
+    P.slevel_begin.push_back(ns);
   }
 };
 
 }  // namespace
+
+// A solve task's target rows: the low-rank block's column cluster (obj >= 0)
+// or the whole index set (obj = -1); every cluster and block it reads lies
+// inside them.
+template <class F>
+static void check_solve_task(const Tree& T, const Task& t, F fail) {
+  const int32_t nb = (int32_t)T.bk.size(), nc = (int32_t)T.cl.size();
+  int64_t lo = 0, hi = T.n;
+  if (t.obj >= 0) {
+    if (t.obj >= nb || T.bk[t.obj].kind != BK_LR) fail("solve target");
+    lo = T.bk[t.obj].c0;
+    hi = lo + T.bk[t.obj].n;
+  }
+  if (t.kind == TASK_SOLVE_SEQ) {
+    if (t.a0 < 0 || t.a0 >= nc) fail("solve cluster");
+    if (T.cl[t.a0].begin < lo || T.cl[t.a0].end > hi) fail("solve cluster rows");
+    return;
+  }
+  if (t.a0 < 0 || t.a0 >= nb || t.a1 < 0 || t.a1 >= nc) fail("solve product ids");
+  const Block& b = T.bk[t.a0];
+  const Cluster& q = T.cl[t.a1];
+  if (b.r0 < lo || b.r0 + b.m > hi || b.c0 < lo || b.c0 + b.n > hi) fail("solve product block");
+  if (q.begin < b.r0 || q.end > b.r0 + b.m) fail("solve product chunk");
+}
 
 // Bounds and ordering checks of everything the device will index with.
 static void validate(const Tree& T, const Plan& P) {
@@ -521,13 +710,32 @@ static void validate(const Tree& T, const Plan& P) {
       const int32_t d = P.deps[t.dep_begin + q];
       if (d < 0 || d >= k) fail("dependency not earlier in ticket order");
     }
-    if (t.kind == TASK_TERM) {
+    if (t.kind == TASK_TERM || t.kind == TASK_TERM_ROWS) {
       if (t.obj < 0 || t.obj >= (int32_t)P.terms.size()) fail("term id");
+      if (t.kind == TASK_TERM_ROWS) {
+        const TermDef& d = P.terms[t.obj];
+        const int32_t hrow = (d.kind == TK_LRA) ? T.bk[d.B].row : T.bk[d.A].row;
+        const Cluster& H = T.cl[hrow];
+        if (t.a1 < 0 || t.a1 >= (int32_t)T.cl.size()) fail("term chunk cluster");
+        const Cluster& q = T.cl[t.a1];
+        if (d.kind == TK_DD || q.begin < H.begin || q.end > H.end) fail("term chunk rows");
+      }
+      continue;
+    }
+    if (t.kind == TASK_SOLVE_SEQ || t.kind == TASK_SOLVE_MV) {
+      check_solve_task(T, t, fail);
       continue;
     }
     if (t.obj < 0 || t.obj >= nb) fail("task block id");
     const Block& b = T.bk[t.obj];
-    if (t.kind == TASK_LR) {
+    if (t.kind == TASK_TS_A || t.kind == TASK_TS_B || t.kind == TASK_TS_C) {
+      if (b.kind != BK_LR || std::max(b.m, b.n) <= TS_BIG || P.lr_cap[t.obj] != 2 * K_MAX ||
+          P.stage_off[t.obj] < 0)
+        fail("big low-rank step block");
+      if (t.a0 < 1 || t.a0 > t.ninst + 1) fail("big low-rank step index");
+      if (t.kind != TASK_TS_B && (t.a1 < 0 || t.a1 >= ts_blocks(b.m) + ts_blocks(b.n))) fail("row block");
+      if (ts_rows(b.m) < 2 * K_MAX || ts_rows(b.n) < 2 * K_MAX) fail("row block height");
+    } else if (t.kind == TASK_LR) {
       if (b.kind != BK_LR || t.diag != b.col) fail("low-rank task");
     } else {
       if (b.kind != BK_DENSE || b.m > LEAF_MAX || b.n > LEAF_MAX) fail("dense task");
@@ -559,6 +767,17 @@ static void validate(const Tree& T, const Plan& P) {
   }
   for (const TermDef& d : P.terms)
     if (d.kind != TK_DD && (d.buf < 0 || d.buf + d.rows * K_MAX > P.term_pool)) fail("term buffer");
+  const int64_t ns = (int64_t)P.stasks.size();
+  if (P.slevel_begin.empty() || P.slevel_begin.back() != ns) fail("solve levels");
+  for (int64_t k = 0; k < ns; ++k) {
+    const Task& t = P.stasks[k];
+    if (t.obj != -1 || (t.kind != TASK_SOLVE_SEQ && t.kind != TASK_SOLVE_MV)) fail("final solve task");
+    check_solve_task(T, t, fail);
+    for (int32_t q = 0; q < t.ndeps; ++q) {
+      const int32_t d = P.sdeps[t.dep_begin + q];
+      if (d < 0 || d >= k || P.stasks[d].level >= t.level) fail("final solve dependency");
+    }
+  }
   for (size_t c = 0; c + 1 < P.sop_begin.size(); ++c) {
     const int64_t len = T.cl[c].end - T.cl[c].begin;
     for (int32_t o = P.sop_begin[c]; o < P.sop_begin[c + 1]; ++o) {

@@ -60,20 +60,61 @@ struct TermInst {
 };
 
 enum TaskKind : int8_t {
-  TASK_DIAG = 0,    // dense diagonal leaf: flush + Cholesky
-  TASK_OFFD = 1,    // dense off-diagonal leaf: flush + triangular solve
-  TASK_LR = 2,      // low-rank leaf: flush (truncation) + V <- L^-1 V
-  TASK_TERM = 3,    // compute the product factor of a term
+  TASK_DIAG = 0,       // dense diagonal leaf: flush + Cholesky
+  TASK_OFFD = 1,       // dense off-diagonal leaf: flush + triangular solve
+  TASK_LR = 2,         // low-rank leaf: flush (truncation), then V <- L^-1 V if a0 == 1
+  TASK_TERM = 3,       // compute the product factor of a term
+  TASK_SOLVE_SEQ = 4,  // W(rows of cluster a0) <- L^-1 W(same rows), the cluster's solve program
+  TASK_SOLVE_MV = 5,   // W(rows of cluster a1) -= L_blk(those rows, :) W(cols of blk), blk = a0
+  TASK_TERM_ROWS = 6,  // rows of cluster a1 of the product factor of term obj
+  // Factored flush of a big low-rank block obj (see ts_rows) as steps: before
+  // term a0 (1-based; a0 = T + 1 is the final truncation after the last of its
+  // T terms) the accumulated [U, -X_1, ..][V, Y_1, ..] is truncated if its rank
+  // would exceed R_ACC, then term a0 is appended:
+  TASK_TS_A = 7,       //   row block a1: Householder QR of its rows (if truncating)
+  TASK_TS_B = 8,       //   stacked R factors: QR, core SVD, small factors; new rank
+  TASK_TS_C = 9,       //   row block a1: its rows of the truncated factor, then the term's columns
 };
+// W of the solve tasks: obj >= 0 is the V factor of that low-rank block (its
+// rows relative to the block's column cluster), obj = -1 the permuted data of
+// the final forward solve.
 
 struct Task {
   int8_t kind;
-  int32_t obj;             // block id (DIAG/OFFD/LR) or term id (TERM)
+  int32_t obj;             // block id (DIAG/OFFD/LR/SOLVE_*, -1: the data) or term id (TERM*)
   int32_t dep_begin, ndeps;  // into Plan::deps (task indices, already in ticket order)
   int32_t inst_begin, ninst; // into Plan::insts (leaf tasks)
   int32_t diag;            // DIAG/OFFD: diagonal leaf block of the column cluster; LR: column cluster
   int32_t level;           // longest-path depth
+  int32_t a0, a1;          // kind-specific (see TaskKind)
 };
+
+// Solves over clusters of at most SOLVE_SEQ points run as one task; larger
+// ones are split at their sons, with the coupling product W2 -= L21 W1 done in
+// row chunks of at most SOLVE_CHUNK points.  Term products with more than
+// TERM_SPLIT rows are computed in row chunks of at most SOLVE_CHUNK points.
+constexpr int64_t SOLVE_SEQ = 512;
+constexpr int64_t SOLVE_CHUNK = 512;
+constexpr int64_t TERM_SPLIT = 1024;
+
+// Low-rank blocks with more than TS_BIG rows or columns take their factored
+// flush as TASK_TS_* steps: their factors are stored with 2 K_MAX columns, the
+// accumulation lives there in place, and every truncation runs on row blocks
+// of the two factors in parallel (QR of each row block, then one QR of the
+// stacked R factors: tall-skinny QR).
+constexpr int64_t TS_BIG = 2048;
+constexpr int TS_GMAX = 16;          // row blocks per factor at most
+constexpr int64_t TS_MINROWS = 1024; // rows per row block at least (>= 2 K_MAX)
+// Row blocks of a factor with `rows` rows: g blocks of ceil(rows / g) rows.
+inline int ts_blocks(int64_t rows) {
+  int64_t g = (rows + TS_MINROWS - 1) / TS_MINROWS;
+  if (g > TS_GMAX) g = TS_GMAX;
+  return g < 1 ? 1 : (int)g;
+}
+inline int64_t ts_rows(int64_t rows) {
+  const int g = ts_blocks(rows);
+  return (rows + g - 1) / g;
+}
 
 // One step of the H forward substitution W <- L_cc^{-1} W over a cluster c:
 //   SOP_TRSV  : W[off .. off+m) <- L_blk^{-1} W[off ..)   (blk dense diagonal leaf)
@@ -99,7 +140,14 @@ struct Tree {
 struct Plan {
   // storage
   std::vector<int64_t> dense_off;   // block id -> offset (doubles) in dense pool, -1 otherwise
-  std::vector<int64_t> lr_off;      // block id -> offset of U (m*K_MAX) then V (n*K_MAX)
+  std::vector<int64_t> lr_off;      // block id -> offset of U (m x cap), then V (n x cap), cap = lr_cap
+  std::vector<int64_t> lr_voff;     // block id -> offset of V
+  std::vector<int32_t> lr_cap;      // block id -> columns of its U and V storage (K_MAX, or 2 K_MAX if big)
+  // big low-rank blocks (TASK_TS_*): offset of their staging area (row-block
+  // Householder coefficients and the small factors of the last truncation),
+  // -1 otherwise; stage_pool doubles in all
+  std::vector<int64_t> stage_off;
+  int64_t stage_pool = 0;
   int64_t dense_pool = 0, lr_pool = 0, term_pool = 0;
   std::vector<int32_t> dense_ids, lr_ids, diag_leaf_ids;  // leaves by kind (pre-order)
   // leaves (pre-order) of every block's subtree: sub_leaves[sub_begin[b] .. sub_end[b])
@@ -115,6 +163,11 @@ struct Plan {
   // solve programs per cluster, CSR
   std::vector<int32_t> sop_begin;
   std::vector<SolveOp> sops;
+  // the final forward solve L v = Z as its own task graph (solve tasks with
+  // obj = -1), in level order: stasks[slevel_begin[l] .. slevel_begin[l + 1])
+  std::vector<Task> stasks;
+  std::vector<int32_t> sdeps;
+  std::vector<int32_t> slevel_begin;
   // work counters (algorithmic)
   int64_t n_dense_entries = 0;
   int64_t max_lr_rows = 0;      // max(m, n) over low-rank leaves

@@ -242,9 +242,12 @@ bool admit(hm_server* sv, Request* q, int k) {
 bool enqueue_solve(hm_server* sv, int k) {
   Slot& s = sv->slots[k];
   hm_dataset* ds = s.req->ds;
-  const DevData D = slot_view(s);
+  DevData D = slot_view(s);
+  D.W = ds->d_W;
+  D.r = ds->r;
   return hipEventRecord(s.ev_sol0, s.st) == hipSuccess &&
-         launch_solve(D, ds->d_Z, ds->d_perm, ds->r, ds->d_W, ds->d_diag_ids,
+         launch_solve(D, ds->d_Z, ds->d_perm, ds->plan.slevel_begin.data(),
+                      (int32_t)ds->plan.slevel_begin.size() - 1, sv->grid, ds->d_diag_ids,
                       (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, s.st) == hipSuccess &&
          hipMemcpyAsync(s.h_out, ds->d_out, sizeof(double) * (1 + ds->r), hipMemcpyDeviceToHost, s.st) ==
              hipSuccess &&

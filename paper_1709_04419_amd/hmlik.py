@@ -21,6 +21,13 @@ LIB_PATH = os.path.join(_HERE, "libhmlik.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1709_04419_amd.build`")
+# One HIP runtime per process: torch ships its own libamdhip64 (soname
+# libamdhip64.so.7, loaded under the unversioned name).  Loading torch first
+# makes the library bind to that same runtime, so that torch tensors and
+# streams can be handed to it; loading the library first would give the
+# process two runtimes, and torch would then find no GPU.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 (HM_OK, HM_ERR_ARG, HM_ERR_NOT_SPD, HM_ERR_OOM, HM_ERR_DEVICE, HM_ERR_INTERNAL, HM_ERR_CANCELLED,

@@ -6,13 +6,13 @@ Only `oracle/` and the seeded input generators are used.  Cases:
 
   * basin, n = 256,000 (80% uniform in a non-convex basin, 20% in ten Gaussian
     clusters, seed 31), theta = (1, 0.1, 0.325), nugget 1e-6, leaf 64, eta 2,
-    accuracy eps = 1e-7 (Remark 2.4);
+    accuracy eps = 1e-7 (Remark 2.4); the same at n = 64,000 (seed 33);
   * uniform on [0,1]^2, n = 64,000 (seed 21), nugget 1e-6, leaf 64, eta 2, fixed
     rank (Definition 2.1): ell in {0.05, 0.2} x nu in {0.5, 1.0, 1.5} at k = 10,
     and k = 5, 20 at ell = 0.05, nu = 0.5.
 
-Z is one seeded standard-normal column (seed 32 for the basin, 22 for the
-uniform cloud).  Each case records L~, log|C~|, v^T v (eq. (4), Section 3.1),
+Z is one seeded standard-normal column (seed 32 / 34 for the basin clouds, 22
+for the uniform cloud).  Each case records L~, log|C~|, v^T v (eq. (4), Section 3.1),
 the status with the failing block and pivot on a breakdown, the largest rank,
 whether the rank cap bound, and the storage of C~ and L~ in bytes at the actual
 ranks (dense entries plus (m + n) k per low-rank block, 8 bytes each).
@@ -35,7 +35,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 OUT = os.path.join(HERE, "fullsize.json")
 
-CASES = [("basin256k_eps1e-7", "basin", 256000, 31, 32, (1.0, 0.1, 0.325), 1e-7, 0)]
+CASES = [("basin256k_eps1e-7", "basin", 256000, 31, 32, (1.0, 0.1, 0.325), 1e-7, 0),
+         ("basin64k_eps1e-7", "basin", 64000, 33, 34, (1.0, 0.1, 0.325), 1e-7, 0)]
 for _ell in (0.05, 0.2):
     for _nu in (0.5, 1.0, 1.5):
         CASES.append((f"uniform64k_l{_ell}_nu{_nu}_k10", "uniform", 64000, 21, 22, (1.0, _ell, _nu), 0.0, 10))
