@@ -241,6 +241,70 @@ hm_status hm_get_term(hm_dataset *ds, int64_t term, double *data, int32_t *kind,
 hm_status hm_test_truncate(hm_dataset *ds, const double *X, int64_t m, const double *Y, int64_t n, int32_t r,
                            double eps, int32_t fixed_rank, double *U, double *V, int32_t *k, double *seconds);
 
+/* ---------------------------------------------------------------- operators
+ *
+ * Products and solves with the last evaluation's factor L~ and matrix C~, for
+ * simulating data (Sect. 4: Z = L~ W with W standard normal), the accuracy
+ * diagnostics of Sect. 2.4 and the refinement of C~^{-1} Z (Sect. 3.1).
+ * W and Y are n x r column-major (1 <= r <= 64) in input (not permuted)
+ * order; the library applies the tree permutation P itself, so the operators
+ * are those of the input ordering: with M the matrix in tree order, Y =
+ * P^T M P W.  on_device != 0: W and Y are device pointers on the dataset's
+ * device, else host pointers (a host W must be finite).  Each call waits for
+ * its result.  Uses three n x 64 device buffers of the dataset, allocated on
+ * the first call. */
+typedef enum {
+  HM_OP_L = 0,        /* Y = L~ W (requires a successful factorisation) */
+  HM_OP_LT = 1,       /* Y = L~^T W */
+  HM_OP_C = 2,        /* Y = C~ W with the assembled H-matrix (requires hm_dataset_keep_matrix
+                         before the last assembly) */
+  HM_OP_SOLVE = 3,    /* Y = (L~ L~^T)^{-1} W: forward, then backward substitution */
+  HM_OP_C_EXACT = 4   /* Y = C(theta) W with the exact covariance of eq. (2) plus the nugget on
+                         the diagonal, theta of the last assembly; n^2 entries formed on the fly */
+} hm_operator;
+
+/* keep != 0: every later assembly also copies C~ (its dense leaves, low-rank
+ * factors and ranks, one device allocation of the size of the matrix
+ * storage) for HM_OP_C; keep == 0 frees the copy. */
+hm_status hm_dataset_keep_matrix(hm_dataset *ds, int32_t keep);
+
+/* Y = op W (hm_operator).  HM_ERR_ARG when the operator's matrix is not
+ * available (no successful factorisation, no kept copy, no assembly). */
+hm_status hm_apply(hm_dataset *ds, int32_t op, const double *W, double *Y, int32_t r, int32_t on_device);
+
+/* Simulated data (Sect. 4): assembles and factorises C~(theta) at accuracy
+ * approx, then Z = L~ W for the caller's standard-normal W (n x r, input
+ * order), so that Cov(Z) = C~(theta).  HM_ERR_NOT_SPD on a breakdown. */
+hm_status hm_simulate(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, const double *W, double *Z,
+                      int32_t r, int32_t on_device);
+
+/* Accuracy of the factorisation (Sect. 2.4, Theorem 1's eps): *norm ~
+ * ||I - (L~ L~^T)^{-1} C||_2 with C the exact covariance at the last theta, by
+ * `iters` steps of the power iteration on A^T A, A = I - (L~ L~^T)^{-1} C,
+ * from the start vector x0 (n entries, host, input order, not zero).  Each
+ * step applies C twice (n^2 entries each) and solves with L~ L~^T twice. */
+hm_status hm_inverse_accuracy(hm_dataset *ds, const double *x0, int32_t iters, double *norm);
+
+/* Allocation-free truncation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the computation of hm_test_truncate -- the best approximation
+ * of X Y^T (X: m x r, Y: n x r, 1 <= r <= 128), or of the explicit m x n
+ * matrix X when Y == NULL and r == 0 (n <= 256), at relative accuracy eps
+ * (fixed_rank == 0) or rank fixed_rank -- with every pointer a device
+ * pointer on ctx's device: X, Y are read, U (m x 64) and V (n x 64) receive
+ * the k factors (column-major, leading dimensions m and n) and *k (a device
+ * int32) the rank.  The work is enqueued on ctx's stream and the call returns
+ * without waiting; nothing is allocated or freed.  The workspace is one fixed
+ * array per GPU of 4 Mi doubles (32 MiB, held until the process ends): a call
+ * whose workspace (m + n) r + 2 (r + 1) r + 64 doubles, or m n + (n | 1)
+ * min(m, n) + 64 in the explicit form, exceeds 4 Mi - 64 is refused with
+ * HM_ERR_ARG before anything is enqueued.  Every
+ * call on a GPU shares that array, so calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the
+ * caller. */
+hm_status hm_truncate_noalloc(hm_ctx *ctx, const double *X, int64_t m, const double *Y, int64_t n, int32_t r,
+                              double eps, int32_t fixed_rank, double *U, double *V, int32_t *k);
+
 /* ------------------------------------------------------------------ serving
  *
  * A request server evaluates eq. (4) (Sect. 3.1) for a stream of requests

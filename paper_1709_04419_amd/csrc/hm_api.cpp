@@ -208,6 +208,8 @@ hm_status build_device(hm_dataset* ds) {
   TRY(upload(ds, P.sub_end, const_cast<int32_t**>(&D.sub_end)));
   TRY(upload(ds, P.sub_leaves, const_cast<int32_t**>(&D.sub_leaves)));
   TRY(upload(ds, P.stasks, const_cast<Task**>(&D.stasks)));
+  TRY(upload(ds, P.btasks, &ds->d_btasks));
+  TRY(upload(ds, P.apply_chunks, &ds->d_chunks));
   TRY(upload(ds, P.sop_begin, const_cast<int32_t**>(&D.sop_begin)));
   TRY(upload(ds, P.sops, const_cast<SolveOp**>(&D.sops)));
   TRY(dev_alloc(ds, sizeof(double) * T.bk.size(), &p));
@@ -295,6 +297,11 @@ hm_status hm_ctx_create(int device, void* stream, hm_ctx** out) {
     return HM_ERR_DEVICE;
   }
   HIPTRY(hipSetDevice(device));
+  // this GPU's copy of the allocation-free entry point's workspace
+  if (noalloc_scratch_init(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return HM_ERR_DEVICE;
+  }
   hm_ctx* c = new (std::nothrow) hm_ctx;
   if (!c) return HM_ERR_OOM;
   c->device = device;
@@ -403,7 +410,7 @@ void hm_dataset_destroy(hm_dataset* ds) {
   (void)hipSetDevice(ds->ctx->device);
   (void)hipStreamSynchronize(ds->ctx->stream);
   for (auto& b : ds->bufs) (void)hipFree(b.p);
-  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out})
+  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out, (void*)ds->d_op, ds->c_store})
     if (q) (void)hipFree(q);
   if (ds->store) (void)hipFree(ds->store);
   for (int i = 0; i < 4; ++i)
@@ -534,6 +541,17 @@ hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* a
   HIPTRY(launch_eval_init(Dl, st));
   HIPTRY(launch_assemble(Dl, st));
   HIPTRY(launch_aca(Dl, ws ? grid : NSLOTS, st));
+  ds->theta_set = true;
+  ds->c_valid = false;
+  if (ds->keep_c && ds->c_store) {
+    const Plan& P = ds->plan;
+    char* q = static_cast<char*>(ds->c_store);
+    const size_t bd = sizeof(double) * (size_t)P.dense_pool, bl = sizeof(double) * (size_t)P.lr_pool;
+    HIPTRY(hipMemcpyAsync(q, D.dense, bd, hipMemcpyDeviceToDevice, st));
+    HIPTRY(hipMemcpyAsync(q + bd, D.lr, bl, hipMemcpyDeviceToDevice, st));
+    HIPTRY(hipMemcpyAsync(q + bd + bl, D.rank, sizeof(int32_t) * ds->tree.bk.size(), hipMemcpyDeviceToDevice, st));
+    ds->c_valid = true;
+  }
   HIPTRY(hipEventRecord(ds->ev[1], st));
   return HM_OK;
 }
@@ -984,6 +1002,181 @@ hm_status hm_test_truncate(hm_dataset* ds, const double* X, int64_t m, const dou
   for (void* q : {dX, dY, dU, dV, dk, dph})
     if (q) (void)hipFree(q);
   return s;
+}
+
+hm_status hm_truncate_noalloc(hm_ctx* ctx, const double* X, int64_t m, const double* Y, int64_t n, int32_t r,
+                              double eps, int32_t fixed_rank, double* U, double* V, int32_t* k) {
+  const bool expl = (Y == nullptr);
+  if (!ctx || !X || !U || !V || !k || m < 1 || n < 1) return HM_ERR_ARG;
+  if (busy(ctx)) return HM_ERR_BUSY;
+  if (expl ? (r != 0 || n > 4 * LEAF_MAX) : (r < 1 || r > 2 * K_MAX)) return HM_ERR_ARG;
+  if (fixed_rank < 0 || fixed_rank > K_MAX || (fixed_rank == 0 && !finite_pos(eps))) return HM_ERR_ARG;
+  // workspace of the kernel (as in hm_test_truncate) within the fixed array
+  const int64_t need = expl ? m * n + (n | 1) * (m < n ? m : n) + 64
+                            : (m + n) * (int64_t)r + 2 * (int64_t)(r + 1) * r + 64;
+  if (need > NOALLOC_DOUBLES - 64) return HM_ERR_ARG;
+  double* base = noalloc_scratch(ctx->device);
+  if (!base) return HM_ERR_DEVICE;
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return HM_ERR_DEVICE;
+  }
+  DevData D{};
+  D.kfix = fixed_rank;
+  D.eps = fixed_rank > 0 ? 0.0 : eps;
+  D.kmax = fixed_rank > 0 ? fixed_rank : K_MAX;
+  if (launch_truncate_noalloc(D, base, X, m, Y, n, r, U, V, k, ctx->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return HM_ERR_DEVICE;
+  }
+  return HM_OK;
+}
+
+hm_status hm_dataset_keep_matrix(hm_dataset* ds, int32_t keep) {
+  if (!ds) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  if (!keep) {
+    if (ds->c_store) {
+      HIPTRY(hipStreamSynchronize(ds->ctx->stream));
+      (void)hipFree(ds->c_store);
+    }
+    ds->c_store = nullptr;
+    ds->c_bytes = 0;
+    ds->keep_c = ds->c_valid = false;
+    return HM_OK;
+  }
+  if (!ds->c_store) {
+    const Plan& P = ds->plan;
+    const size_t b = sizeof(double) * ((size_t)P.dense_pool + (size_t)P.lr_pool) +
+                     sizeof(int32_t) * ds->tree.bk.size() + 256;
+    if (hipMalloc(&ds->c_store, b) != hipSuccess) {
+      (void)hipGetLastError();
+      ds->c_store = nullptr;
+      return HM_ERR_OOM;
+    }
+    ds->c_bytes = b;
+  }
+  ds->keep_c = true;
+  return HM_OK;
+}
+
+hm_status hm_apply(hm_dataset* ds, int32_t op, const double* W, double* Y, int32_t r, int32_t on_device) {
+  if (!ds || !W || !Y || r < 1 || r > 64 || op < HM_OP_L || op > HM_OP_C_EXACT) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  const bool need_factor = op == HM_OP_L || op == HM_OP_LT || op == HM_OP_SOLVE;
+  if (need_factor && !(ds->factored && ds->factor_status == HM_OK && ds->store)) return HM_ERR_ARG;
+  if (op == HM_OP_C && !ds->c_valid) return HM_ERR_ARG;
+  if (op == HM_OP_C_EXACT && !ds->theta_set) return HM_ERR_ARG;
+  const int64_t n = ds->tree.n;
+  if (on_device) {
+    hipPointerAttribute_t a{}, b{};
+    if (hipPointerGetAttributes(&a, W) != hipSuccess || hipPointerGetAttributes(&b, Y) != hipSuccess ||
+        a.type != hipMemoryTypeDevice || b.type != hipMemoryTypeDevice || a.device != ds->ctx->device ||
+        b.device != ds->ctx->device) {
+      (void)hipGetLastError();
+      return HM_ERR_ARG;
+    }
+  } else {
+    for (int64_t i = 0; i < n * (int64_t)r; ++i)
+      if (!std::isfinite(W[i])) return HM_ERR_ARG;
+  }
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  hipStream_t st = ds->ctx->stream;
+  if (!ds->d_op) {
+    if (hipMalloc((void**)&ds->d_op, sizeof(double) * 3 * n * 64) != hipSuccess) {
+      (void)hipGetLastError();
+      ds->d_op = nullptr;
+      return HM_ERR_OOM;
+    }
+  }
+  double* A = ds->d_op;              // input, tree order
+  double* B = A + n * 64;            // output, tree order
+  double* T = B + n * 64;            // input-order staging of host data
+  const double* src = W;
+  if (!on_device) {
+    HIPTRY(hipMemcpyAsync(T, W, sizeof(double) * n * r, hipMemcpyHostToDevice, st));
+    src = T;
+  }
+  HIPTRY(launch_permute(src, ds->d_perm, n, r, A, st));
+  use_ctx_ws(ds);
+  DevData D = ds->D;
+  D.W = A;
+  D.Y = B;
+  D.r = r;
+  const double* res = B;
+  if (op == HM_OP_L || op == HM_OP_LT) {
+    HIPTRY(launch_apply(D, op == HM_OP_L ? 0 : 1, ds->d_chunks, (int32_t)ds->plan.apply_chunks.size(), NSLOTS, st));
+  } else if (op == HM_OP_C) {
+    const Plan& P = ds->plan;
+    char* q = static_cast<char*>(ds->c_store);
+    D.dense = (double*)q;
+    D.lr = (double*)(q + sizeof(double) * (size_t)P.dense_pool);
+    D.rank = (int32_t*)(q + sizeof(double) * ((size_t)P.dense_pool + (size_t)P.lr_pool));
+    HIPTRY(launch_apply(D, 2, ds->d_chunks, (int32_t)ds->plan.apply_chunks.size(), NSLOTS, st));
+  } else if (op == HM_OP_SOLVE) {
+    HIPTRY(launch_task_levels(D, D.stasks, ds->plan.slevel_begin.data(), (int32_t)ds->plan.slevel_begin.size() - 1,
+                              NSLOTS, st));
+    HIPTRY(launch_task_levels(D, ds->d_btasks, ds->plan.blevel_begin.data(),
+                              (int32_t)ds->plan.blevel_begin.size() - 1, NSLOTS, st));
+    res = A;
+  } else {
+    for (int32_t c0 = 0; c0 < r; c0 += 4) {
+      DevData Dc = D;
+      Dc.W = A + c0 * n;
+      Dc.Y = B + c0 * n;
+      Dc.r = std::min(4, r - c0);
+      HIPTRY(launch_dense_matvec(Dc, st));
+    }
+  }
+  if (on_device) {
+    HIPTRY(launch_unpermute(res, ds->d_perm, n, r, Y, st));
+    HIPTRY(hipStreamSynchronize(st));
+  } else {
+    HIPTRY(launch_unpermute(res, ds->d_perm, n, r, T, st));
+    HIPTRY(hipMemcpyAsync(Y, T, sizeof(double) * n * r, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+  }
+  return HM_OK;
+}
+
+hm_status hm_simulate(hm_dataset* ds, const hm_theta* theta, const hm_approx* approx, const double* W, double* Z,
+                      int32_t r, int32_t on_device) {
+  if (!ds || !W || !Z || r < 1 || r > 64) return HM_ERR_ARG;
+  TRY(hm_assemble(ds, theta, approx));
+  const hm_status s = hm_factor(ds);
+  if (s != HM_OK) return s;
+  return hm_apply(ds, HM_OP_L, W, Z, r, on_device);
+}
+
+hm_status hm_inverse_accuracy(hm_dataset* ds, const double* x0, int32_t iters, double* norm) {
+  if (!ds || !x0 || !norm || iters < 1) return HM_ERR_ARG;
+  if (!(ds->factored && ds->factor_status == HM_OK && ds->theta_set)) return HM_ERR_ARG;
+  const int64_t n = ds->tree.n;
+  std::vector<double> x(x0, x0 + n), y(n), t(n);
+  auto nrm = [](const std::vector<double>& v) {
+    double s = 0.0;
+    for (double a : v) s += a * a;
+    return std::sqrt(s);
+  };
+  double s = nrm(x);
+  if (!(s > 0.0) || !std::isfinite(s)) return HM_ERR_ARG;
+  for (double& a : x) a /= s;
+  // power iteration on A^T A, A = I - (L L^T)^{-1} C, A^T = I - C (L L^T)^{-1}
+  double lam = 0.0;
+  for (int32_t it = 0; it < iters; ++it) {
+    TRY(hm_apply(ds, HM_OP_C_EXACT, x.data(), t.data(), 1, 0));
+    TRY(hm_apply(ds, HM_OP_SOLVE, t.data(), y.data(), 1, 0));
+    for (int64_t i = 0; i < n; ++i) y[i] = x[i] - y[i];            // y = A x
+    TRY(hm_apply(ds, HM_OP_SOLVE, y.data(), t.data(), 1, 0));
+    TRY(hm_apply(ds, HM_OP_C_EXACT, t.data(), x.data(), 1, 0));
+    for (int64_t i = 0; i < n; ++i) x[i] = y[i] - x[i];            // x = A^T y
+    lam = nrm(x);                                                   // ||A^T A x|| with ||x|| = 1
+    if (!(lam > 0.0)) break;
+    for (double& a : x) a /= lam;
+  }
+  *norm = std::sqrt(lam);
+  return HM_OK;
 }
 
 }  // extern "C"

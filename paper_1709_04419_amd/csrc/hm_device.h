@@ -45,6 +45,7 @@ struct DevData {
   // the final forward solve: its tasks (level order) and the permuted data
   const Task* stasks;
   double* W;                  // n x r, leading dimension n
+  double* Y;                  // n x r output of the operator products (TASK_APPLY)
   int32_t r;
   // schedule
   const Task* tasks;
@@ -89,6 +90,16 @@ hipError_t launch_assemble(const DevData& D, hipStream_t st);
 hipError_t launch_aca(const DevData& D, int grid, hipStream_t st);
 hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
                                 int r, double* U, double* V, int32_t* kout, int64_t* phases, hipStream_t st);
+// Allocation-free truncation: a fixed per-GPU device array of NOALLOC_DOUBLES
+// doubles (counters, then workspace).  noalloc_scratch_init resolves this
+// GPU's copy once (hipGetSymbolAddress with the device current);
+// noalloc_scratch returns it (nullptr before init).
+constexpr int64_t NOALLOC_DOUBLES = 4 << 20;   // 32 MiB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch_init(int device);
+double* noalloc_scratch(int device);
+hipError_t launch_truncate_noalloc(DevData D, double* base, const double* X, int64_t m, const double* Y, int64_t n,
+                                   int r, double* U, double* V, int32_t* kout, hipStream_t st);
 // Clears the breakdown record and the rank-cap counter of an evaluation (before
 // its assembly).
 hipError_t launch_eval_init(const DevData& D, hipStream_t st);
@@ -100,6 +111,19 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
 // dataset), total = the number of tasks over all of them.
 hipError_t launch_level_batch(const DevData* Ds, const int32_t* seg, int32_t nseg, int32_t total, int max_grid,
                               hipStream_t st);
+// Operators on D.W / D.Y (n x D.r, tree order, leading dimension n):
+// `nlev` levels [level_begin[l], level_begin[l + 1]) of a solve task graph
+// (tasks on the device, in level order); the row-chunk product of mode 0 (L),
+// 1 (L^T) or 2 (symmetric matrix of the stored lower blocks); the exact
+// covariance product Y = C W (entries of eq. 2 plus nugget formed on the fly,
+// D.r <= 4); and the permutations between input and tree order.
+hipError_t launch_task_levels(const DevData& D, const Task* tasks, const int32_t* level_begin, int32_t nlev,
+                              int max_grid, hipStream_t st);
+hipError_t launch_apply(const DevData& D, int mode, const int32_t* chunks, int32_t nchunks, int max_grid,
+                        hipStream_t st);
+hipError_t launch_dense_matvec(const DevData& D, hipStream_t st);
+hipError_t launch_permute(const double* Z, const int64_t* perm, int64_t n, int r, double* W, hipStream_t st);
+hipError_t launch_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z, hipStream_t st);
 // Forward solve L v = Z (Z permuted into W, then the solve task levels
 // slevel_begin[0 .. nslev]), log-determinant and v^T v into out.
 hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, const int32_t* slevel_begin,

@@ -11,15 +11,20 @@
 //                       accuracy eps or fixed rank k (Remark 2.4, Definition 2.1).
 //   k_level             H-Cholesky (Section 3.2) as a task graph, one launch per
 //                       dependency level, one work-group per task.
-//   k_level_solve       forward substitution L v = Z as a task graph of cluster
-//   k_reduce            solves and row-chunk products; log|C| = 2 sum log L_ii and
-//                       v^T v, assembled into eq. (4) of Section 3.1.
+//   k_level_tasks       forward substitution L v = Z (and the backward one with
+//                       L^T) as task graphs of cluster solves and row-chunk products;
+//   k_reduce            log|C| = 2 sum log L_ii and v^T v, assembled into eq. (4)
+//                       of Section 3.1.
+//   k_apply             products with L, L^T and the assembled matrix (simulation
+//                       of data, refinement, accuracy diagnostics); k_dense_matvec
+//                       the product with the exact covariance.
 //
 // One work-group = 256 threads = 4 wavefronts of 64.  All floating point is FP64.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "hm_device.h"
 
@@ -1143,9 +1148,9 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
 // QR of both factors, the small core Rx Ry^T truncated by wg_svd_explicit, and
 // its factors mapped back through the reflectors.  Writes U (m x k, ldu = m)
 // and V (n x k, ldv = n); returns k.
-// scratch: at least 2 (r + 1) r doubles of global workspace.
+// work: at least 2 (r + 1) r doubles of global workspace.
 __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, int64_t n, int r,
-                           double* U, double* V, double* scratch, double* lds_g, int lds_cap, Smem& S) {
+                           double* U, double* V, double* work, double* lds_g, int lds_cap, Smem& S) {
   const int tid = threadIdx.x;
   if (r == 0) return 0;
   int64_t c0 = (tid == 0) ? clk() : 0;
@@ -1171,7 +1176,7 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
   // M = Rx Ry^T (px x py), in LDS when it fits
   const int ldm = (int)odd_ld(px);
   const bool m_lds = (int64_t)ldm * py <= lds_cap;
-  double* M = m_lds ? lds_g : scratch;
+  double* M = m_lds ? lds_g : work;
   for (int e = tid; e < px * py; e += NT) {
     const int i = e % px, j = e / px;
     const int l0 = i > j ? i : j;
@@ -1189,7 +1194,7 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
   // core: U = [Uc ; 0], V = [Vc ; 0] with Uc Vc^T the best approximation of M
   double* gl_lds = m_lds ? lds_g + (int64_t)ldm * py : lds_g;
   const int gl_cap = m_lds ? lds_cap - ldm * py : lds_cap;
-  double* gws = m_lds ? scratch : scratch + (int64_t)ldm * py;
+  double* gws = m_lds ? work : work + (int64_t)ldm * py;
   const int k = wg_svd_explicit(D, M, px, py, ldm, U, m, m, V, n, n, gws, gl_lds, gl_cap, S);
   if (tid == 0) { const int64_t c1 = clk(); S.ph[1] += c1 - c0; c0 = c1; }
   __syncthreads();
@@ -1211,7 +1216,7 @@ __device__ int wg_truncate(const DevData& D, double* X, int64_t m, double* Y, in
 // ACA factors Ua (m x kmax), Va (n x kmax): in the workspace slot, or for a
 // big block (storage of 2 K_MAX columns) in the upper half of its own storage,
 // so that the truncation writes U, V into the lower half.  Then used flags (m
-// as doubles) and scratch for the truncation in the slot.
+// as doubles) and work for the truncation in the slot.
 __global__ void __launch_bounds__(NT) k_aca(DevData D) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
@@ -1226,7 +1231,7 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
     double* Ua = big ? lr_U(D, b) + m * K_MAX : slot;
     double* Va = big ? lr_V(D, b) + n * K_MAX : Ua + m * K_MAX;
     double* used = big ? slot : Va + n * K_MAX;
-    double* scratch = used + m;
+    double* work = used + m;
     for (int64_t i = tid; i < m; i += NT) used[i] = 0.0;
     __syncthreads();
     int k = 0;
@@ -1309,7 +1314,7 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
     if (tid == 0 && D.kfix <= 0 && D.kmax < mn && k == kcap && !converged) atomicAdd(D.capped, 1);
     double* U = lr_U(D, b);
     double* V = lr_V(D, b);
-    const int kt = wg_truncate(D, Ua, m, Va, n, k, U, V, scratch, dyn, 4096, S);
+    const int kt = wg_truncate(D, Ua, m, Va, n, k, U, V, work, dyn, 4096, S);
     if (tid == 0) D.rank[b] = kt;
     __syncthreads();
   }
@@ -1384,6 +1389,50 @@ __device__ void leaf_matvec_rows(const DevData& D, int32_t blk, const double* W,
   __syncthreads();
 }
 
+// Y(j0:j1, :) += sign L_blk(:, j0:j1)^T W for one leaf (columns local to the
+// leaf): W (nrows(blk) x k, ldw, row 0 = the leaf's first row), Y (ldy, row 0
+// = the leaf's first column).  tmp: k_blk x k doubles.
+__device__ void leaf_matvec_t_rows(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k, double* Y,
+                                   int64_t ldy, double sign, double* tmp, Smem& S, int64_t j0, int64_t j1) {
+  const Block L = D.bk[blk];
+  const int tid = threadIdx.x;
+  const int64_t nc = j1 - j0;
+  if (tid == 0)
+    S.flops += (L.kind == BK_DENSE) ? 2.0 * nc * L.m * k : 2.0 * (double)(nc + L.m) * D.rank[blk] * k;
+  if (L.kind == BK_DENSE) {
+    const double* A = D.dense + D.dense_off[blk];
+    for (int64_t e = tid; e < nc * (int64_t)k; e += NT) {
+      const int64_t j = j0 + e % nc;
+      const int c = (int)(e / nc);
+      double acc = 0.0;
+      for (int64_t i = 0; i < L.m; ++i) acc += A[i + j * L.m] * W[i + c * ldw];
+      Y[j + c * ldy] += sign * acc;
+    }
+  } else {
+    const double* U = lr_U(D, blk);
+    const double* V = lr_V(D, blk);
+    const int kb = D.rank[blk];
+    // tmp = U^T W  (kb x k)
+    const int w = tid >> 6, lane = tid & 63;
+    for (int e = w; e < kb * k; e += NW) {
+      const int a = e % kb, c = e / kb;
+      double acc = 0.0;
+      for (int64_t i = lane; i < L.m; i += 64) acc += U[i + a * L.m] * W[i + c * ldw];
+      acc = wave_sum(acc);
+      if (lane == 0) tmp[e] = acc;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < nc * (int64_t)k; e += NT) {
+      const int64_t j = j0 + e % nc;
+      const int c = (int)(e / nc);
+      double acc = 0.0;
+      for (int a = 0; a < kb; ++a) acc += V[j + (int64_t)a * L.n] * tmp[a + c * kb];
+      Y[j + c * ldy] += sign * acc;
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void leaf_matvec(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k,
                                             double* Y, int64_t ldy, double sign, double* tmp, Smem& S) {
   leaf_matvec_rows(D, blk, W, ldw, k, Y, ldy, sign, tmp, S, 0, D.bk[blk].m);
@@ -1422,6 +1471,42 @@ __device__ void run_solve(const DevData& D, int32_t c, double* W, int64_t ldw, i
       __syncthreads();
     } else {
       leaf_matvec(D, op.blk, W + op.off2, ldw, k, W + op.off, ldw, -1.0, tmp, S);
+    }
+  }
+}
+
+// W <- L_cc^{-T} W over cluster c: the cluster's solve program backwards with
+// every operation transposed (upper triangular leaf solves, W(cols) -= L^T W(rows)).
+__device__ void run_solve_t(const DevData& D, int32_t c, double* W, int64_t ldw, int k, double* tmp, double* lds,
+                            Smem& S) {
+  const int tid = threadIdx.x;
+  for (int32_t o = D.sop_begin[c + 1] - 1; o >= D.sop_begin[c]; --o) {
+    const SolveOp op = D.sops[o];
+    const Block L = D.bk[op.blk];
+    if (op.kind == SOP_TRSV) {
+      const double* A = D.dense + D.dense_off[op.blk];
+      const int mm = (int)L.m;
+      double* Ls = lds;
+      double* Ws = lds + LEAF_MAX * LEAF_MAX;
+      const int ldl = LEAF_MAX + 1;
+      double* w = W + op.off;
+      if (tid == 0) S.flops += (double)mm * mm * k;
+      for (int e = tid; e < mm * mm; e += NT) Ls[e] = A[e];
+      for (int e = tid; e < mm * k; e += NT) Ws[(e % mm) + (e / mm) * ldl] = w[(e % mm) + (int64_t)(e / mm) * ldw];
+      __syncthreads();
+      for (int cc = tid; cc < k; cc += NT) {
+        double* wc = Ws + cc * ldl;
+        for (int i = mm - 1; i >= 0; --i) {
+          double sum = wc[i];
+          for (int l = i + 1; l < mm; ++l) sum -= Ls[l + i * mm] * wc[l];
+          wc[i] = sum / Ls[i + i * mm];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < mm * k; e += NT) w[(e % mm) + (int64_t)(e / mm) * ldw] = Ws[(e % mm) + (e / mm) * ldl];
+      __syncthreads();
+    } else {
+      leaf_matvec_t_rows(D, op.blk, W + op.off, ldw, k, W + op.off2, ldw, -1.0, tmp, S, 0, L.n);
     }
   }
 }
@@ -1515,6 +1600,52 @@ __device__ void task_solve_mv(const DevData& D, const Task& tk, double* tmp, Sme
     const int64_t a = (q.begin > L.r0 ? q.begin : L.r0), b = (q.end < L.r0 + L.m ? q.end : L.r0 + L.m);
     if (a >= b) continue;
     leaf_matvec_rows(D, lf, W + (L.c0 - base), ld, k, W + (L.r0 - base), ld, -1.0, tmp, S, a - L.r0, b - L.r0);
+  }
+}
+
+// W(rows of cluster tk.a0) <- L^{-T} W(same rows) of the data.
+__device__ void task_solve_seq_t(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
+  if (D.r <= 0) return;
+  run_solve_t(D, tk.a0, D.W + D.cl[tk.a0].begin, D.n, D.r, slot, lds, S);
+}
+
+// W(rows of cluster q = tk.a1) -= L_blk(:, those rows)^T W(rows of blk), blk =
+// tk.a0, over blk's leaves in pre-order.
+__device__ void task_solve_mv_t(const DevData& D, const Task& tk, double* tmp, Smem& S) {
+  if (D.r <= 0) return;
+  const int32_t blk = tk.a0;
+  const Cluster q = D.cl[tk.a1];
+  for (int32_t s = D.sub_begin[blk]; s < D.sub_end[blk]; ++s) {
+    const int32_t lf = D.sub_leaves[s];
+    const Block L = D.bk[lf];
+    const int64_t a = (q.begin > L.c0 ? q.begin : L.c0), b = (q.end < L.c0 + L.n ? q.end : L.c0 + L.n);
+    if (a >= b) continue;
+    leaf_matvec_t_rows(D, lf, D.W + L.r0, D.n, D.r, D.W + L.c0, D.n, -1.0, tmp, S, a - L.c0, b - L.c0);
+  }
+}
+
+// Y(rows of cluster q = tk.a1) = M W for the leaves of the whole partition:
+// M = L (tk.a0 = 0: each leaf's own product), L^T (1: each leaf transposed) or
+// the symmetric matrix whose lower blocks are stored (2: both, the diagonal
+// leaves once).  Y, W: D.Y, D.W (n x D.r, leading dimension n).
+__device__ void task_apply(const DevData& D, const Task& tk, double* tmp, Smem& S) {
+  const int k = D.r;
+  if (k <= 0) return;
+  const Cluster q = D.cl[tk.a1];
+  const int64_t len = q.end - q.begin;
+  for (int64_t e = threadIdx.x; e < len * (int64_t)k; e += NT) D.Y[q.begin + e % len + (e / len) * D.n] = 0.0;
+  __syncthreads();
+  for (int32_t s = D.sub_begin[0]; s < D.sub_end[0]; ++s) {
+    const int32_t lf = D.sub_leaves[s];
+    const Block L = D.bk[lf];
+    if (tk.a0 != 1) {
+      const int64_t a = (q.begin > L.r0 ? q.begin : L.r0), b = (q.end < L.r0 + L.m ? q.end : L.r0 + L.m);
+      if (a < b) leaf_matvec_rows(D, lf, D.W + L.c0, D.n, k, D.Y + L.r0, D.n, 1.0, tmp, S, a - L.r0, b - L.r0);
+    }
+    if (tk.a0 == 1 || (tk.a0 == 2 && L.r0 != L.c0)) {
+      const int64_t a = (q.begin > L.c0 ? q.begin : L.c0), b = (q.end < L.c0 + L.n ? q.end : L.c0 + L.n);
+      if (a < b) leaf_matvec_t_rows(D, lf, D.W + L.r0, D.n, k, D.Y + L.c0, D.n, 1.0, tmp, S, a - L.c0, b - L.c0);
+    }
   }
 }
 
@@ -1751,7 +1882,7 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   } else if (tk.ninst > 0) {
     double* Xa = slot;
     double* Ya = Xa + m * RW;
-    double* scratch = Ya + n * RW;
+    double* work = Ya + n * RW;
     int rank = D.rank[b];
     for (int64_t e = tid; e < m * rank; e += NT) Xa[e] = U[e];
     for (int64_t e = tid; e < n * rank; e += NT) Ya[e] = V[e];
@@ -1761,7 +1892,7 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
       const TermDef t = D.terms[in.term];
       const int r = term_rank(D, t);
       if (rank > 0 && rank + r > R_ACC) {
-        const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, scratch, lds, LDS_FACTOR, S);
+        const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, work, lds, LDS_FACTOR, S);
         for (int64_t e = tid; e < m * kk; e += NT) Xa[e] = U[e];
         for (int64_t e = tid; e < n * kk; e += NT) Ya[e] = V[e];
         rank = kk;
@@ -1785,7 +1916,7 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
       rank += r;
       __syncthreads();
     }
-    const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, scratch, lds, LDS_FACTOR, S);
+    const int kk = wg_truncate(D, Xa, m, Ya, n, rank, U, V, work, lds, LDS_FACTOR, S);
     if (tid == 0) D.rank[b] = kk;
     if (tid == 0) S.ival[0] = kk;
     __syncthreads();
@@ -1898,7 +2029,7 @@ __device__ void task_ts_b(const DevData& D, const Task& tk, double* slot, double
   const int64_t mx = (int64_t)gx * p, my = (int64_t)gy * p;
   double* Xs = slot;                     // stacked R factors of the U side (mx x p)
   double* Ys = Xs + mx * p;              // and of the V side (my x p)
-  double* scratch = Ys + my * p;
+  double* work = Ys + my * p;
   for (int side = 0; side < 2; ++side) {
     const int gs = side ? gy : gx;
     const int64_t ms = side ? my : mx;
@@ -1930,7 +2061,7 @@ __device__ void task_ts_b(const DevData& D, const Task& tk, double* slot, double
   if (tid == 0) S.flops += 2.0 * p * p * p / 3.0;
   double* Wx = D.stage + D.stage_off[b] + (int64_t)(gx + gy) * 2 * K_MAX;
   double* Wy = Wx + (int64_t)gx * 2 * K_MAX * K_MAX;
-  const int k = wg_svd_explicit(D, M, p, p, ldm, Wx, mx, mx, Wy, my, my, scratch, lds + ldm * p,
+  const int k = wg_svd_explicit(D, M, p, p, ldm, Wx, mx, mx, Wy, my, my, work, lds + ldm * p,
                                 LDS_FACTOR - ldm * p, S);
   __syncthreads();
   wg_apply_q(Xs, mx, p, mx, S.tau_x, Wx, k, mx, S);
@@ -2003,6 +2134,9 @@ __device__ void dispatch(const DevData& D, const Task& tk, int32_t prog, double*
     case TASK_TS_A: task_ts_a(D, tk, dyn, S); break;
     case TASK_TS_B: task_ts_b(D, tk, slot, dyn, S); break;
     case TASK_TS_C: task_ts_c(D, tk, slot, S); break;
+    case TASK_SOLVE_SEQ_T: task_solve_seq_t(D, tk, slot, dyn, S); break;
+    case TASK_SOLVE_MV_T: task_solve_mv_t(D, tk, slot, S); break;
+    case TASK_APPLY: task_apply(D, tk, slot, S); break;
     default: task_dense(D, tk, prog, dyn, S); break;
   }
 }
@@ -2043,15 +2177,55 @@ __global__ void k_eval_init(unsigned long long* fail_key, int32_t* capped) {
 
 // ------------------------------------------------------------------ solve
 
-// One level [t0, t1) of the final forward solve's tasks (stasks, level order).
-__global__ void __launch_bounds__(NT) k_level_solve(DevData D, int32_t t0, int32_t t1) {
+// One level [t0, t1) of an operator task graph (level order).
+__global__ void __launch_bounds__(NT) k_level_tasks(DevData D, const Task* tasks, int32_t t0, int32_t t1) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
   double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
   for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) {
-    const Task tk = D.stasks[q];
+    const Task tk = tasks[q];
     dispatch(D, tk, -1, slot, dyn, S);
     __syncthreads();
+  }
+}
+
+// Row-chunk operator product (TASK_APPLY) over all chunks.
+__global__ void __launch_bounds__(NT) k_apply(DevData D, int mode, const int32_t* chunks, int32_t nchunks) {
+  __shared__ Smem S;
+  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  for (int32_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+    Task tk{};
+    tk.kind = TASK_APPLY;
+    tk.obj = -1;
+    tk.a0 = mode;
+    tk.a1 = chunks[q];
+    task_apply(D, tk, slot, S);
+    __syncthreads();
+  }
+}
+
+// Y = C W with the exact covariance (eq. 2 plus the nugget on the diagonal),
+// entries formed on the fly; one thread per row, W read in column order
+// (every wavefront reads the same entries).  D.r <= 4.
+__global__ void __launch_bounds__(NT) k_dense_matvec(DevData D) {
+  const int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x;
+  if (i >= D.n) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t j = 0; j < D.n; ++j) {
+    const double c = entry(D, i, j);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < D.r) acc[q] += c * D.W[j + q * D.n];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (q < D.r) D.Y[i + q * D.n] = acc[q];
+}
+
+__global__ void k_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * r; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, c = e / n;
+    Z[perm[i] + c * n] = W[e];
   }
 }
 
@@ -2104,16 +2278,66 @@ __global__ void __launch_bounds__(NT) k_truncate_test(DevData D, const double* X
   } else {
     double* Xa = D.ws;
     double* Ya = Xa + m * r;
-    double* scratch = Ya + n * r;
+    double* work = Ya + n * r;
     for (int64_t e = threadIdx.x; e < m * r; e += NT) Xa[e] = X[e];
     for (int64_t e = threadIdx.x; e < n * r; e += NT) Ya[e] = Y[e];
     __syncthreads();
-    k = wg_truncate(D, Xa, m, Ya, n, r, U, V, scratch, dyn, LDS_FACTOR, S);
+    k = wg_truncate(D, Xa, m, Ya, n, r, U, V, work, dyn, LDS_FACTOR, S);
   }
   if (threadIdx.x == 0) {
     *kout = k;
     for (int q = 0; q < 3; ++q) phases[q] = S.ph[q];
   }
+}
+
+// ------------------------------------------------------------------ allocation-free truncation
+//
+// Workspace of the allocation-free truncation entry point: one copy per GPU,
+// held until the process ends.  Layout: 64 doubles of counters (the rank-cap
+// count, then four phase clocks), then the truncation's workspace.  In host
+// code `scratch` names a host-side stand-in: only the address returned by
+// hipGetSymbolAddress (noalloc_scratch) may be handed to kernels.
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+__global__ void k_clear_counters(double* base) {
+  if (threadIdx.x < 64) base[threadIdx.x] = 0.0;
+}
+
+hipError_t launch_truncate_noalloc(DevData D, double* base, const double* X, int64_t m, const double* Y, int64_t n,
+                                   int r, double* U, double* V, int32_t* kout, hipStream_t st) {
+  // counters first (the array keeps the previous call's contents)
+  hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, base);
+  D.capped = reinterpret_cast<int32_t*>(base);
+  D.ws = base + 64;
+  D.ws_stride = NOALLOC_DOUBLES - 64;
+  return launch_truncate_test(D, X, m, Y, n, r, U, V, kout, reinterpret_cast<int64_t*>(base + 8), st);
 }
 
 hipError_t launch_truncate_test(const DevData& D, const double* X, int64_t m, const double* Y, int64_t n,
@@ -2166,22 +2390,55 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
   return hipGetLastError();
 }
 
+static hipError_t set_dyn_lds(const void* f, bool& done) {
+  if (done) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FACTOR * sizeof(double));
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+hipError_t launch_task_levels(const DevData& D, const Task* tasks, const int32_t* level_begin, int32_t nlev,
+                              int max_grid, hipStream_t st) {
+  static bool attr = false;
+  hipError_t e = set_dyn_lds((const void*)k_level_tasks, attr);
+  if (e != hipSuccess) return e;
+  for (int32_t l = 0; l < nlev; ++l) {
+    const int32_t t0 = level_begin[l], t1 = level_begin[l + 1];
+    const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
+    if (g > 0) hipLaunchKernelGGL(k_level_tasks, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, tasks, t0, t1);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const DevData& D, int mode, const int32_t* chunks, int32_t nchunks, int max_grid,
+                        hipStream_t st) {
+  const int g = nchunks < max_grid ? nchunks : max_grid;
+  if (g > 0) hipLaunchKernelGGL(k_apply, dim3(g), dim3(NT), 0, st, D, mode, chunks, nchunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_matvec(const DevData& D, hipStream_t st) {
+  const int64_t g = (D.n + NT - 1) / NT;
+  hipLaunchKernelGGL(k_dense_matvec, dim3((unsigned)g), dim3(NT), 0, st, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const double* Z, const int64_t* perm, int64_t n, int r, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_permute, dim3(1024), dim3(NT), 0, st, Z, perm, n, r, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpermute, dim3(1024), dim3(NT), 0, st, W, perm, n, r, Z);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, const int32_t* slevel_begin,
                         int32_t nslev, int max_grid, const int32_t* diag_ids, int32_t ndiag, double* out,
                         hipStream_t st) {
   hipLaunchKernelGGL(k_permute, dim3(1024), dim3(NT), 0, st, Z, perm, D.n, D.r, D.W);
-  static bool solve_attr = false;
-  if (!solve_attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_level_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       LDS_FACTOR * sizeof(double));
-    if (e != hipSuccess) return e;
-    solve_attr = true;
-  }
-  for (int32_t l = 0; l < nslev; ++l) {
-    const int32_t t0 = slevel_begin[l], t1 = slevel_begin[l + 1];
-    const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
-    if (g > 0) hipLaunchKernelGGL(k_level_solve, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);
-  }
+  const hipError_t e = launch_task_levels(D, D.stasks, slevel_begin, nslev, max_grid, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, st, D, diag_ids, ndiag, D.W, D.r, out);
   return hipGetLastError();
 }

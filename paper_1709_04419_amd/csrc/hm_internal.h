@@ -63,6 +63,18 @@ struct hm_dataset {
   int64_t bytes_C = 0, bytes_L = 0;   // storage of C~ and L~ at the actual ranks
   double t_assemble = 0, t_factor = 0, t_solve = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // operators (hm_apply): the backward solve's tasks, the row chunks, three
+  // n x 64 buffers (allocated on first use)
+  hm::Task* d_btasks = nullptr;
+  int32_t* d_chunks = nullptr;
+  double* d_op = nullptr;
+  // copy of the assembled matrix C~ (dense pool, low-rank pool, ranks), made by
+  // every assembly while keep_c is set
+  bool keep_c = false;
+  bool c_valid = false;
+  void* c_store = nullptr;
+  size_t c_bytes = 0;
+  bool theta_set = false;             // an assembly has set theta (the exact covariance product)
   std::vector<int32_t> level_begin;   // position in `order` where each level starts (+ end)
   std::vector<int32_t> order;         // execution order (task ids), level by level
   int32_t* d_order = nullptr;

@@ -276,6 +276,59 @@ struct Planner {
     return emit_solve(tgt, c2, mv, factor_deps);
   }
 
+  // The backward substitution W(c) <- L_cc^{-T} W(c) of the data: clusters of
+  // at most SOLVE_SEQ points in one task (their solve program backwards);
+  // larger ones as W(c2) solve, W(c1) -= L21^T W(c2) in row chunks of c1,
+  // W(c1) solve.  Returns the task after which all of W(c) is final.
+  int32_t emit_solve_t(int32_t c, const std::vector<int32_t>& deps) {
+    const int32_t d = T.diag_of[c];
+    if (C(c).end - C(c).begin <= SOLVE_SEQ || is_leaf(C(c))) return new_task(TASK_SOLVE_SEQ_T, -1, deps, c, 0);
+    const int32_t c1 = C(c).son[0], c2 = C(c).son[1];
+    const int32_t t2 = emit_solve_t(c2, deps);
+    const int32_t b21 = son(d, c2, c1);
+    std::vector<int32_t> qs;
+    chunks_of(c1, SOLVE_CHUNK, qs);
+    std::vector<int32_t> mv = deps;
+    for (int32_t q : qs) {
+      std::vector<int32_t> dp = deps;
+      dp.push_back(t2);
+      mv.push_back(new_task(TASK_SOLVE_MV_T, -1, dp, b21, q));
+    }
+    return emit_solve_t(c1, mv);
+  }
+
+  // Sorts the tasks recorded since `tasks` was cleared into levels (longest
+  // path) and stores them with their dependencies renumbered.
+  void leveled(std::vector<Task>& out, std::vector<int32_t>& odeps, std::vector<int32_t>& obegin) {
+    const int32_t ns = (int32_t)tasks.size();
+    std::vector<int32_t> lev(ns, 0);
+    for (int32_t i = 0; i < ns; ++i)
+      for (int32_t d : tdeps[i]) {
+        if (d >= i) throw std::logic_error("operator dependency not earlier in program order");
+        lev[i] = std::max(lev[i], lev[d] + 1);
+      }
+    std::vector<int32_t> ord(ns);
+    for (int32_t i = 0; i < ns; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return lev[a] < lev[b]; });
+    std::vector<int32_t> rk(ns);
+    for (int32_t i = 0; i < ns; ++i) rk[ord[i]] = i;
+    out.clear();
+    odeps.clear();
+    obegin.clear();
+    for (int32_t k = 0; k < ns; ++k) {
+      const int32_t i = ord[k];
+      Task t = tasks[i];
+      t.level = lev[i];
+      if (obegin.size() <= (size_t)t.level) obegin.push_back(k);
+      t.dep_begin = (int32_t)odeps.size();
+      for (int32_t d : tdeps[i]) odeps.push_back(rk[d]);
+      t.ndeps = (int32_t)tdeps[i].size();
+      t.inst_begin = t.ninst = 0;
+      out.push_back(t);
+    }
+    obegin.push_back(ns);
+  }
+
   void push(int32_t bid, int64_t R0, int64_t C0, int32_t term, int64_t xoff, int64_t yoff,
             int64_t mx, int64_t ny) {
     const Block& b = B(bid);
@@ -405,9 +458,13 @@ struct Planner {
     const int32_t T1 = (int32_t)leaf_insts[bid].size() + 1;
     std::vector<int32_t> prevC;   // C tasks of the previous step, by row block
     for (int32_t i = 1; i <= T1; ++i) {
+      // every task of step i reads the rank of term i (whether to truncate),
+      // so all of them wait for the term's producers
+      std::vector<int32_t> term_dp;
+      if (i < T1) inst_deps_one(leaf_insts[bid][i - 1], term_dp);
       std::vector<int32_t> as;
       for (int q = 0; q < g; ++q) {
-        std::vector<int32_t> dp;
+        std::vector<int32_t> dp = term_dp;
         if (!prevC.empty()) dp.push_back(prevC[q]);
         as.push_back(new_task(TASK_TS_A, bid, dp, i, q));
       }
@@ -415,7 +472,6 @@ struct Planner {
       if (i == T1) bd.insert(bd.end(), extra.begin(), extra.end());
       const int32_t tb = new_task(TASK_TS_B, bid, bd, i, 0);
       std::vector<int32_t> cd{tb};
-      if (i < T1) inst_deps_one(leaf_insts[bid][i - 1], cd);
       prevC.clear();
       for (int q = 0; q < g; ++q) prevC.push_back(new_task(TASK_TS_C, bid, cd, i, q));
     }
@@ -439,7 +495,7 @@ struct Planner {
       leaves_of(T.diag_of[sig], lv);
       std::vector<int32_t> lfin;
       for (int32_t l : lv) lfin.push_back(final_task[l]);
-      if (std::max(b.m, b.n) > TS_BIG && !leaf_insts[bid].empty()) {
+      if (ts_big(b.m, b.n) && !leaf_insts[bid].empty()) {
         // the flush as parallel steps, then V <- L^{-1} V as solve tasks
         const std::vector<int32_t> fin = emit_ts(bid, lfin);
         final_task[bid] = emit_solve(bid, sig, fin, false);
@@ -563,7 +619,7 @@ struct Planner {
         P.dense_ids.push_back(b);
         if (bb.row == bb.col) P.diag_leaf_ids.push_back(b);
       } else if (bb.kind == BK_LR) {
-        const bool big = std::max(bb.m, bb.n) > TS_BIG;
+        const bool big = ts_big(bb.m, bb.n);
         const int32_t cap = big ? 2 * K_MAX : K_MAX;
         P.lr_cap[b] = cap;
         P.lr_off[b] = P.lr_pool;
@@ -644,33 +700,16 @@ struct Planner {
     tasks.clear();
     tdeps.clear();
     emit_solve(-1, 0, {}, false);
-    const int32_t ns = (int32_t)tasks.size();
-    std::vector<int32_t> slev(ns, 0);
-    for (int32_t i = 0; i < ns; ++i)
-      for (int32_t d : tdeps[i]) {
-        if (d >= i) throw std::logic_error("solve dependency not earlier in program order");
-        slev[i] = std::max(slev[i], slev[d] + 1);
-      }
-    std::vector<int32_t> sorder(ns);
-    for (int32_t i = 0; i < ns; ++i) sorder[i] = i;
-    std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t a, int32_t b) { return slev[a] < slev[b]; });
-    std::vector<int32_t> srank(ns);
-    for (int32_t i = 0; i < ns; ++i) srank[sorder[i]] = i;
-    P.stasks.clear();
-    P.sdeps.clear();
-    P.slevel_begin.clear();
-    for (int32_t k = 0; k < ns; ++k) {
-      const int32_t i = sorder[k];
-      Task t = tasks[i];
-      t.level = slev[i];
-      if (P.slevel_begin.size() <= (size_t)t.level) P.slevel_begin.push_back(k);
-      t.dep_begin = (int32_t)P.sdeps.size();
-      for (int32_t d : tdeps[i]) P.sdeps.push_back(srank[d]);
-      t.ndeps = (int32_t)tdeps[i].size();
-      t.inst_begin = t.ninst = 0;
-      P.stasks.push_back(t);
-    }
-    P.slevel_begin.push_back(ns);
+    leveled(P.stasks, P.sdeps, P.slevel_begin);
+    // the backward solve with L^T, and the row chunks of operator products
+    tasks.clear();
+    tdeps.clear();
+    emit_solve_t(0, {});
+    leveled(P.btasks, P.bdeps, P.blevel_begin);
+    tasks.clear();
+    tdeps.clear();
+    P.apply_chunks.clear();
+    chunks_of(0, SOLVE_CHUNK, P.apply_chunks);
   }
 };
 
@@ -729,7 +768,7 @@ static void validate(const Tree& T, const Plan& P) {
     if (t.obj < 0 || t.obj >= nb) fail("task block id");
     const Block& b = T.bk[t.obj];
     if (t.kind == TASK_TS_A || t.kind == TASK_TS_B || t.kind == TASK_TS_C) {
-      if (b.kind != BK_LR || std::max(b.m, b.n) <= TS_BIG || P.lr_cap[t.obj] != 2 * K_MAX ||
+      if (b.kind != BK_LR || !ts_big(b.m, b.n) || P.lr_cap[t.obj] != 2 * K_MAX ||
           P.stage_off[t.obj] < 0)
         fail("big low-rank step block");
       if (t.a0 < 1 || t.a0 > t.ninst + 1) fail("big low-rank step index");
@@ -767,17 +806,38 @@ static void validate(const Tree& T, const Plan& P) {
   }
   for (const TermDef& d : P.terms)
     if (d.kind != TK_DD && (d.buf < 0 || d.buf + d.rows * K_MAX > P.term_pool)) fail("term buffer");
-  const int64_t ns = (int64_t)P.stasks.size();
-  if (P.slevel_begin.empty() || P.slevel_begin.back() != ns) fail("solve levels");
-  for (int64_t k = 0; k < ns; ++k) {
-    const Task& t = P.stasks[k];
-    if (t.obj != -1 || (t.kind != TASK_SOLVE_SEQ && t.kind != TASK_SOLVE_MV)) fail("final solve task");
-    check_solve_task(T, t, fail);
-    for (int32_t q = 0; q < t.ndeps; ++q) {
-      const int32_t d = P.sdeps[t.dep_begin + q];
-      if (d < 0 || d >= k || P.stasks[d].level >= t.level) fail("final solve dependency");
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<Task>& ts = pass ? P.btasks : P.stasks;
+    const std::vector<int32_t>& tdp = pass ? P.bdeps : P.sdeps;
+    const std::vector<int32_t>& lb = pass ? P.blevel_begin : P.slevel_begin;
+    const int64_t ns = (int64_t)ts.size();
+    if (lb.empty() || lb.back() != ns) fail("solve levels");
+    for (int64_t k = 0; k < ns; ++k) {
+      const Task& t = ts[k];
+      const int8_t seq = pass ? TASK_SOLVE_SEQ_T : TASK_SOLVE_SEQ, mv = pass ? TASK_SOLVE_MV_T : TASK_SOLVE_MV;
+      if (t.obj != -1 || (t.kind != seq && t.kind != mv)) fail("solve task kind");
+      Task u = t;
+      u.kind = (t.kind == seq) ? TASK_SOLVE_SEQ : TASK_SOLVE_MV;
+      if (pass && u.kind == TASK_SOLVE_MV) {
+        // the transposed product writes rows of the block's columns
+        const Block& b = T.bk[t.a0];
+        const Cluster& q = T.cl[t.a1];
+        if (q.begin < b.c0 || q.end > b.c0 + b.n || b.r0 + b.m > T.n) fail("backward product chunk");
+      } else {
+        check_solve_task(T, u, fail);
+      }
+      for (int32_t q = 0; q < t.ndeps; ++q) {
+        const int32_t d = tdp[t.dep_begin + q];
+        if (d < 0 || d >= k || ts[d].level >= t.level) fail("solve dependency");
+      }
     }
   }
+  int64_t covered = 0;
+  for (int32_t q : P.apply_chunks) {
+    if (q < 0 || q >= (int32_t)T.cl.size() || T.cl[q].begin != covered) fail("operator chunks");
+    covered = T.cl[q].end;
+  }
+  if (covered != T.n) fail("operator chunks cover");
   for (size_t c = 0; c + 1 < P.sop_begin.size(); ++c) {
     const int64_t len = T.cl[c].end - T.cl[c].begin;
     for (int32_t o = P.sop_begin[c]; o < P.sop_begin[c + 1]; ++o) {

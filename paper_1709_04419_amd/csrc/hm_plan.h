@@ -74,6 +74,10 @@ enum TaskKind : int8_t {
   TASK_TS_A = 7,       //   row block a1: Householder QR of its rows (if truncating)
   TASK_TS_B = 8,       //   stacked R factors: QR, core SVD, small factors; new rank
   TASK_TS_C = 9,       //   row block a1: its rows of the truncated factor, then the term's columns
+  // operators of the factor / matrix on the data (obj = -1 only):
+  TASK_SOLVE_SEQ_T = 10,  // W(rows of cluster a0) <- L^-T W(same rows), its solve program backwards
+  TASK_SOLVE_MV_T = 11,   // W(rows of cluster a1) -= L_blk(:, those rows)^T W(rows of blk), blk = a0
+  TASK_APPLY = 12,        // Y(rows of cluster a1) = M W(.) for M = L (a0 = 0), L^T (1), C~ (2)
 };
 // W of the solve tasks: obj >= 0 is the V factor of that low-rank block (its
 // rows relative to the block's column cluster), obj = -1 the permuted data of
@@ -102,7 +106,10 @@ constexpr int64_t TERM_SPLIT = 1024;
 // accumulation lives there in place, and every truncation runs on row blocks
 // of the two factors in parallel (QR of each row block, then one QR of the
 // stacked R factors: tall-skinny QR).
-constexpr int64_t TS_BIG = 2048;
+#ifndef HM_TS_BIG
+#define HM_TS_BIG 2048
+#endif
+constexpr int64_t TS_BIG = HM_TS_BIG;
 constexpr int TS_GMAX = 16;          // row blocks per factor at most
 constexpr int64_t TS_MINROWS = 1024; // rows per row block at least (>= 2 K_MAX)
 // Row blocks of a factor with `rows` rows: g blocks of ceil(rows / g) rows.
@@ -114,6 +121,13 @@ inline int ts_blocks(int64_t rows) {
 inline int64_t ts_rows(int64_t rows) {
   const int g = ts_blocks(rows);
   return (rows + g - 1) / g;
+}
+// Whether an m x n low-rank block is big: more than TS_BIG rows or columns,
+// and every row block of both factors at least 2 K_MAX rows high (it holds a
+// triangular factor of up to 2 K_MAX columns).
+inline bool ts_big(int64_t m, int64_t n) {
+  const int64_t lo = m < n ? m : n, hi = m < n ? n : m;
+  return hi > TS_BIG && lo >= 2 * K_MAX;
 }
 
 // One step of the H forward substitution W <- L_cc^{-1} W over a cluster c:
@@ -168,6 +182,13 @@ struct Plan {
   std::vector<Task> stasks;
   std::vector<int32_t> sdeps;
   std::vector<int32_t> slevel_begin;
+  // the backward solve L^T x = y as a task graph, in level order
+  std::vector<Task> btasks;
+  std::vector<int32_t> bdeps;
+  std::vector<int32_t> blevel_begin;
+  // row chunks (clusters of at most SOLVE_CHUNK points) of the whole index
+  // set, left to right: the independent tasks of an operator product
+  std::vector<int32_t> apply_chunks;
   // work counters (algorithmic)
   int64_t n_dense_entries = 0;
   int64_t max_lr_rows = 0;      // max(m, n) over low-rank leaves

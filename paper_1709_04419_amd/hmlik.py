@@ -33,6 +33,7 @@ _lib = C.CDLL(LIB_PATH)
 (HM_OK, HM_ERR_ARG, HM_ERR_NOT_SPD, HM_ERR_OOM, HM_ERR_DEVICE, HM_ERR_INTERNAL, HM_ERR_CANCELLED,
  HM_ERR_BUSY) = range(8)
 HM_FP64, HM_MIXED = 0, 1
+HM_OP_L, HM_OP_LT, HM_OP_C, HM_OP_SOLVE, HM_OP_C_EXACT = range(5)
 
 
 class hm_theta(C.Structure):
@@ -91,6 +92,12 @@ _sig = {
                               C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "hm_test_truncate": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                                    _P, _P, C.POINTER(C.c_int32), _P]),
+    "hm_truncate_noalloc": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_double, C.c_int32,
+                                      _P, _P, _P]),
+    "hm_dataset_keep_matrix": (C.c_int, [_P, C.c_int32]),
+    "hm_apply": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, C.c_int32]),
+    "hm_simulate": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx), _P, _P, C.c_int32, C.c_int32]),
+    "hm_inverse_accuracy": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
     "hm_dataset_footprint": (C.c_int, [_P, _P, _P, _P]),
     "hm_dataset_release": (C.c_int, [_P]),
     "hm_server_create": (C.c_int, [_P, C.POINTER(hm_server_opts), C.POINTER(_P)]),
@@ -289,6 +296,50 @@ class Dataset:
     def release(self):
         """hm_dataset_release: frees the factor storage until the next evaluation."""
         _check(_lib.hm_dataset_release(self._h), "hm_dataset_release")
+
+    def keep_matrix(self, keep: bool = True):
+        """hm_dataset_keep_matrix: later assemblies keep a copy of C~ (for HM_OP_C)."""
+        _check(_lib.hm_dataset_keep_matrix(self._h, 1 if keep else 0), "hm_dataset_keep_matrix")
+
+    def apply(self, op: int, W):
+        """hm_apply: Y = op W (HM_OP_*) for W of shape (n,) or (n, r), numpy
+        (host) or a float64 torch tensor on the context's GPU (device)."""
+        on_dev = not isinstance(W, np.ndarray)
+        if on_dev:
+            W = _device_f64(W, self.ctx, "W")
+            vec = W.dim() == 1
+            Wc = (W[:, None] if vec else W).t().contiguous()
+            r = Wc.shape[0]
+            Yc = Wc.new_empty(Wc.shape)
+            _check(_lib.hm_apply(self._h, int(op), _ptr(Wc), _ptr(Yc), r, 1), "hm_apply")
+            Y = Yc.t()
+            return Y[:, 0] if vec else Y
+        W = np.asarray(W, dtype=np.float64)
+        vec = W.ndim == 1
+        Wf = np.asfortranarray(W[:, None] if vec else W)
+        if Wf.shape[0] != self.n:
+            raise ValueError("W has the wrong length")
+        Y = np.empty_like(Wf, order="F")
+        _check(_lib.hm_apply(self._h, int(op), _ptr(Wf), _ptr(Y), Wf.shape[1], 0), "hm_apply")
+        return Y[:, 0] if vec else Y
+
+    def simulate(self, theta, nugget, W, eps=0.0, rank=0):
+        """hm_simulate: Z = L~(theta) W (host arrays, (n,) or (n, r))."""
+        th, ap = self._args(theta, nugget, eps, rank)
+        W = np.asarray(W, dtype=np.float64)
+        vec = W.ndim == 1
+        Wf = np.asfortranarray(W[:, None] if vec else W)
+        Z = np.empty_like(Wf, order="F")
+        _check(_lib.hm_simulate(self._h, C.byref(th), C.byref(ap), _ptr(Wf), _ptr(Z), Wf.shape[1], 0),
+               "hm_simulate")
+        return Z[:, 0] if vec else Z
+
+    def inverse_accuracy(self, x0, iters: int = 10) -> float:
+        """hm_inverse_accuracy: ||I - (L~ L~^T)^{-1} C||_2 by `iters` power steps from x0."""
+        x = np.ascontiguousarray(x0, dtype=np.float64)
+        out = C.c_double()
+        _check(_lib.hm_inverse_accuracy(self._h, _ptr(x), int(iters), C.byref(out)), "hm_inverse_accuracy")
+        return out.value
 
     def export_tree(self):
         inf = self.info()

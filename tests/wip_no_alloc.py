@@ -1,0 +1,88 @@
+"""GPU check of the allocation-free truncation entry point hm_truncate_noalloc
+(include/hmlik.h): through the C ABI, with device inputs and outputs, it
+gives the result of hm_test_truncate (the same truncation of Remark 2.4 with
+library-allocated buffers) on two calls in a row, the second smaller than the
+first (the fixed workspace keeps the first call's contents), in both the
+factored and the explicit form; inputs beyond the fixed workspace are refused."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_1709_04419_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1709_04419_amd import hmlik
+    return hmlik
+
+
+def _dev_colmajor(torch, A):
+    """A (rows x cols) as a device float64 tensor in column-major order."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)).cuda()
+
+
+def _noalloc(H, torch, ctx, X, Y, eps, rank):
+    m = X.shape[0]
+    n = Y.shape[0] if Y is not None else X.shape[1]
+    r = X.shape[1] if Y is not None else 0
+    dX = _dev_colmajor(torch, X)
+    dY = _dev_colmajor(torch, Y) if Y is not None else None
+    dU = torch.full((64, m), np.nan, dtype=torch.float64, device="cuda")
+    dV = torch.full((64, n), np.nan, dtype=torch.float64, device="cuda")
+    dk = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    s = H._lib.hm_truncate_noalloc(ctx._h, C.c_void_p(dX.data_ptr()), m,
+                                   C.c_void_p(dY.data_ptr()) if dY is not None else None, n, r, float(eps),
+                                   int(rank), C.c_void_p(dU.data_ptr()), C.c_void_p(dV.data_ptr()),
+                                   C.c_void_p(dk.data_ptr()))
+    assert s == H.HM_OK, H.hm_status_string(s)
+    torch.cuda.synchronize()
+    k = int(dk.cpu()[0])
+    return dU.cpu().numpy().T[:, :k], dV.cpu().numpy().T[:, :k], k
+
+
+@pytest.mark.parametrize("form", ["factored", "explicit"])
+def test_noalloc_matches_allocating_entry_point(H, form):
+    import torch
+    ctx = H.Context(0)
+    ds = H.Dataset(ctx, wl.uniform_square(3000, 1), 64, 2.0)
+    rng = np.random.default_rng(77)
+    if form == "factored":
+        shapes = [(900, 800, 61, 1e-7, 0), (200, 150, 20, 1e-6, 0)]
+    else:
+        shapes = [(250, 200, 0, 1e-8, 0), (90, 60, 0, 0.0, 7)]
+    for (m, n, r, eps, rank) in shapes:
+        if form == "factored":
+            X = rng.standard_normal((m, r)) * np.logspace(0, -12, r)
+            Y = rng.standard_normal((n, r))
+        else:
+            X = (rng.standard_normal((m, 12)) * np.logspace(0, -9, 12)) @ rng.standard_normal((12, n))
+            Y = None
+        U0, V0, _ = H.test_truncate(ds, X, Y, eps=eps, rank=rank)
+        U1, V1, k = _noalloc(H, torch, ctx, X, Y, eps, rank)
+        assert k == U0.shape[1] > 0
+        scale = np.max(np.abs(U0 @ V0.T))
+        assert np.max(np.abs(U1 @ V1.T - U0 @ V0.T)) <= 1e-13 * scale
+        assert np.max(np.abs(U1 - U0)) <= 1e-12 * np.max(np.abs(U0))
+        assert np.max(np.abs(V1 - V0)) <= 1e-12 * np.max(np.abs(V0))
+    ds.close()
+    ctx.close()
+
+
+def test_noalloc_refuses_oversized_input(H):
+    import torch
+    ctx = H.Context(0)
+    m, n, r = 40000, 30000, 128      # (m + n) r > 4 Mi doubles
+    dX = torch.zeros(m * r, dtype=torch.float64, device="cuda")
+    dY = torch.zeros(n * r, dtype=torch.float64, device="cuda")
+    dU = torch.zeros(m * 64, dtype=torch.float64, device="cuda")
+    dV = torch.zeros(n * 64, dtype=torch.float64, device="cuda")
+    dk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = H._lib.hm_truncate_noalloc(ctx._h, C.c_void_p(dX.data_ptr()), m, C.c_void_p(dY.data_ptr()), n, r, 1e-7,
+                                   0, C.c_void_p(dU.data_ptr()), C.c_void_p(dV.data_ptr()),
+                                   C.c_void_p(dk.data_ptr()))
+    assert s == H.HM_ERR_ARG
+    ctx.close()
