@@ -129,6 +129,22 @@ print(json.dumps(out))
                       f"({t2:.2f} s); value at n={n_full} extrapolated by the measured growth t ~ n^{alpha:.2f}"}
 
 
+def oracle_error(n: int, eps: float, r) -> dict | None:
+    """Relative differences to the oracle's FP64 values for this workload,
+    stored by tests/golden/make_fullsize.py (None when there are none)."""
+    path = os.path.join(ROOT, "tests", "golden", "fullsize.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(f"basin{n // 1000}k_eps" + f"{eps:g}".replace("e-0", "e-"))
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("n") != n or rec.get("points_seed") != 31 or rec.get("status") != "ok":
+        return None
+    out = {k: abs(float(r[k][0]) - rec[k]) / abs(rec[k]) for k in ("loglik", "logdet", "quadform")}
+    out["source"] = "oracle (tests/golden/fullsize.json)"
+    return out
+
+
 def traffic_per_launch(n: int):
     """HBM bytes per k_level launch from the committed counter summary, or None
     when there is none for this workload or the kernel source has changed."""
@@ -157,6 +173,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
     ap.add_argument("--form", choices=("plain", "served", "batched", "stream"), default="plain")
+    ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64",
+                    help="plain form: FP64, or the mixed-precision form with refinement of C~^-1 Z")
+    ap.add_argument("--refine-max-iter", type=int, default=10)
+    ap.add_argument("--refine-tol", type=float, default=1e-12)
     ap.add_argument("--rate", type=float, default=0.25)
     ap.add_argument("--budget-gib", type=float, default=96.0)
     ap.add_argument("--replicates", type=int, default=16)
@@ -185,6 +205,8 @@ def main():
     from paper_1709_04419_amd import workloads as wl
 
     n, eps = args.n, args.eps
+    mixed = args.prec == "mixed"
+    pk = dict(prec=hmlik.HM_MIXED, refine_max_iter=args.refine_max_iter, refine_tol=args.refine_tol) if mixed else {}
     P = wl.basin_clusters(n, 31)
     Z = wl.standard_normal(n, 1, 32)
     ctx = hmlik.Context(0)
@@ -207,7 +229,7 @@ def main():
         log(f"warm-up: schedule tuned from one timed evaluation, {t_tune:.2f} s")
     elif warm:
         s = time.perf_counter()
-        ds.loglik(THETA, NUGGET, eps, 0)
+        ds.loglik(THETA, NUGGET, eps, 0, **pk)
         log(f"warm-up evaluation: {time.perf_counter() - s:.2f} s")
     torch.cuda.synchronize()
     # timed steps: up to --steps, within the wall budget (at least one)
@@ -220,7 +242,7 @@ def main():
             log(f"wall budget reached after {k} of {args.steps} steps")
             break
         s = time.perf_counter()
-        r = ds.loglik(THETA, NUGGET, eps, 0)
+        r = ds.loglik(THETA, NUGGET, eps, 0, **pk)
         lat.append(time.perf_counter() - s)
         fac.append(r["t_factor"][0])
         asm.append(r["t_assemble"][0])
@@ -259,12 +281,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": "basin256k" if n == 256000 else f"basin{n}", "n": n,
                    "points": "basin_clusters(seed 31): 80% uniform in a non-convex basin, 20% in 10 clusters",
                    "theta": {"sigma2": THETA[0], "ell": THETA[1], "nu": THETA[2]}, "nugget": NUGGET,
-                   "eps": eps, "leaf_size": LEAF, "eta": ETA, "precision": "fp64",
+                   "eps": eps, "leaf_size": LEAF, "eta": ETA,
+                   "precision": (f"mixed: FP32 low-rank factors and update products, FP64 leaves/log-det/"
+                                 f"recompression, refinement of C~^-1 Z (at most {args.refine_max_iter} steps, "
+                                 f"tol {args.refine_tol:g})") if mixed else "fp64",
                    "blocks": info["nblocks"], "tasks": info["ntasks"], "levels": launches,
                    "schedule": "longest-path levels" if args.no_tune else
                                "levels re-balanced from one timed evaluation (untimed, before the steps)"},
@@ -273,6 +298,12 @@ def main():
                       "solve": float(np.mean(sol)) * 1e3, "dataset_setup_host": t_setup * 1e3,
                       "schedule_tuning": t_tune * 1e3},
         "loglik": float(r["loglik"][0]),
+        "logdet": float(r["logdet"][0]),
+        "quadform": float(r["quadform"][0]),
+        "refine": ({"quad": float(r["refine_quad"][0]), "resid": float(r["refine_resid"][0]),
+                    "iters": int(r["refine_iters"][0])} if mixed else None),
+        "bytes_C": int(r["bytes_C"][0]), "bytes_L": int(r["bytes_L"][0]), "max_rank": int(r["max_rank"][0]),
+        "vs_oracle": oracle_error(n, eps, r),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_per_launch(n),
                      "kernel": "k_level (H-Cholesky task executor, one launch per dependency level)",

@@ -410,7 +410,7 @@ void hm_dataset_destroy(hm_dataset* ds) {
   (void)hipSetDevice(ds->ctx->device);
   (void)hipStreamSynchronize(ds->ctx->stream);
   for (auto& b : ds->bufs) (void)hipFree(b.p);
-  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out, (void*)ds->d_op, ds->c_store})
+  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out, (void*)ds->d_op, (void*)ds->d_part, ds->c_store})
     if (q) (void)hipFree(q);
   if (ds->store) (void)hipFree(ds->store);
   for (int i = 0; i < 4; ++i)
@@ -498,6 +498,19 @@ hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t o
 
 namespace hm_int {
 
+hm_status alloc_matrix_copy(hm_dataset* ds) {
+  const Plan& P = ds->plan;
+  const size_t b = sizeof(double) * ((size_t)P.dense_pool + (size_t)P.lr_pool) +
+                   sizeof(int32_t) * ds->tree.bk.size() + 256;
+  if (hipMalloc(&ds->c_store, b) != hipSuccess) {
+    (void)hipGetLastError();
+    ds->c_store = nullptr;
+    return HM_ERR_OOM;
+  }
+  ds->c_bytes = b;
+  return HM_OK;
+}
+
 hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
   if (!th || !ap) return HM_ERR_ARG;
   if (!finite_pos(th->sigma2) || !finite_pos(th->ell) || !finite_pos(th->nu)) return HM_ERR_ARG;
@@ -506,11 +519,13 @@ hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap) {
   if (ap->fixed_rank == 0 && !finite_pos(ap->eps)) return HM_ERR_ARG;
   if (ap->fixed_rank > 0 && !(std::isfinite(ap->eps) && ap->eps >= 0.0)) return HM_ERR_ARG;
   if (th->nu > 50.0) return HM_ERR_ARG;
-  if (ap->refine_max_iter < 0 || !std::isfinite(ap->refine_tol) || ap->refine_tol < 0.0) return HM_ERR_ARG;
+  if (ap->refine_max_iter < 0 || ap->refine_max_iter > 100 || !std::isfinite(ap->refine_tol) ||
+      ap->refine_tol < 0.0)
+    return HM_ERR_ARG;
   if (ap->prec == HM_FP64) {
     if (ap->refine_max_iter != 0 || ap->refine_tol != 0.0) return HM_ERR_ARG;
-  } else {
-    return HM_ERR_ARG;   // HM_MIXED is not available in this build
+  } else if (ap->prec != HM_MIXED) {
+    return HM_ERR_ARG;
   }
   return HM_OK;
 }
@@ -535,6 +550,12 @@ hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* a
   D.kfix = ap->fixed_rank;
   D.eps = (ap->fixed_rank > 0) ? 0.0 : ap->eps;
   D.kmax = (ap->fixed_rank > 0) ? ap->fixed_rank : K_MAX;
+  D.mixed = ap->prec == HM_MIXED ? 1 : 0;
+  ds->prec = ap->prec;
+  ds->refine_max_iter = ap->refine_max_iter;
+  ds->refine_tol = ap->refine_tol;
+  // the mixed form refines C~^{-1} Z with the assembled matrix: keep a copy
+  if (D.mixed && !ds->c_store) TRY(alloc_matrix_copy(ds));
   DevData Dl = D;
   if (ws) Dl.ws = ws;
   HIPTRY(hipEventRecord(ds->ev[0], st));
@@ -543,7 +564,7 @@ hm_status assemble_launch(hm_dataset* ds, const hm_theta* th, const hm_approx* a
   HIPTRY(launch_aca(Dl, ws ? grid : NSLOTS, st));
   ds->theta_set = true;
   ds->c_valid = false;
-  if (ds->keep_c && ds->c_store) {
+  if ((ds->keep_c || D.mixed) && ds->c_store) {
     const Plan& P = ds->plan;
     char* q = static_cast<char*>(ds->c_store);
     const size_t bd = sizeof(double) * (size_t)P.dense_pool, bl = sizeof(double) * (size_t)P.lr_pool;
@@ -597,8 +618,16 @@ void fill_results(const hm_dataset* ds, const double* res, int32_t max_rank, hm_
     if (ds->factor_status == HM_OK) {
       o.logdet = res[0];
       o.quadform = res[1 + c];
-      o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.quadform;
-      o.refine_quad = o.quadform;
+      if (ds->prec == HM_MIXED && (size_t)c < ds->ref_quad.size()) {
+        // eq. (4) with the refined quadratic form Z^T C~^{-1} Z
+        o.refine_quad = ds->ref_quad[c];
+        o.refine_resid = ds->ref_resid[c];
+        o.refine_iters = ds->ref_iters;
+        o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.refine_quad;
+      } else {
+        o.refine_quad = o.quadform;
+        o.loglik = c0 - 0.5 * o.logdet - 0.5 * o.quadform;
+      }
     } else {
       o.logdet = o.quadform = o.loglik = o.refine_quad = NAN;
     }
@@ -687,6 +716,91 @@ hm_status hm_factor(hm_dataset* ds) {
   return finish_factor(ds);
 }
 
+// Iterative refinement of x = C~^{-1} Z (mixed form): x_0 = (L~ L~^T)^{-1} Z,
+// then x += (L~ L~^T)^{-1} (Z - C~ x) with C~ the assembled matrix (FP64
+// products), until the relative residual ||Z - C~ x|| / ||Z|| of every column
+// is at most refine_tol or refine_max_iter corrections were applied.  Fills
+// ds->ref_quad (Z^T x), ds->ref_resid and ds->ref_iters.  Tree order
+// throughout; buffers: the operator buffers and the data's solve buffer.
+static hm_status refine(hm_dataset* ds) {
+  const int64_t n = ds->tree.n;
+  const int r = ds->r;
+  hipStream_t st = ds->ctx->stream;
+  constexpr int G = 256;   // work-groups of the vector steps (partial sums)
+  if (!ds->d_op && hipMalloc((void**)&ds->d_op, sizeof(double) * 3 * n * 64) != hipSuccess) {
+    (void)hipGetLastError();
+    ds->d_op = nullptr;
+    return HM_ERR_OOM;
+  }
+  if (!ds->d_part && hipMalloc((void**)&ds->d_part, sizeof(double) * G * 2 * 64) != hipSuccess) {
+    (void)hipGetLastError();
+    ds->d_part = nullptr;
+    return HM_ERR_OOM;
+  }
+  if (!ds->c_valid) return HM_ERR_ARG;
+  double* Zt = ds->d_op;
+  double* X = Zt + n * 64;
+  double* Y = X + n * 64;
+  double* R = ds->d_W;
+  use_ctx_ws(ds);
+  DevData D = ds->D;
+  D.r = r;
+  DevData Dc = D;   // the kept assembled matrix
+  {
+    const Plan& P = ds->plan;
+    char* q = static_cast<char*>(ds->c_store);
+    Dc.dense = (double*)q;
+    Dc.lr = (double*)(q + sizeof(double) * (size_t)P.dense_pool);
+    Dc.rank = (int32_t*)(q + sizeof(double) * ((size_t)P.dense_pool + (size_t)P.lr_pool));
+  }
+  const Plan& P = ds->plan;
+  auto solve_in_place = [&](double* W) -> hm_status {
+    DevData Ds = D;
+    Ds.W = W;
+    HIPTRY(launch_task_levels(Ds, Ds.stasks, P.slevel_begin.data(), (int32_t)P.slevel_begin.size() - 1, NSLOTS, st));
+    HIPTRY(launch_task_levels(Ds, ds->d_btasks, P.blevel_begin.data(), (int32_t)P.blevel_begin.size() - 1, NSLOTS,
+                              st));
+    return HM_OK;
+  };
+  std::vector<double> part(G * 2 * 64);
+  HIPTRY(launch_permute(ds->d_Z, ds->d_perm, n, r, Zt, st));
+  HIPTRY(hipMemcpyAsync(X, Zt, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
+  TRY(solve_in_place(X));
+  ds->ref_resid.assign(r, 0.0);
+  int it = 0;
+  for (;; ++it) {
+    DevData Da = Dc;
+    Da.W = X;
+    Da.Y = Y;
+    HIPTRY(launch_apply(Da, 2, ds->d_chunks, (int32_t)P.apply_chunks.size(), NSLOTS, st));
+    HIPTRY(launch_refine_resid(Zt, Y, R, n, r, ds->d_part, G, st));
+    HIPTRY(hipMemcpyAsync(part.data(), ds->d_part, sizeof(double) * G * 2 * r, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    double worst = 0.0;
+    for (int c = 0; c < r; ++c) {
+      double sr = 0.0, sz = 0.0;
+      for (int g = 0; g < G; ++g) {
+        sr += part[g * 2 * r + c];
+        sz += part[g * 2 * r + r + c];
+      }
+      ds->ref_resid[c] = sz > 0.0 ? std::sqrt(sr / sz) : 0.0;
+      worst = std::max(worst, ds->ref_resid[c]);
+    }
+    if (worst <= ds->refine_tol || it >= ds->refine_max_iter) break;
+    TRY(solve_in_place(R));
+    HIPTRY(launch_refine_update(X, R, Zt, n, r, ds->d_part, G, st));
+  }
+  ds->ref_iters = it;
+  // Z^T x of the final x
+  HIPTRY(launch_refine_update(X, nullptr, Zt, n, r, ds->d_part, G, st));
+  HIPTRY(hipMemcpyAsync(part.data(), ds->d_part, sizeof(double) * G * 2 * r, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  ds->ref_quad.assign(r, 0.0);
+  for (int c = 0; c < r; ++c)
+    for (int g = 0; g < G; ++g) ds->ref_quad[c] += part[g * 2 * r + c];
+  return HM_OK;
+}
+
 hm_status hm_solve(hm_dataset* ds, hm_result* out) {
   if (!ds || !out || !ds->factored || ds->r < 1) return HM_ERR_ARG;
   if (busy(ds->ctx)) return HM_ERR_BUSY;
@@ -716,6 +830,16 @@ hm_status hm_solve(hm_dataset* ds, hm_result* out) {
     HIPTRY(hipEventElapsedTime(&ms, ds->ev[2], ds->ev[3]));
     ds->t_solve = ms * 1e-3;
     HIPTRY(hipMemcpy(res.data(), ds->d_out, sizeof(double) * (1 + r), hipMemcpyDeviceToHost));
+    ds->ref_quad.clear();
+    if (ds->prec == HM_MIXED) {
+      HIPTRY(hipEventRecord(ds->ev[2], st));
+      TRY(refine(ds));
+      HIPTRY(hipEventRecord(ds->ev[3], st));
+      HIPTRY(hipEventSynchronize(ds->ev[3]));
+      float ms2 = 0;
+      HIPTRY(hipEventElapsedTime(&ms2, ds->ev[2], ds->ev[3]));
+      ds->t_solve += ms2 * 1e-3;
+    }
   }
   fill_results(ds, res.data(), max_rank, out);
   return ds->factor_status;
@@ -1033,6 +1157,7 @@ hm_status hm_truncate_noalloc(hm_ctx* ctx, const double* X, int64_t m, const dou
 }
 
 hm_status hm_dataset_keep_matrix(hm_dataset* ds, int32_t keep) {
+  // (the mixed form allocates the copy itself, see assemble_launch)
   if (!ds) return HM_ERR_ARG;
   if (busy(ds->ctx)) return HM_ERR_BUSY;
   HIPTRY(hipSetDevice(ds->ctx->device));
@@ -1046,17 +1171,7 @@ hm_status hm_dataset_keep_matrix(hm_dataset* ds, int32_t keep) {
     ds->keep_c = ds->c_valid = false;
     return HM_OK;
   }
-  if (!ds->c_store) {
-    const Plan& P = ds->plan;
-    const size_t b = sizeof(double) * ((size_t)P.dense_pool + (size_t)P.lr_pool) +
-                     sizeof(int32_t) * ds->tree.bk.size() + 256;
-    if (hipMalloc(&ds->c_store, b) != hipSuccess) {
-      (void)hipGetLastError();
-      ds->c_store = nullptr;
-      return HM_ERR_OOM;
-    }
-    ds->c_bytes = b;
-  }
+  if (!ds->c_store) TRY(alloc_matrix_copy(ds));
   ds->keep_c = true;
   return HM_OK;
 }

@@ -78,6 +78,7 @@ struct DevData {
   double eps;
   int32_t kfix;
   int32_t kmax;               // rank cap (K_MAX, or kfix)
+  int32_t mixed;              // 1: low-rank factors FP32-valued, their products in FP32 (HM_MIXED)
   int32_t dflush;             // low-rank blocks of at most dflush x dflush take their updates explicitly
 };
 
@@ -122,6 +123,14 @@ hipError_t launch_task_levels(const DevData& D, const Task* tasks, const int32_t
 hipError_t launch_apply(const DevData& D, int mode, const int32_t* chunks, int32_t nchunks, int max_grid,
                         hipStream_t st);
 hipError_t launch_dense_matvec(const DevData& D, hipStream_t st);
+// Refinement vector steps on n x r arrays (leading dimension n), with
+// per-work-group partial sums (fixed order) in part (grid x (2 r) doubles):
+//   resid:  R = Z - Y; part[g][c] = sum R^2, part[g][r + c] = sum Z^2 (column c)
+//   update: X += Dx; part[g][c] = sum Z X (column c, after the update)
+hipError_t launch_refine_resid(const double* Z, const double* Y, double* R, int64_t n, int r, double* part, int grid,
+                               hipStream_t st);
+hipError_t launch_refine_update(double* X, const double* Dx, const double* Z, int64_t n, int r, double* part,
+                                int grid, hipStream_t st);
 hipError_t launch_permute(const double* Z, const int64_t* perm, int64_t n, int r, double* W, hipStream_t st);
 hipError_t launch_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z, hipStream_t st);
 // Forward solve L v = Z (Z permuted into W, then the solve task levels

@@ -193,6 +193,17 @@ __device__ __forceinline__ double entry(const DevData& D, int64_t i, int64_t j) 
 __device__ __forceinline__ double* lr_U(const DevData& D, int32_t b) { return D.lr + D.lr_off[b]; }
 __device__ __forceinline__ double* lr_V(const DevData& D, int32_t b) { return D.lr + D.lr_voff[b]; }
 
+// Rounds the rows x cols block A (ld) to FP32 values (the storage precision of
+// low-rank factors in the mixed form).
+__device__ void round_f32(double* A, int64_t rows, int cols, int64_t ld) {
+  for (int64_t e = threadIdx.x; e < rows * (int64_t)cols; e += NT) {
+    double* p = A + (e % rows) + (e / rows) * ld;
+    *p = (double)(float)*p;
+  }
+  __syncthreads();
+}
+
+
 // ------------------------------------------------------------------ dense leaves
 
 __global__ void __launch_bounds__(NT) k_assemble_dense(DevData D) {
@@ -239,7 +250,10 @@ __device__ __forceinline__ int group_size(int cols) {
 }
 
 // Panels with more rows than these take the wave-per-column QR steps and the
-// blocked QR (TALL_QR_ROWS), and the blocked application of Q (TALL_ROWS).
+// blocked QR (TALL_QR_ROWS), and the blocked application of Q (TALL_ROWS);
+// the pivoted QR takes wave-per-column steps while the columns below the pivot
+// row have at least CPQR_WAVE_ROWS entries.
+#define CPQR_WAVE_ROWS 96
 #define TALL_QR_ROWS 512
 #define TALL_ROWS 256
 
@@ -945,7 +959,44 @@ __device__ int wg_cpqr(double* A, int m, int n, int64_t lda, double tolrel, Smem
     const int C = n - j - 1;
     double sp = 0.0, t = 0.0, beta = alpha, scale = 0.0;
     flops += 2.0 * (m - j) + 6.0 * (double)(m - j) * C;
-    if (C > 0) {
+    if (C > 0 && m - j - 1 >= CPQR_WAVE_ROWS) {
+      // long columns: one wavefront per trailing column (each load instruction
+      // reads 64 consecutive rows), columns dealt round-robin to the waves;
+      // every wave forms the pivot column's norm itself, over the same rows in
+      // the same order, so all waves hold the same reflector
+      double pl = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) pl += a[i] * a[i];
+      sp = wave_sum(pl);
+      if (sp != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + sp), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      for (int cc = wv; cc < C; cc += NW) {
+        const int q = j + 1 + cc;
+        const int col = (q == bq) ? pj : pos[q];
+        double* ac = A + (int64_t)col * lda;
+        const double acj = ac[j];
+        double pn = 0.0;
+        if (sp != 0.0) {
+          double dl = 0.0;
+          for (int i = j + 1 + lane; i < m; i += 64) dl += a[i] * ac[i];
+          const double dot = wave_sum(dl);
+          const double f = t * (acj + scale * dot);
+          const double fs = f * scale;
+          if (lane == 0) ac[j] = acj - f;
+          for (int i = j + 1 + lane; i < m; i += 64) {
+            const double y = ac[i] - fs * a[i];
+            ac[i] = y;
+            pn += y * y;
+          }
+        } else {
+          for (int i = j + 1 + lane; i < m; i += 64) pn += ac[i] * ac[i];
+        }
+        pn = wave_sum(pn);
+        if (lane == 0) S.cn[nxt][col] = pn;
+      }
+    } else if (C > 0) {
       const int g = group_size(C);
       const int c = tid / g, gl = tid % g;
       const int q = j + 1 + (c < C ? c : 0);
@@ -1317,6 +1368,10 @@ __global__ void __launch_bounds__(NT) k_aca(DevData D) {
     const int kt = wg_truncate(D, Ua, m, Va, n, k, U, V, work, dyn, 4096, S);
     if (tid == 0) D.rank[b] = kt;
     __syncthreads();
+    if (D.mixed) {
+      round_f32(U, m, kt, m);
+      round_f32(V, n, kt, n);
+    }
   }
 }
 
@@ -1347,8 +1402,16 @@ __device__ __forceinline__ void term_factors(const DevData& D, const TermDef& t,
 // Y(i0:i1, :) += sign L_blk(i0:i1, :) W for one leaf of the factor (rows
 // local to the leaf): W (ncols(blk) x k, ldw), Y (ldy, row 0 = the leaf's
 // first row).  tmp: k_blk x k doubles (global or shared).
+__device__ void leaf_matvec_rows_f32(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k, double* Y,
+                                     int64_t ldy, float sign, double* tmp, Smem& S, int64_t i0, int64_t i1);
+
 __device__ void leaf_matvec_rows(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k, double* Y,
-                                 int64_t ldy, double sign, double* tmp, Smem& S, int64_t i0, int64_t i1) {
+                                 int64_t ldy, double sign, double* tmp, Smem& S, int64_t i0, int64_t i1,
+                                 bool f32 = false) {
+  if (f32) {
+    leaf_matvec_rows_f32(D, blk, W, ldw, k, Y, ldy, (float)sign, tmp, S, i0, i1);
+    return;
+  }
   const Block L = D.bk[blk];
   const int tid = threadIdx.x;
   const int64_t mr = i1 - i0;
@@ -1384,6 +1447,50 @@ __device__ void leaf_matvec_rows(const DevData& D, int32_t blk, const double* W,
       double acc = 0.0;
       for (int a = 0; a < kb; ++a) acc += U[i + (int64_t)a * L.m] * tmp[a + c * kb];
       Y[i + c * ldy] += sign * acc;
+    }
+  }
+  __syncthreads();
+}
+
+// FP32 arithmetic form of leaf_matvec_rows (the mixed-precision term
+// products): operands rounded to FP32, products and sums in FP32, Y kept
+// FP32-valued.
+__device__ void leaf_matvec_rows_f32(const DevData& D, int32_t blk, const double* W, int64_t ldw, int k, double* Y,
+                                     int64_t ldy, float sign, double* tmp, Smem& S, int64_t i0, int64_t i1) {
+  const Block L = D.bk[blk];
+  const int tid = threadIdx.x;
+  const int64_t mr = i1 - i0;
+  if (tid == 0)
+    S.flops += (L.kind == BK_DENSE) ? 2.0 * mr * L.n * k : 2.0 * (double)(mr + L.n) * D.rank[blk] * k;
+  if (L.kind == BK_DENSE) {
+    const double* A = D.dense + D.dense_off[blk];
+    for (int64_t e = tid; e < mr * (int64_t)k; e += NT) {
+      const int64_t i = i0 + e % mr;
+      const int c = (int)(e / mr);
+      float acc = 0.0f;
+      for (int64_t l = 0; l < L.n; ++l) acc += (float)A[i + l * L.m] * (float)W[l + c * ldw];
+      Y[i + c * ldy] = (double)((float)Y[i + c * ldy] + sign * acc);
+    }
+  } else {
+    const double* U = lr_U(D, blk);
+    const double* V = lr_V(D, blk);
+    const int kb = D.rank[blk];
+    const int w = tid >> 6, lane = tid & 63;
+    for (int e = w; e < kb * k; e += NW) {
+      const int a = e % kb, c = e / kb;
+      float acc = 0.0f;
+      for (int64_t l = lane; l < L.n; l += 64) acc += (float)V[l + a * L.n] * (float)W[l + c * ldw];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (lane == 0) tmp[e] = (double)acc;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < mr * (int64_t)k; e += NT) {
+      const int64_t i = i0 + e % mr;
+      const int c = (int)(e / mr);
+      float acc = 0.0f;
+      for (int a = 0; a < kb; ++a) acc += (float)U[i + (int64_t)a * L.m] * (float)tmp[a + c * kb];
+      Y[i + c * ldy] = (double)((float)Y[i + c * ldy] + sign * acc);
     }
   }
   __syncthreads();
@@ -1525,7 +1632,8 @@ __device__ void task_term(const DevData& D, int32_t tid_term, double* tmp, Smem&
   for (int32_t q = D.sub_begin[H]; q < D.sub_end[H]; ++q) {
     const int32_t lf = D.sub_leaves[q];
     const Block L = D.bk[lf];
-    leaf_matvec(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp, S);
+    leaf_matvec_rows(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp, S, 0, L.m,
+                     D.mixed != 0);
   }
 }
 
@@ -1552,7 +1660,7 @@ __device__ void task_term_rows(const DevData& D, const Task& tk, double* tmp, Sm
     const int64_t a = (q.begin > L.r0 ? q.begin : L.r0), b = (q.end < L.r0 + L.m ? q.end : L.r0 + L.m);
     if (a >= b) continue;
     leaf_matvec_rows(D, lf, Vr + (L.c0 - HB.c0), RB.n, k, out + (L.r0 - HB.r0), t.rows, 1.0, tmp, S,
-                     a - L.r0, b - L.r0);
+                     a - L.r0, b - L.r0, D.mixed != 0);
   }
 }
 
@@ -1581,7 +1689,10 @@ __device__ void task_solve_seq(const DevData& D, const Task& tk, double* slot, d
   int k;
   solve_target(D, tk.obj, W, ld, k, base);
   if (k <= 0) return;
-  run_solve(D, tk.a0, W + (D.cl[tk.a0].begin - base), ld, k, slot, lds, S);
+  const Cluster c = D.cl[tk.a0];
+  run_solve(D, tk.a0, W + (c.begin - base), ld, k, slot, lds, S);
+  // rows of c are final: a low-rank factor's V is stored FP32-valued in the mixed form
+  if (D.mixed && tk.obj >= 0) round_f32(W + (c.begin - base), c.end - c.begin, k, ld);
 }
 
 // W(rows of cluster q = tk.a1) -= L_blk(those rows, :) W(cols of blk), blk =
@@ -1731,6 +1842,55 @@ __device__ __forceinline__ void tile_xyT(Tile& T, double sign, const double* X, 
   }
 }
 
+// FP32 form of tile_xyT (mixed precision): operands rounded to FP32, the
+// product formed and accumulated by v_mfma_f32_16x16x4f32 in FP32, then added
+// to the FP64 tile.  That instruction holds accumulator row 4 (l >> 4) + q in
+// lane l, register q, against (l >> 4) + 4 q for the FP64 one, so the A
+// operand's rows are fed permuted (row 4 a + q carries tile row a + 4 q) to
+// land every product in the lane and register of the FP64 tile's entry.
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void tile_xyT_f32(Tile& T, double sign, const double* X, int64_t ldx, int64_t xr,
+                                             const double* Y, int64_t ldy, int64_t yr, int r, int i0, int i1, int j0,
+                                             int j1) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr0 = 16 * w;
+  if (wr0 >= i1 || wr0 + 16 <= i0) return;
+  const int ar = lane & 15;
+  const int i = wr0 + (ar >> 2) + 4 * (ar & 3);     // the permuted A row
+  const bool rowin = i >= i0 && i < i1;
+  const double* xp = X + xr + (rowin ? i - i0 : 0);
+  const int kl = lane >> 4;
+  bool colin[4];
+  const double* yp[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = 16 * c + (lane & 15);
+    colin[c] = j >= j0 && j < j1;
+    yp[c] = Y + yr + (colin[c] ? j - j0 : 0);
+  }
+  const bool cact[4] = {16 * 0 < j1 && 16 * 0 + 16 > j0, 16 * 1 < j1 && 16 * 1 + 16 > j0,
+                        16 * 2 < j1 && 16 * 2 + 16 > j0, 16 * 3 < j1 && 16 * 3 + 16 > j0};
+  fvec4 acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = fvec4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < r; k0 += 4) {
+    const int k = k0 + kl;
+    const bool kin = k < r;
+    const float a = (kin && rowin) ? (float)xp[(int64_t)k * ldx] : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (!cact[c]) continue;
+      const float bv = (kin && colin[c]) ? (float)yp[c][(int64_t)k * ldy] : 0.0f;
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T.acc[c][q] += sign * (double)acc[c][q];
+}
+
 // Subtracts a leaf's restricted update terms, in order, from the tm x tn tile
 // at (ti0, tj0) of the block (FP64 matrix instructions, factors read from
 // global memory).
@@ -1751,8 +1911,14 @@ __device__ void apply_terms(const DevData& D, const Task& tk, int ti0, int tj0, 
     int64_t ldx, ldy;
     term_factors(D, t, X, ldx, Y, ldy);
     if (tid == 0) S.flops += 2.0 * (r1 - r0) * (c1 - c0) * r;
-    tile_xyT(T, -1.0, X, ldx, in.xr0 + (r0 - in.lr0), Y, ldy, in.yr0 + (c0 - in.lc0), r, r0 - ti0, r1 - ti0,
-             c0 - tj0, c1 - tj0);
+    // products of dense leaves stay FP64; products with low-rank factors are
+    // FP32 in the mixed form
+    if (D.mixed && t.kind != TK_DD)
+      tile_xyT_f32(T, -1.0, X, ldx, in.xr0 + (r0 - in.lr0), Y, ldy, in.yr0 + (c0 - in.lc0), r, r0 - ti0, r1 - ti0,
+                   c0 - tj0, c1 - tj0);
+    else
+      tile_xyT(T, -1.0, X, ldx, in.xr0 + (r0 - in.lr0), Y, ldy, in.yr0 + (c0 - in.lc0), r, r0 - ti0, r1 - ti0,
+               c0 - tj0, c1 - tj0);
   }
 }
 
@@ -1821,8 +1987,8 @@ __device__ void task_dense(const DevData& D, const Task& tk, int32_t prog, doubl
 // Low-rank leaf whose row and column clusters both hold at most D.dflush
 // points (<= CMAX): the updated block U V^T - sum X Y^T is formed exactly, one
 // LEAF_MAX x LEAF_MAX tile at a time in registers, and replaced by its best
-// approximation (wg_svd_explicit).  The explicit block lives in LDS when it is
-// a single tile, else in the work-group's global workspace slot.  Returns the
+// approximation (wg_svd_explicit).  The explicit block lives in LDS when it
+// fits (up to 128 x 128), else in the work-group's global workspace slot.  Returns the
 // new rank (also written to D.rank).
 __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, double* lds, Smem& S) {
   const int tid = threadIdx.x;
@@ -1833,7 +1999,7 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
   double* V = lr_V(D, b);
   const int k0 = D.rank[b];
   const int64_t c0 = (tid == 0) ? clk() : 0;
-  const bool small = m <= LEAF_MAX && n <= LEAF_MAX;
+  const bool small = (int64_t)(m | 1) * n <= LDS_FACTOR;   // the explicit block fits in LDS
   const int lda = small ? (m | 1) : m;
   double* A = small ? lds : slot;
   for (int tj0 = 0; tj0 < n; tj0 += LEAF_MAX) {
@@ -1842,7 +2008,10 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
       const int tn = (n - tj0 < LEAF_MAX) ? n - tj0 : LEAF_MAX;
       Tile T;
       tile_zero(T);
-      if (k0 > 0) tile_xyT(T, 1.0, U, m, ti0, V, n, tj0, k0, 0, tm, 0, tn);
+      if (k0 > 0) {
+        if (D.mixed) tile_xyT_f32(T, 1.0, U, m, ti0, V, n, tj0, k0, 0, tm, 0, tn);
+        else tile_xyT(T, 1.0, U, m, ti0, V, n, tj0, k0, 0, tm, 0, tn);
+      }
       apply_terms(D, tk, ti0, tj0, tm, tn, T, S);
       tile_store(T, A + ti0 + (int64_t)tj0 * lda, lda, tm, tn);
     }
@@ -1860,6 +2029,10 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
   const int k = wg_svd_explicit(D, A, m, n, lda, U, m, m, V, n, n, gws, glds, gcap, S, true);
   if (tid == 0) D.rank[b] = k;
   __syncthreads();
+  if (D.mixed) {
+    round_f32(U, m, k, m);
+    round_f32(V, n, k, n);
+  }
   return k;
 }
 
@@ -1920,6 +2093,10 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
     if (tid == 0) D.rank[b] = kk;
     if (tid == 0) S.ival[0] = kk;
     __syncthreads();
+    if (D.mixed) {
+      round_f32(U, m, kk, m);
+      round_f32(V, n, kk, n);
+    }
   } else {
     if (tid == 0) S.ival[0] = D.rank[b];
     __syncthreads();
@@ -1929,6 +2106,7 @@ __device__ void task_lr(const DevData& D, const Task& tk, double* slot, double* 
   if (tk.a0 == 0) return;   // the solve runs as tasks of its own
   int64_t c0 = (tid == 0) ? clk() : 0;
   if (k > 0) run_solve(D, tk.diag, V, n, k, slot, lds, S);
+  if (D.mixed && k > 0) round_f32(V, n, k, n);
   if (tid == 0) S.ph[3] += clk() - c0;
 }
 
@@ -2099,7 +2277,9 @@ __device__ void task_ts_c(const DevData& D, const Task& tk, double* slot, Smem& 
     __syncthreads();
     wg_apply_q(A, rows, p, ld, tau, tmp, app, rows, S);
     __syncthreads();
-    for (int64_t e = tid; e < rows * app; e += NT) A[(e % rows) + (e / rows) * ld] = tmp[e];
+    const bool fin = tk.a0 > tk.ninst;
+    for (int64_t e = tid; e < rows * app; e += NT)
+      A[(e % rows) + (e / rows) * ld] = (fin && D.mixed) ? (double)(float)tmp[e] : tmp[e];
     __syncthreads();
   }
   if (tk.a0 > tk.ninst) return;        // the final step appends nothing
@@ -2220,6 +2400,52 @@ __global__ void __launch_bounds__(NT) k_dense_matvec(DevData D) {
 #pragma unroll
   for (int q = 0; q < 4; ++q)
     if (q < D.r) D.Y[i + q * D.n] = acc[q];
+}
+
+// R = Z - Y and per-work-group partial sums of R^2 and Z^2 per column, each
+// work-group over a contiguous range of rows, in a fixed order.
+__global__ void __launch_bounds__(NT) k_refine_resid(const double* Z, const double* Y, double* R, int64_t n, int r,
+                                                     double* part) {
+  __shared__ double red[NW];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = blockIdx.x * per, i1 = (i0 + per < n) ? i0 + per : n;
+  for (int c = 0; c < r; ++c) {
+    double sr = 0.0, sz = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) {
+      const double z = Z[i + c * n], v = z - Y[i + c * n];
+      R[i + c * n] = v;
+      sr += v * v;
+      sz += z * z;
+    }
+    sr = block_sum(sr, red);
+    sz = block_sum(sz, red);
+    if (threadIdx.x == 0) {
+      part[blockIdx.x * 2 * r + c] = sr;
+      part[blockIdx.x * 2 * r + r + c] = sz;
+    }
+  }
+}
+
+// X += Dx (Dx may be null: no update) and per-work-group partial sums of Z X
+// per column.
+__global__ void __launch_bounds__(NT) k_refine_update(double* X, const double* Dx, const double* Z, int64_t n, int r,
+                                                      double* part) {
+  __shared__ double red[NW];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = blockIdx.x * per, i1 = (i0 + per < n) ? i0 + per : n;
+  for (int c = 0; c < r; ++c) {
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) {
+      double x = X[i + c * n];
+      if (Dx) {
+        x += Dx[i + c * n];
+        X[i + c * n] = x;
+      }
+      s += Z[i + c * n] * x;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x * 2 * r + c] = s;
+  }
 }
 
 __global__ void k_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z) {
@@ -2420,6 +2646,18 @@ hipError_t launch_apply(const DevData& D, int mode, const int32_t* chunks, int32
 hipError_t launch_dense_matvec(const DevData& D, hipStream_t st) {
   const int64_t g = (D.n + NT - 1) / NT;
   hipLaunchKernelGGL(k_dense_matvec, dim3((unsigned)g), dim3(NT), 0, st, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_resid(const double* Z, const double* Y, double* R, int64_t n, int r, double* part, int grid,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_resid, dim3(grid), dim3(NT), 0, st, Z, Y, R, n, r, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_update(double* X, const double* Dx, const double* Z, int64_t n, int r, double* part,
+                                int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_update, dim3(grid), dim3(NT), 0, st, X, Dx, Z, n, r, part);
   return hipGetLastError();
 }
 

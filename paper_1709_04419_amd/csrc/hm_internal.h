@@ -75,6 +75,14 @@ struct hm_dataset {
   void* c_store = nullptr;
   size_t c_bytes = 0;
   bool theta_set = false;             // an assembly has set theta (the exact covariance product)
+  // arithmetic of the last assembly (hm_precision) and its refinement controls
+  int32_t prec = HM_FP64;
+  int32_t refine_max_iter = 0;
+  double refine_tol = 0.0;
+  double* d_part = nullptr;           // partial sums of the refinement (NSLOTS_RED x 128 doubles)
+  // per column: refined Z^T x, its relative residual, and the corrections applied
+  std::vector<double> ref_quad, ref_resid;
+  int32_t ref_iters = 0;
   std::vector<int32_t> level_begin;   // position in `order` where each level starts (+ end)
   std::vector<int32_t> order;         // execution order (task ids), level by level
   int32_t* d_order = nullptr;
@@ -83,6 +91,8 @@ struct hm_dataset {
 
 namespace hm_int {
 
+// allocates the copy of the assembled matrix (dense pool, low-rank pool, ranks)
+hm_status alloc_matrix_copy(hm_dataset* ds);
 // theta and accuracy checks shared by every evaluation entry point
 hm_status check_theta_approx(const hm_theta* th, const hm_approx* ap);
 // allocates the factor storage if it is not attached

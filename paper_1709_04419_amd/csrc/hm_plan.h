@@ -107,11 +107,14 @@ constexpr int64_t TERM_SPLIT = 1024;
 // of the two factors in parallel (QR of each row block, then one QR of the
 // stacked R factors: tall-skinny QR).
 #ifndef HM_TS_BIG
-#define HM_TS_BIG 2048
+#define HM_TS_BIG 256
+#endif
+#ifndef HM_TS_MINROWS
+#define HM_TS_MINROWS 256
 #endif
 constexpr int64_t TS_BIG = HM_TS_BIG;
-constexpr int TS_GMAX = 16;          // row blocks per factor at most
-constexpr int64_t TS_MINROWS = 1024; // rows per row block at least (>= 2 K_MAX)
+constexpr int TS_GMAX = 16;                     // row blocks per factor at most
+constexpr int64_t TS_MINROWS = HM_TS_MINROWS;   // rows per row block at least (>= 2 K_MAX)
 // Row blocks of a factor with `rows` rows: g blocks of ceil(rows / g) rows.
 inline int ts_blocks(int64_t rows) {
   int64_t g = (rows + TS_MINROWS - 1) / TS_MINROWS;

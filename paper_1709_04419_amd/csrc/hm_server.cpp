@@ -482,6 +482,7 @@ hm_status hm_server_create(hm_ctx* ctx, const hm_server_opts* opts, hm_server** 
 hm_status hm_server_submit(hm_server* sv, hm_dataset* ds, const hm_theta* theta, const hm_approx* approx,
                            uint64_t* ticket) {
   if (!sv || !ds || !ticket || ds->ctx != sv->ctx || ds->r < 1) return HM_ERR_ARG;
+  if (approx && approx->prec != HM_FP64) return HM_ERR_ARG;   // served and batched forms: FP64
   const hm_status c = check_theta_approx(theta, approx);
   if (c != HM_OK) return c;
   if (sv->budget > 0 && (int64_t)ds->store_bytes > sv->budget) return HM_ERR_OOM;

@@ -246,8 +246,8 @@ class Dataset:
         return (hm_theta(sigma2, ell, nu, nugget),
                 hm_approx(int(rank), float(eps), int(prec), int(refine_max_iter), float(refine_tol)))
 
-    def assemble(self, theta, nugget, eps=0.0, rank=0):
-        th, ap = self._args(theta, nugget, eps, rank)
+    def assemble(self, theta, nugget, eps=0.0, rank=0, prec=HM_FP64, refine_max_iter=0, refine_tol=0.0):
+        th, ap = self._args(theta, nugget, eps, rank, prec, refine_max_iter, refine_tol)
         _check(_lib.hm_assemble(self._h, C.byref(th), C.byref(ap)), "hm_assemble")
 
     def factor(self) -> int:
@@ -263,19 +263,22 @@ class Dataset:
             raise HMError(s, "hm_solve")
         return _results(out)
 
-    def loglik(self, theta, nugget, eps=0.0, rank=0):
-        """Eq. (4) for every column of Z; returns a dict of arrays."""
-        th, ap = self._args(theta, nugget, eps, rank)
+    def loglik(self, theta, nugget, eps=0.0, rank=0, prec=HM_FP64, refine_max_iter=0, refine_tol=0.0):
+        """Eq. (4) for every column of Z; returns a dict of arrays.  prec=HM_MIXED
+        selects the mixed-precision form with iterative refinement of C~^{-1} Z
+        (at most refine_max_iter corrections, stopping at relative residual
+        refine_tol)."""
+        th, ap = self._args(theta, nugget, eps, rank, prec, refine_max_iter, refine_tol)
         out = (hm_result * self.r)()
         s = _lib.hm_loglik(self._h, C.byref(th), C.byref(ap), out)
         if s not in (HM_OK, HM_ERR_NOT_SPD):
             raise HMError(s, "hm_loglik")
         return _results(out)
 
-    def tune_schedule(self, theta, nugget, eps=0.0, rank=0) -> int:
+    def tune_schedule(self, theta, nugget, eps=0.0, rank=0, prec=HM_FP64) -> int:
         """hm_tune_schedule: one timed evaluation, then the level assignment of
         the factorisation's tasks is re-balanced (results unchanged)."""
-        th, ap = self._args(theta, nugget, eps, rank)
+        th, ap = self._args(theta, nugget, eps, rank, prec)
         s = _lib.hm_tune_schedule(self._h, C.byref(th), C.byref(ap))
         if s not in (HM_OK, HM_ERR_NOT_SPD):
             raise HMError(s, "hm_tune_schedule")
