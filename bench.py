@@ -172,7 +172,11 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
-    ap.add_argument("--form", choices=("plain", "served", "batched", "stream"), default="plain")
+    ap.add_argument("--form", choices=("plain", "served", "batched", "stream", "mc"), default="plain")
+    ap.add_argument("--mc-n", type=int, default=4000, help="mc form: locations")
+    ap.add_argument("--mc-mixed-replicates", type=int, default=0,
+                    help="mc form: mixed-precision fits for the first replicates only (0: all)")
+    ap.add_argument("--mc-max-evals", type=int, default=300)
     ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64",
                     help="plain form: FP64, or the mixed-precision form with refinement of C~^-1 Z")
     ap.add_argument("--refine-max-iter", type=int, default=10)
@@ -197,6 +201,8 @@ def main():
         return batched(args)
     if args.form == "stream":
         return stream(args)
+    if args.form == "mc":
+        return mc(args)
 
     import numpy as np
     import torch
@@ -416,6 +422,24 @@ def nm_trace(seed: int, length: int):
         out.append(tuple(float(v) for v in np.exp(x)))
         x = gen.send(float(np.sum(((x - centre) / scale) ** 2)))
     return out
+
+
+def mc(args):
+    """Monte-Carlo study of theta-hat (Section 4, Fig. 3): replicates simulated
+    on the device, FP64 fits through the request server, mixed fits one by one."""
+    from paper_1709_04419_amd import hmlik
+    from paper_1709_04419_amd import mc_study
+
+    ctx = hmlik.Context(0)
+    try:
+        out = mc_study.run(ctx, args.mc_n, args.replicates, eps=args.eps, mixed=(args.prec == "mixed"),
+                           mixed_replicates=args.mc_mixed_replicates, max_evals=args.mc_max_evals,
+                           refine_max_iter=args.refine_max_iter, refine_tol=args.refine_tol, log=log)
+    finally:
+        ctx.close()
+    out.update(metric="Monte-Carlo theta-hat study (Section 4, Fig. 3)", form="mc", data="synthetic",
+               n_gpus=1)
+    print(json.dumps(out), flush=True)
 
 
 def stream(args):

@@ -17,8 +17,10 @@
  *     returns (host pointers) or used only in the call's stream order
  *     (device pointers).  Handles are owned by the library.
  *   - Matrices are column-major; coordinates are n x 2 row-major (x0 y0 x1 y1 ...).
- *   - All arithmetic is FP64.  Results are deterministic: the same inputs give
- *     bitwise-equal outputs.
+ *   - Arithmetic is FP64 (prec = HM_FP64), or FP64 with FP32-valued low-rank
+ *     factors and FP32 low-rank products (prec = HM_MIXED, see hm_approx).
+ *     Results are deterministic: the same inputs give bitwise-equal outputs
+ *     (a level schedule only reorders tasks that do not depend on each other).
  *   - Calls on one dataset must not overlap; different datasets may be used
  *     from different threads only with different contexts.  While a request
  *     server (hm_server_*) exists on a context, it alone issues that context's
@@ -166,10 +168,11 @@ hm_status hm_solve(hm_dataset *ds, hm_result *out);
 hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, hm_result *out);
 
 /* Schedule tuning: runs one evaluation at theta (assembly and factorisation,
- * with per-task timing), then re-assigns the factorisation's tasks to levels:
- * sweeping backwards, a task moves to the latest level before its first
- * dependent task whose longest task (as timed) is at least as long, so that it
- * no longer sets the length of a level.  Later factorisations of the dataset,
+ * with per-task timing), then rebuilds the factorisation's levels from the
+ * timed durations: each level is led by the ready task with the longest timed
+ * chain to the end, takes every ready task that would lengthen the schedule if
+ * deferred, and every other ready task no longer than the level already is;
+ * longer tasks run first within a level.  Later factorisations of the dataset,
  * at any theta, use the new assignment; they run the same tasks on the same
  * inputs, so results are bitwise unchanged.  Returns the evaluation's status
  * (on HM_ERR_NOT_SPD the schedule is left as it was).  Allocates the timing
@@ -284,6 +287,19 @@ hm_status hm_simulate(hm_dataset *ds, const hm_theta *theta, const hm_approx *ap
  * from the start vector x0 (n entries, host, input order, not zero).  Each
  * step applies C twice (n^2 entries each) and solves with L~ L~^T twice. */
 hm_status hm_inverse_accuracy(hm_dataset *ds, const double *x0, int32_t iters, double *norm);
+
+/* Entries of the exact covariance C(theta) of eq. (2) plus the nugget on the
+ * diagonal (Sect. 2.2, 2.4), at the theta of the last assembly, in input
+ * order: out[a + b ldo] = C(i0 + a, j0 + b) for a < ni, b < nj (column-major,
+ * ldo >= ni).  The reference side of the accuracy diagnostics of Sect. 2.4
+ * (KLD and the error of log|C~| need C itself).  out is a host array, or a
+ * device array on the context's GPU with on_device = 1 (checked).
+ * HM_ERR_ARG for a range outside 0 .. n-1, ldo < ni, no assembly yet, or a
+ * pointer of the wrong kind; HM_ERR_OOM if the index map or the host staging
+ * buffer (ni nj doubles) cannot be allocated.  Allocates the index map (n
+ * int64) on first use. */
+hm_status hm_exact_block(hm_dataset *ds, int64_t i0, int64_t ni, int64_t j0, int64_t nj, double *out, int64_t ldo,
+                         int32_t on_device);
 
 /* Allocation-free truncation, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

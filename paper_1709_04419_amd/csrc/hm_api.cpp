@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -410,7 +411,8 @@ void hm_dataset_destroy(hm_dataset* ds) {
   (void)hipSetDevice(ds->ctx->device);
   (void)hipStreamSynchronize(ds->ctx->stream);
   for (auto& b : ds->bufs) (void)hipFree(b.p);
-  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out, (void*)ds->d_op, (void*)ds->d_part, ds->c_store})
+  for (void* q : {(void*)ds->d_Z, (void*)ds->d_W, (void*)ds->d_out, (void*)ds->d_op, (void*)ds->d_part, ds->c_store,
+                  (void*)ds->d_iperm})
     if (q) (void)hipFree(q);
   if (ds->store) (void)hipFree(ds->store);
   for (int i = 0; i < 4; ++i)
@@ -890,46 +892,6 @@ hm_status hm_loglik_batch(hm_ctx* ctx, int32_t m, hm_dataset* const* ds, const h
   return s != HM_OK ? s : any;
 }
 
-// Re-assigns tasks to levels.  Starting from the longest-path levels and
-// sweeping from the last task to the first, a task moves to the latest level
-// before its earliest successor (at most `horizon` levels on) whose longest
-// task, by the measured durations, is at least as long as it: it then no longer
-// sets the duration of a level.  Every dependency stays in an earlier level and
-// the number of levels does not change.
-static void relevel(const Plan& P, const std::vector<double>& dur, int32_t horizon, std::vector<int32_t>& lev) {
-  const int32_t nt = (int32_t)P.tasks.size();
-  lev.resize(nt);
-  int32_t L = 0;
-  for (int32_t t = 0; t < nt; ++t) {
-    lev[t] = P.tasks[t].level;
-    L = std::max(L, lev[t] + 1);
-  }
-  std::vector<int32_t> sbeg(nt + 1, 0), succ(P.deps.size());
-  for (int32_t t = 0; t < nt; ++t)
-    for (int32_t q = 0; q < P.tasks[t].ndeps; ++q) ++sbeg[P.deps[P.tasks[t].dep_begin + q] + 1];
-  for (int32_t t = 0; t < nt; ++t) sbeg[t + 1] += sbeg[t];
-  {
-    std::vector<int32_t> fill(sbeg.begin(), sbeg.end() - 1);
-    for (int32_t t = 0; t < nt; ++t)
-      for (int32_t q = 0; q < P.tasks[t].ndeps; ++q) succ[fill[P.deps[P.tasks[t].dep_begin + q]]++] = t;
-  }
-  std::vector<std::multiset<double>> at(L);
-  for (int32_t t = 0; t < nt; ++t) at[lev[t]].insert(dur[t]);
-  for (int32_t t = nt - 1; t >= 0; --t) {
-    int32_t hi = L - 1;
-    for (int32_t q = sbeg[t]; q < sbeg[t + 1]; ++q) hi = std::min(hi, lev[succ[q]] - 1);
-    const int32_t l0 = lev[t];
-    for (int32_t l = std::min(hi, l0 + horizon); l > l0; --l) {
-      if (!at[l].empty() && *at[l].rbegin() >= dur[t]) {
-        at[l0].erase(at[l0].find(dur[t]));
-        at[l].insert(dur[t]);
-        lev[t] = l;
-        break;
-      }
-    }
-  }
-}
-
 hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_approx* approx) {
   if (!ds || ds->r < 1) return HM_ERR_ARG;
   if (busy(ds->ctx)) return HM_ERR_BUSY;
@@ -951,17 +913,13 @@ hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_appro
   HIPTRY(hipMemcpy(tt.data(), ds->tt_buf, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost));
   std::vector<double> dur(nt);
   for (int32_t t = 0; t < nt; ++t) dur[t] = (double)(tt[7 * (size_t)t + 1] - tt[7 * (size_t)t]);
-  std::vector<int32_t> lev;
-  relevel(ds->plan, dur, 512, lev);
-  // counting sort of the task ids by level (stable)
-  int32_t L = 0;
-  for (int32_t v : lev) L = std::max(L, v + 1);
-  std::vector<int32_t> cnt(L + 1, 0);
-  for (int32_t v : lev) ++cnt[v + 1];
-  for (int32_t l = 0; l < L; ++l) cnt[l + 1] += cnt[l];
-  ds->level_begin.assign(cnt.begin(), cnt.end());
-  std::vector<int32_t> order(nt);
-  for (int32_t t = 0; t < nt; ++t) order[cnt[lev[t]]++] = t;
+  std::vector<int32_t> order, level_begin;
+  try {
+    schedule_by_durations(ds->plan, dur, order, level_begin);
+  } catch (const std::exception&) {
+    return HM_ERR_INTERNAL;
+  }
+  ds->level_begin = level_begin;
   ds->order = order;
   HIPTRY(hipMemcpy(ds->d_order, ds->order.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
   return HM_OK;
@@ -1253,6 +1211,56 @@ hm_status hm_apply(hm_dataset* ds, int32_t op, const double* W, double* Y, int32
     HIPTRY(hipStreamSynchronize(st));
   }
   return HM_OK;
+}
+
+hm_status hm_exact_block(hm_dataset* ds, int64_t i0, int64_t ni, int64_t j0, int64_t nj, double* out, int64_t ldo,
+                         int32_t on_device) {
+  if (!ds || !out) return HM_ERR_ARG;
+  const int64_t n = ds->tree.n;
+  if (i0 < 0 || ni < 0 || j0 < 0 || nj < 0 || i0 > n - ni || j0 > n - nj || ldo < (ni > 1 ? ni : 1))
+    return HM_ERR_ARG;
+  if (!ds->theta_set) return HM_ERR_ARG;
+  if (busy(ds->ctx)) return HM_ERR_BUSY;
+  if (ni == 0 || nj == 0) return HM_OK;
+  if (nj > 1 && ldo > (INT64_MAX - ni) / (nj - 1)) return HM_ERR_ARG;
+  HIPTRY(hipSetDevice(ds->ctx->device));
+  hipStream_t st = ds->ctx->stream;
+  if (on_device) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, out) != hipSuccess || a.type != hipMemoryTypeDevice ||
+        a.device != ds->ctx->device) {
+      (void)hipGetLastError();
+      return HM_ERR_ARG;
+    }
+  }
+  if (!ds->d_iperm) {
+    std::vector<int64_t> ip(n);
+    for (int64_t q = 0; q < n; ++q) ip[ds->tree.perm[q]] = q;
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(int64_t) * n) != hipSuccess) {
+      (void)hipGetLastError();
+      return HM_ERR_OOM;
+    }
+    ds->d_iperm = (int64_t*)p;
+    HIPTRY(hipMemcpy(ds->d_iperm, ip.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice));
+  }
+  if (on_device) {
+    HIPTRY(launch_exact_block(ds->D, ds->d_iperm, i0, ni, j0, nj, out, ldo, st));
+    HIPTRY(hipStreamSynchronize(st));
+    return HM_OK;
+  }
+  double* tmp = nullptr;
+  if (hipMalloc((void**)&tmp, sizeof(double) * ni * nj) != hipSuccess) {
+    (void)hipGetLastError();
+    return HM_ERR_OOM;
+  }
+  hipError_t e = launch_exact_block(ds->D, ds->d_iperm, i0, ni, j0, nj, tmp, ni, st);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(out, sizeof(double) * ldo, tmp, sizeof(double) * ni, sizeof(double) * ni, nj,
+                         hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  return e == hipSuccess ? HM_OK : HM_ERR_DEVICE;
 }
 
 hm_status hm_simulate(hm_dataset* ds, const hm_theta* theta, const hm_approx* approx, const double* W, double* Z,

@@ -123,6 +123,8 @@ hipError_t launch_task_levels(const DevData& D, const Task* tasks, const int32_t
 hipError_t launch_apply(const DevData& D, int mode, const int32_t* chunks, int32_t nchunks, int max_grid,
                         hipStream_t st);
 hipError_t launch_dense_matvec(const DevData& D, hipStream_t st);
+hipError_t launch_exact_block(const DevData& D, const int64_t* iperm, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                              double* out, int64_t ldo, hipStream_t st);
 // Refinement vector steps on n x r arrays (leading dimension n), with
 // per-work-group partial sums (fixed order) in part (grid x (2 r) doubles):
 //   resid:  R = Z - Y; part[g][c] = sum R^2, part[g][r + c] = sum Z^2 (column c)

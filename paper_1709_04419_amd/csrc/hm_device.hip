@@ -231,6 +231,7 @@ struct Smem {
   double cn[2][CMAX];      // pivoted QR: partial column norms^2 (by column), by step parity
   int32_t pos[2][CMAX];    // pivoted QR: column at each position, by step parity
   double tau_p[CMAX];      // pivoted QR: reflector coefficients
+  double tau_g[CMAX];      // QR of the transposed triangular factor (explicit SVD)
   double Tb[QB][QB];       // compact WY factor of a block of reflectors
   double gp[NW][QB * (QB - 1) / 2];   // per-wave partial Gram entries of that block
   int32_t flag;
@@ -254,6 +255,8 @@ __device__ __forceinline__ int group_size(int cols) {
 // the pivoted QR takes wave-per-column steps while the columns below the pivot
 // row have at least CPQR_WAVE_ROWS entries.
 #define CPQR_WAVE_ROWS 96
+// Rows per thread loaded together in the passes of the row-stored pivoted QR.
+#define CPQR_ROWS_BATCH 32
 #define TALL_QR_ROWS 512
 #define TALL_ROWS 256
 
@@ -972,29 +975,57 @@ __device__ int wg_cpqr(double* A, int m, int n, int64_t lda, double tolrel, Smem
         t = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      for (int cc = wv; cc < C; cc += NW) {
-        const int q = j + 1 + cc;
-        const int col = (q == bq) ? pj : pos[q];
-        double* ac = A + (int64_t)col * lda;
-        const double acj = ac[j];
-        double pn = 0.0;
+      // four columns of a wave at a time, so that each row step has five
+      // independent loads in flight
+      for (int c0 = 4 * wv; c0 < C; c0 += 4 * NW) {
+        const int nc = (C - c0 < 4) ? C - c0 : 4;
+        double* cols[4];
+        int cid[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = j + 1 + c0 + (u < nc ? u : 0);
+          cid[u] = (q == bq) ? pj : pos[q];
+          cols[u] = A + (int64_t)cid[u] * lda;
+        }
+        double pn[4] = {0.0, 0.0, 0.0, 0.0};
         if (sp != 0.0) {
-          double dl = 0.0;
-          for (int i = j + 1 + lane; i < m; i += 64) dl += a[i] * ac[i];
-          const double dot = wave_sum(dl);
-          const double f = t * (acj + scale * dot);
-          const double fs = f * scale;
-          if (lane == 0) ac[j] = acj - f;
+          double acj[4], dl[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acj[u] = cols[u][j];
           for (int i = j + 1 + lane; i < m; i += 64) {
-            const double y = ac[i] - fs * a[i];
-            ac[i] = y;
-            pn += y * y;
+            const double ai = a[i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dl[u] += ai * cols[u][i];
+          }
+          double fs[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double dot = wave_sum(dl[u]);
+            const double f = t * (acj[u] + scale * dot);
+            fs[u] = f * scale;
+            if (lane == 0 && u < nc) cols[u][j] = acj[u] - f;
+          }
+          for (int i = j + 1 + lane; i < m; i += 64) {
+            const double ai = a[i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (u < nc) {
+                const double y = cols[u][i] - fs[u] * ai;
+                cols[u][i] = y;
+                pn[u] += y * y;
+              }
           }
         } else {
-          for (int i = j + 1 + lane; i < m; i += 64) pn += ac[i] * ac[i];
+          for (int i = j + 1 + lane; i < m; i += 64) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pn[u] += cols[u][i] * cols[u][i];
+          }
         }
-        pn = wave_sum(pn);
-        if (lane == 0) S.cn[nxt][col] = pn;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double v = wave_sum(pn[u]);
+          if (lane == 0 && u < nc) S.cn[nxt][cid[u]] = v;
+        }
       }
     } else if (C > 0) {
       const int g = group_size(C);
@@ -1094,6 +1125,134 @@ __device__ int wg_cpqr(double* A, int m, int n, int64_t lda, double tolrel, Smem
   return r;
 }
 
+// Pivoted QR of a matrix stored by rows (At[c + i ldt] = A(i, c); n <= NT):
+// the same steps, pivot rule, stopping rule and outputs as wg_cpqr, with the
+// entries of column c at At[c + i ldt].  Thread c owns column c for the whole
+// factorisation: it forms the column's dot product with the pivot column, its
+// update and its new norm by itself, reading one row of 64 consecutive
+// columns per wavefront load, so no step needs a cross-lane reduction except
+// the pivot column's norm.  The pivot column is staged in sa (LDS, m doubles);
+// piv (LDS, n ints) marks the columns already chosen.
+__device__ int wg_cpqr_rows(double* At, int m, int n, int64_t ldt, double tolrel, double* sa, int32_t* piv,
+                            Smem& S) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int p = m < n ? m : n;
+  const int c = tid;
+  const bool own = c < n;
+  double* col = At + c;
+  if (own) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < m; i += CPQR_ROWS_BATCH) {
+      double x[CPQR_ROWS_BATCH];
+#pragma unroll
+      for (int u = 0; u < CPQR_ROWS_BATCH; ++u) x[u] = (i + u < m) ? col[(int64_t)(i + u) * ldt] : 0.0;
+#pragma unroll
+      for (int u = 0; u < CPQR_ROWS_BATCH; ++u) v[u & 3] += x[u] * x[u];
+    }
+    S.cn[0][c] = (v[0] + v[1]) + (v[2] + v[3]);
+    S.pos[0][c] = c;
+    piv[c] = 0;
+  }
+  __syncthreads();
+  const double f2 = block_sum(own ? S.cn[0][c] : 0.0, S.red);
+  const double thr = tolrel * tolrel * f2;
+  int r = p;
+  double flops = 0.0;
+  for (int j = 0; j < p; ++j) {
+    const int cur = j & 1, nxt = cur ^ 1;
+    const int32_t* pos = S.pos[cur];
+    const double* cn = S.cn[cur];
+    double best = -1.0;
+    int bq = n;
+    for (int q = j + lane; q < n; q += 64) {
+      const double v = cn[pos[q]];
+      if (v > best) { best = v; bq = q; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b2 = __shfl_xor(best, o, 64);
+      const int q2 = __shfl_xor(bq, o, 64);
+      if (b2 > best || (b2 == best && q2 < bq)) { best = b2; bq = q2; }
+    }
+    if (!(best > thr)) { r = j; break; }
+    const int pc = pos[bq], pj = pos[j];
+    for (int q = tid; q < n; q += NT) S.pos[nxt][q] = (q == j) ? pc : (q == bq) ? pj : pos[q];
+    for (int i = j + tid; i < m; i += NT) sa[i] = At[pc + (int64_t)i * ldt];
+    __syncthreads();
+    const double alpha = sa[j];
+    double pl = 0.0;
+    for (int i = j + 1 + lane; i < m; i += 64) pl += sa[i] * sa[i];
+    const double sp = wave_sum(pl);
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (sp != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sp), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    flops += 2.0 * (m - j) + 6.0 * (double)(m - j) * (n - j - 1);
+    if (own && c != pc && !piv[c]) {
+      double pn0 = 0.0, pn1 = 0.0, pn2 = 0.0, pn3 = 0.0;
+      if (sp != 0.0) {
+        const double acj = col[(int64_t)j * ldt];
+        // CPQR_ROWS_BATCH rows in flight per thread (a wavefront keeps as many
+        // loads of 512 consecutive bytes outstanding)
+        // rows past the end of the column load as zero (the batch stays whole)
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = j + 1; i < m; i += CPQR_ROWS_BATCH) {
+          double x[CPQR_ROWS_BATCH];
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; ++u) x[u] = (i + u < m) ? col[(int64_t)(i + u) * ldt] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; ++u)
+            if (i + u < m) d[u & 3] += sa[i + u] * x[u];
+        }
+        const double dot = (d[0] + d[1]) + (d[2] + d[3]);
+        const double f = t * (acj + scale * dot);
+        col[(int64_t)j * ldt] = acj - f;
+        const double fs = f * scale;
+        for (int i = j + 1; i < m; i += CPQR_ROWS_BATCH) {
+          double y[CPQR_ROWS_BATCH];
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; ++u) y[u] = (i + u < m) ? col[(int64_t)(i + u) * ldt] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; ++u)
+            if (i + u < m) {
+              y[u] -= fs * sa[i + u];
+              col[(int64_t)(i + u) * ldt] = y[u];
+            }
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; u += 4) {
+            pn0 += y[u] * y[u]; pn1 += y[u + 1] * y[u + 1]; pn2 += y[u + 2] * y[u + 2]; pn3 += y[u + 3] * y[u + 3];
+          }
+        }
+      } else {
+        for (int i = j + 1; i < m; i += CPQR_ROWS_BATCH) {
+          double y[CPQR_ROWS_BATCH];
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; ++u) y[u] = (i + u < m) ? col[(int64_t)(i + u) * ldt] : 0.0;
+#pragma unroll
+          for (int u = 0; u < CPQR_ROWS_BATCH; u += 4) {
+            pn0 += y[u] * y[u]; pn1 += y[u + 1] * y[u + 1]; pn2 += y[u + 2] * y[u + 2]; pn3 += y[u + 3] * y[u + 3];
+          }
+        }
+      }
+      S.cn[nxt][c] = (pn0 + pn1) + (pn2 + pn3);
+    }
+    // the pivot column becomes R(j, j) and, below it, the reflector
+    if (tid == 0) {
+      At[pc + (int64_t)j * ldt] = beta;
+      S.tau_p[j] = t;
+      piv[pc] = 1;
+    }
+    if (sp != 0.0)
+      for (int i = j + 1 + tid; i < m; i += NT) At[pc + (int64_t)i * ldt] = sa[i] * scale;
+    __syncthreads();
+  }
+  if (tid == 0) S.flops += flops;
+  __syncthreads();
+  return r;
+}
+
 // Best approximation of an explicit m x n matrix A (lda; destroyed; n <= CMAX)
 // at the accuracy of D (relative eps, or the fixed rank), capped at D.kmax.
 // Pivoted QR A P = Q R (wg_cpqr; in the accuracy mode stopped at a remainder
@@ -1109,7 +1268,8 @@ __device__ int wg_cpqr(double* A, int m, int n, int64_t lda, double tolrel, Smem
 // R^T when it does not fit in lds (lds_cap doubles).
 __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_t lda, double* U, int64_t mU,
                                int64_t ldu, double* V, int64_t nV, int64_t ldv, double* gws, double* lds,
-                               int lds_cap, Smem& S, bool timed = false) {
+                               int lds_cap, Smem& S, bool timed = false, double* a_spill = nullptr,
+                               bool by_rows = false) {
   const int tid = threadIdx.x;
   int64_t c0 = (timed && tid == 0) ? clk() : 0;
   const double u = 2.220446049250313e-16;
@@ -1118,22 +1278,71 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
     tolrel = 2.0 * (double)(m > n ? m : n) * u;
     if (1e-3 * D.eps < tolrel) tolrel = 1e-3 * D.eps;
   }
-  const int r = wg_cpqr(A, m, n, lda, tolrel, S);
+  if (D.mixed) {
+    // FP32-valued inputs: below 4 u_32 ||A||_F the remainder is rounding of the
+    // inputs (kept under 1e-2 eps, so no singular value that eps keeps is lost)
+    double t32 = 4.0 * 5.9604644775390625e-8;
+    if (D.kfix <= 0 && 1e-2 * D.eps < t32) t32 = 1e-2 * D.eps;
+    if (t32 > tolrel) tolrel = t32;
+  }
+  const int r = by_rows ? wg_cpqr_rows(A, m, n, lda, tolrel, lds, (int32_t*)(lds + m), S)
+                        : wg_cpqr(A, m, n, lda, tolrel, S);
   if (timed && tid == 0) { const int64_t c1 = clk(); S.ph[0] += c1 - c0; c0 = c1; }
+  // entry (i, c) of the factored A
+  const int64_t si = by_rows ? lda : 1, sc = by_rows ? 1 : lda;
   if (r == 0) return 0;
   const int32_t* pos = S.pos[r & 1];
   const int ldg = (int)odd_ld(n);
+  if (a_spill && (int64_t)ldg * r > lds_cap && (int64_t)ldg * r <= lds_cap + lda * n) {
+    // A sits in LDS just below `lds`: move it to global memory so that the
+    // Jacobi iteration gets the whole arena
+    double* src = A;
+    for (int64_t e = tid; e < lda * n; e += NT) a_spill[e] = src[e];
+    __syncthreads();
+    A = a_spill;
+    lds = src;
+    lds_cap += (int)(lda * n);
+  }
   double* G = ((int64_t)ldg * r <= lds_cap) ? lds : gws;
   for (int e = tid; e < n * r; e += NT) {
     const int q = e % n, i = e / n;
-    G[q + i * ldg] = (i <= q) ? A[i + (int64_t)pos[q] * lda] : 0.0;
+    G[q + i * ldg] = (i <= q) ? A[i * si + (int64_t)pos[q] * sc] : 0.0;
   }
   __syncthreads();
-  wg_jacobi(G, n, r, ldg, S);
-  for (int l = tid; l < r; l += NT) {
-    double sq = 0.0;
-    for (int q = 0; q < n; ++q) sq += G[q + l * ldg] * G[q + l * ldg];
-    S.sig[l] = sqrt(sq);
+  // Explicit flushes with r well below n: QR of R^T = Q2 [R2; 0] first, and
+  // the Jacobi iteration on the r x r factor R2 (R2 J = X Sigma, so that
+  // R^T J = Q2 [X; 0] Sigma): the same rotations (R2 has the Gram matrix of
+  // R^T), on r rows instead of n.
+  const int ldm = (int)odd_ld(r);
+  const bool precond = (by_rows || a_spill) && n >= 2 * r && r >= 8 && (int64_t)ldm * r + odd_ld(n) <= lds_cap;
+  double* M = lds;
+  double* Gq = G;
+  if (precond) {
+    wg_qr(G, n, r, ldg, S.tau_g, S);
+    if (G != gws) {
+      // R2 and the reflectors to global memory: LDS is for the r x r iteration
+      for (int e = tid; e < ldg * r; e += NT) gws[e] = G[e];
+      __syncthreads();
+      Gq = gws;
+    }
+    for (int e = tid; e < r * r; e += NT) {
+      const int i = e % r, j = e / r;
+      M[i + j * ldm] = (i <= j) ? Gq[i + (int64_t)j * ldg] : 0.0;
+    }
+    __syncthreads();
+    wg_jacobi(M, r, r, ldm, S);
+    for (int l = tid; l < r; l += NT) {
+      double sq = 0.0;
+      for (int q = 0; q < r; ++q) sq += M[q + l * ldm] * M[q + l * ldm];
+      S.sig[l] = sqrt(sq);
+    }
+  } else {
+    wg_jacobi(G, n, r, ldg, S);
+    for (int l = tid; l < r; l += NT) {
+      double sq = 0.0;
+      for (int q = 0; q < n; ++q) sq += G[q + l * ldg] * G[q + l * ldg];
+      S.sig[l] = sqrt(sq);
+    }
   }
   __syncthreads();
   for (int l = tid; l < r; l += NT) {
@@ -1166,22 +1375,57 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
     V[c + l * ldv] = 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < n * k; e += NT) {
-    const int q = e % n, l = e / n;
-    const int o = S.ord[l];
-    V[pos[q] + l * ldv] = G[q + o * ldg] / S.sig[o];
-  }
-  // U(i, l) = (R G(:, o_l))_i / sigma_l for i < r, zero below
-  for (int64_t e = tid; e < mU * k; e += NT) {
-    const int64_t i = e % mU;
-    const int l = (int)(e / mU);
-    double acc = 0.0;
-    if (i < r) {
-      const int o = S.ord[l];
-      for (int q = (int)i; q < n; ++q) acc += A[i + (int64_t)pos[q] * lda] * G[q + o * ldg];
-      acc /= S.sig[o];
+  if (precond) {
+    // V(pos[q], l) = (Q2 [X(:, o_l); 0])(q), in column chunks staged in LDS
+    const int ldb = (int)odd_ld(n);
+    double* Bc = M + (int64_t)ldm * r;
+    int kc = (lds_cap - ldm * r) / ldb;
+    if (kc > k) kc = k;
+    for (int l0 = 0; l0 < k; l0 += kc) {
+      const int nb = (k - l0 < kc) ? k - l0 : kc;
+      for (int e = tid; e < n * nb; e += NT) {
+        const int q = e % n, l = e / n;
+        const int o = S.ord[l0 + l];
+        Bc[q + l * ldb] = (q < r) ? M[q + o * ldm] / S.sig[o] : 0.0;
+      }
+      __syncthreads();
+      wg_apply_q(Gq, n, r, ldg, S.tau_g, Bc, nb, ldb, S);
+      for (int e = tid; e < n * nb; e += NT) {
+        const int q = e % n, l = e / n;
+        V[pos[q] + (int64_t)(l0 + l) * ldv] = Bc[q + l * ldb];
+      }
+      __syncthreads();
     }
-    U[i + l * ldu] = acc;
+    // U(:, l) = R W(:, l) = R2^T X(:, o_l), zero below row r
+    for (int64_t e = tid; e < mU * k; e += NT) {
+      const int64_t i = e % mU;
+      const int l = (int)(e / mU);
+      double acc = 0.0;
+      if (i < r) {
+        const int o = S.ord[l];
+        for (int j = 0; j <= (int)i; ++j) acc += Gq[j + i * ldg] * M[j + o * ldm];
+        acc /= S.sig[o];
+      }
+      U[i + l * ldu] = acc;
+    }
+  } else {
+    for (int e = tid; e < n * k; e += NT) {
+      const int q = e % n, l = e / n;
+      const int o = S.ord[l];
+      V[pos[q] + l * ldv] = G[q + o * ldg] / S.sig[o];
+    }
+    // U(i, l) = (R G(:, o_l))_i / sigma_l for i < r, zero below
+    for (int64_t e = tid; e < mU * k; e += NT) {
+      const int64_t i = e % mU;
+      const int l = (int)(e / mU);
+      double acc = 0.0;
+      if (i < r) {
+        const int o = S.ord[l];
+        for (int q = (int)i; q < n; ++q) acc += A[i * si + (int64_t)pos[q] * sc] * G[q + o * ldg];
+        acc /= S.sig[o];
+      }
+      U[i + l * ldu] = acc;
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -1189,7 +1433,20 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
     for (int j = 0; j < r; ++j) f += 4.0 * (double)(m - j) * k;
     S.flops += f;
   }
-  wg_apply_q(A, m, r, lda, S.tau_p, U, k, ldu, S, pos);
+  if (by_rows) {
+    // reflector j lies in column pos[j] below row j: gather the reflectors
+    // into columns (LDS when they fit; G is no longer needed)
+    const int64_t ldr = odd_ld(m);
+    double* Vr = (ldr * r <= lds_cap) ? lds : gws;
+    for (int e = tid; e < m * r; e += NT) {
+      const int i = e % m, j = e / m;
+      Vr[i + j * ldr] = (i > j) ? A[(int64_t)i * lda + pos[j]] : 0.0;
+    }
+    __syncthreads();
+    wg_apply_q(Vr, m, r, ldr, S.tau_p, U, k, ldu, S);
+  } else {
+    wg_apply_q(A, m, r, lda, S.tau_p, U, k, ldu, S, pos);
+  }
   if (timed && tid == 0) S.ph[2] += clk() - c0;
   return k;
 }
@@ -1805,6 +2062,18 @@ __device__ __forceinline__ void tile_store(const Tile& T, double* dst, int64_t l
     }
 }
 
+// tile_store into a matrix stored by rows: entry (i, j) at dst[j + i ld].
+__device__ __forceinline__ void tile_store_t(const Tile& T, double* dst, int64_t ld, int tm, int tn) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * w + mrow(lane, q), j = 16 * c + (lane & 15);
+      if (i < tm && j < tn) dst[j + (int64_t)i * ld] = T.acc[c][q];
+    }
+}
+
 // Tile += sign X Y^T over tile rows [i0, i1) and columns [j0, j1): row i uses
 // X row xr + (i - i0), column j uses Y row yr + (j - j0), r columns each.
 // Entries outside the rectangle are left exactly as they are (their products
@@ -1829,16 +2098,25 @@ __device__ __forceinline__ void tile_xyT(Tile& T, double sign, const double* X, 
   }
   const bool cact[4] = {16 * 0 < j1 && 16 * 0 + 16 > j0, 16 * 1 < j1 && 16 * 1 + 16 > j0,
                         16 * 2 < j1 && 16 * 2 + 16 > j0, 16 * 3 < j1 && 16 * 3 + 16 > j0};
-  for (int k0 = 0; k0 < r; k0 += 4) {
-    const int k = k0 + kl;
-    const bool kin = k < r;
-    const double a = (kin && rowin) ? sign * xp[(int64_t)k * ldx] : 0.0;
+  // four steps (16 columns of the factors) at a time, every operand load
+  // issued before the first product; columns past r load as zero
+  for (int k0 = 0; k0 < r; k0 += 16) {
+    const int ns = (r - k0 + 3) >> 2;          // steps with at least one column (wave-uniform)
+    double a[4], bv[4][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (!cact[c]) continue;
-      const double bv = (kin && colin[c]) ? yp[c][(int64_t)k * ldy] : 0.0;
-      T.acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, T.acc[c], 0, 0, 0);
+    for (int s = 0; s < 4; ++s) {
+      const int64_t k = k0 + 4 * s + kl;
+      const bool kin = k < r;
+      a[s] = (kin && rowin) ? sign * xp[k * ldx] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[s][c] = (kin && cact[c] && colin[c]) ? yp[c][k * ldy] : 0.0;
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (s < ns)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (cact[c]) T.acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bv[s][c], T.acc[c], 0, 0, 0);
   }
 }
 
@@ -1874,16 +2152,23 @@ __device__ __forceinline__ void tile_xyT_f32(Tile& T, double sign, const double*
   fvec4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = fvec4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = 0; k0 < r; k0 += 4) {
-    const int k = k0 + kl;
-    const bool kin = k < r;
-    const float a = (kin && rowin) ? (float)xp[(int64_t)k * ldx] : 0.0f;
+  for (int k0 = 0; k0 < r; k0 += 16) {
+    const int ns = (r - k0 + 3) >> 2;
+    float a[4], bv[4][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      if (!cact[c]) continue;
-      const float bv = (kin && colin[c]) ? (float)yp[c][(int64_t)k * ldy] : 0.0f;
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[c], 0, 0, 0);
+    for (int s = 0; s < 4; ++s) {
+      const int64_t k = k0 + 4 * s + kl;
+      const bool kin = k < r;
+      a[s] = (kin && rowin) ? (float)xp[k * ldx] : 0.0f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[s][c] = (kin && cact[c] && colin[c]) ? (float)yp[c][k * ldy] : 0.0f;
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      if (s < ns)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (cact[c]) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[s][c], acc[c], 0, 0, 0);
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c)
@@ -2000,7 +2285,8 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
   const int k0 = D.rank[b];
   const int64_t c0 = (tid == 0) ? clk() : 0;
   const bool small = (int64_t)(m | 1) * n <= LDS_FACTOR;   // the explicit block fits in LDS
-  const int lda = small ? (m | 1) : m;
+  // in LDS by columns; else in the slot by rows (row length n)
+  const int lda = small ? (m | 1) : n;
   double* A = small ? lds : slot;
   for (int tj0 = 0; tj0 < n; tj0 += LEAF_MAX) {
     for (int ti0 = 0; ti0 < m; ti0 += LEAF_MAX) {
@@ -2013,7 +2299,8 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
         else tile_xyT(T, 1.0, U, m, ti0, V, n, tj0, k0, 0, tm, 0, tn);
       }
       apply_terms(D, tk, ti0, tj0, tm, tn, T, S);
-      tile_store(T, A + ti0 + (int64_t)tj0 * lda, lda, tm, tn);
+      if (small) tile_store(T, A + ti0 + (int64_t)tj0 * lda, lda, tm, tn);
+      else tile_store_t(T, A + tj0 + (int64_t)ti0 * lda, lda, tm, tn);
     }
   }
   __syncthreads();
@@ -2025,8 +2312,9 @@ __device__ int lr_dense_flush(const DevData& D, const Task& tk, double* slot, do
   // R^T of the pivoted QR: after the block in LDS, else from the start of LDS
   double* glds = small ? lds + lda * n : lds;
   const int gcap = small ? LDS_FACTOR - lda * n : LDS_FACTOR;
-  double* gws = slot + (small ? 0 : (int64_t)m * n);
-  const int k = wg_svd_explicit(D, A, m, n, lda, U, m, m, V, n, n, gws, glds, gcap, S, true);
+  double* gws = slot + (small ? (int64_t)lda * n : (int64_t)m * n);
+  const int k = wg_svd_explicit(D, A, m, n, lda, U, m, m, V, n, n, gws, glds, gcap, S, true, small ? slot : nullptr,
+                                !small);
   if (tid == 0) D.rank[b] = k;
   __syncthreads();
   if (D.mixed) {
@@ -2402,6 +2690,18 @@ __global__ void __launch_bounds__(NT) k_dense_matvec(DevData D) {
     if (q < D.r) D.Y[i + q * D.n] = acc[q];
 }
 
+// out(a, b) = C(i0 + a, j0 + b) of the exact covariance (eq. 2 plus the nugget
+// on the diagonal) in input order: iperm maps an input index to its position
+// in the tree order of the coordinates.
+__global__ void __launch_bounds__(NT) k_exact_block(DevData D, const int64_t* iperm, int64_t i0, int64_t ni,
+                                                    int64_t j0, int64_t nj, double* out, int64_t ldo) {
+  const int64_t total = ni * nj;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int64_t a = e % ni, b = e / ni;
+    out[a + b * ldo] = entry(D, iperm[i0 + a], iperm[j0 + b]);
+  }
+}
+
 // R = Z - Y and per-work-group partial sums of R^2 and Z^2 per column, each
 // work-group over a contiguous range of rows, in a fixed order.
 __global__ void __launch_bounds__(NT) k_refine_resid(const double* Z, const double* Y, double* R, int64_t n, int r,
@@ -2640,6 +2940,16 @@ hipError_t launch_apply(const DevData& D, int mode, const int32_t* chunks, int32
                         hipStream_t st) {
   const int g = nchunks < max_grid ? nchunks : max_grid;
   if (g > 0) hipLaunchKernelGGL(k_apply, dim3(g), dim3(NT), 0, st, D, mode, chunks, nchunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_block(const DevData& D, const int64_t* iperm, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                              double* out, int64_t ldo, hipStream_t st) {
+  const int64_t total = ni * nj;
+  if (total <= 0) return hipSuccess;
+  int64_t g = (total + NT - 1) / NT;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_exact_block, dim3((unsigned)g), dim3(NT), 0, st, D, iperm, i0, ni, j0, nj, out, ldo);
   return hipGetLastError();
 }
 

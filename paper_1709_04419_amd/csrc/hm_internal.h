@@ -68,6 +68,7 @@ struct hm_dataset {
   hm::Task* d_btasks = nullptr;
   int32_t* d_chunks = nullptr;
   double* d_op = nullptr;
+  int64_t* d_iperm = nullptr;         // input index -> tree position (hm_exact_block, first use)
   // copy of the assembled matrix C~ (dense pool, low-rank pool, ranks), made by
   // every assembly while keep_c is set
   bool keep_c = false;

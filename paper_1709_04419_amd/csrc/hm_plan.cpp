@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <set>
 #include <stdexcept>
 
 namespace hm {
@@ -855,6 +856,86 @@ void build_plan(const Tree& t, Plan& p) {
   Planner pl(t, p);
   pl.run();
   validate(t, p);
+}
+
+}  // namespace hm
+
+namespace hm {
+
+// Greedy level building.  tail(t) is the longest chain of measured durations
+// from t to the end of the factorisation (t included).  Each level starts from
+// the ready task of longest tail, t*, and takes delta = its duration; every
+// ready task whose tail exceeds tail(t*) - delta must run now (deferring it by
+// one level would lengthen the schedule), and delta grows to the longest of
+// those; every other ready task of duration at most delta runs now as well,
+// for free.  Longer, non-critical tasks wait for a level of their own length.
+void schedule_by_durations(const Plan& p, const std::vector<double>& dur, std::vector<int32_t>& order,
+                           std::vector<int32_t>& level_begin) {
+  const int32_t nt = (int32_t)p.tasks.size();
+  if ((int32_t)dur.size() != nt) throw std::logic_error("one duration per task");
+  std::vector<int32_t> sbeg(nt + 1, 0), succ(p.deps.size());
+  for (int32_t t = 0; t < nt; ++t)
+    for (int32_t q = 0; q < p.tasks[t].ndeps; ++q) ++sbeg[p.deps[p.tasks[t].dep_begin + q] + 1];
+  for (int32_t t = 0; t < nt; ++t) sbeg[t + 1] += sbeg[t];
+  {
+    std::vector<int32_t> fill(sbeg.begin(), sbeg.end() - 1);
+    for (int32_t t = 0; t < nt; ++t)
+      for (int32_t q = 0; q < p.tasks[t].ndeps; ++q) succ[fill[p.deps[p.tasks[t].dep_begin + q]]++] = t;
+  }
+  // dependencies precede their tasks in plan order, so one backward sweep
+  std::vector<double> tail(nt, 0.0);
+  for (int32_t t = nt - 1; t >= 0; --t) {
+    double m = 0.0;
+    for (int32_t q = sbeg[t]; q < sbeg[t + 1]; ++q) m = std::max(m, tail[succ[q]]);
+    tail[t] = m + std::max(0.0, dur[t]);
+  }
+  std::vector<int32_t> need(nt);
+  std::set<std::pair<double, int32_t>> by_dur, by_tail;
+  for (int32_t t = 0; t < nt; ++t) {
+    need[t] = p.tasks[t].ndeps;
+    if (!need[t]) {
+      by_dur.insert({dur[t], t});
+      by_tail.insert({tail[t], t});
+    }
+  }
+  order.clear();
+  order.reserve(nt);
+  level_begin.assign(1, 0);
+  std::vector<int32_t> cur;
+  while ((int32_t)order.size() < nt) {
+    if (by_tail.empty()) throw std::logic_error("schedule: no ready task (dependency cycle)");
+    cur.clear();
+    const double tmax = by_tail.rbegin()->first;
+    double delta = dur[by_tail.rbegin()->second];
+    for (bool grew = true; grew;) {
+      grew = false;
+      for (auto it = by_tail.rbegin(); it != by_tail.rend() && it->first > tmax - delta; ++it)
+        if (dur[it->second] > delta) {
+          delta = dur[it->second];
+          grew = true;
+        }
+    }
+    for (auto it = by_tail.rbegin(); it != by_tail.rend() && it->first > tmax - delta; ++it) cur.push_back(it->second);
+    for (auto it = by_dur.begin(); it != by_dur.end() && it->first <= delta; ++it) cur.push_back(it->second);
+    std::sort(cur.begin(), cur.end());
+    cur.erase(std::unique(cur.begin(), cur.end()), cur.end());
+    for (int32_t t : cur) {
+      by_dur.erase({dur[t], t});
+      by_tail.erase({tail[t], t});
+    }
+    // longer tasks first: the level's work-groups take them round-robin
+    std::stable_sort(cur.begin(), cur.end(), [&](int32_t a, int32_t b) { return dur[a] > dur[b]; });
+    for (int32_t t : cur) order.push_back(t);
+    level_begin.push_back((int32_t)order.size());
+    for (int32_t t : cur)
+      for (int32_t q = sbeg[t]; q < sbeg[t + 1]; ++q) {
+        const int32_t s2 = succ[q];
+        if (--need[s2] == 0) {
+          by_dur.insert({dur[s2], s2});
+          by_tail.insert({tail[s2], s2});
+        }
+      }
+  }
 }
 
 }  // namespace hm

@@ -203,5 +203,11 @@ struct Plan {
 void build_tree(const double* coords, int64_t n, int32_t leaf_size, double eta, Tree& t);
 // Symbolic H-Cholesky: terms, instances, tasks, dependencies, solve programs.
 void build_plan(const Tree& t, Plan& p);
+// Level schedule of the factorisation tasks from measured durations (seconds
+// or any unit): order = task ids level by level, level_begin[l] .. [l + 1] the
+// tasks of level l, every dependency in an earlier level, and within a level
+// the longer tasks first.
+void schedule_by_durations(const Plan& p, const std::vector<double>& dur, std::vector<int32_t>& order,
+                           std::vector<int32_t>& level_begin);
 
 }  // namespace hm

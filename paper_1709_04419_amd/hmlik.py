@@ -98,6 +98,7 @@ _sig = {
     "hm_apply": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, C.c_int32]),
     "hm_simulate": (C.c_int, [_P, C.POINTER(hm_theta), C.POINTER(hm_approx), _P, _P, C.c_int32, C.c_int32]),
     "hm_inverse_accuracy": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_double)]),
+    "hm_exact_block": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, C.c_int64, _P, C.c_int64, C.c_int32]),
     "hm_dataset_footprint": (C.c_int, [_P, _P, _P, _P]),
     "hm_dataset_release": (C.c_int, [_P]),
     "hm_server_create": (C.c_int, [_P, C.POINTER(hm_server_opts), C.POINTER(_P)]),
@@ -343,6 +344,19 @@ class Dataset:
         out = C.c_double()
         _check(_lib.hm_inverse_accuracy(self._h, _ptr(x), int(iters), C.byref(out)), "hm_inverse_accuracy")
         return out.value
+
+    def exact_block(self, i0: int, ni: int, j0: int, nj: int, device: bool = False):
+        """hm_exact_block: C(i0:i0+ni, j0:j0+nj) of the exact covariance at the
+        last assembled theta, input order; a numpy array, or with device=True a
+        float64 torch tensor on the context's GPU (column-major storage)."""
+        if device:
+            import torch
+            buf = torch.empty((nj, ni), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+            _check(_lib.hm_exact_block(self._h, i0, ni, j0, nj, _ptr(buf), max(ni, 1), 1), "hm_exact_block")
+            return buf.t()
+        out = np.empty((ni, nj), dtype=np.float64, order="F")
+        _check(_lib.hm_exact_block(self._h, i0, ni, j0, nj, _ptr(out), max(ni, 1), 0), "hm_exact_block")
+        return out
 
     def export_tree(self):
         inf = self.info()

@@ -113,22 +113,55 @@ def _theta(x) -> tuple:
     return tuple(float(v) for v in th)
 
 
-def fit(ds, theta0, nugget: float, eps: float = 1e-7, rank: int = 0, **kw) -> dict:
+def _point(x, nugget, fit_nugget):
+    """(theta, nugget) at the search point x: x = log(theta), or with a fitted
+    nugget x = (log theta, log tau^2); None where the library would reject it."""
+    th = _theta(x[:3])
+    if th is None:
+        return None
+    if not fit_nugget:
+        return th, nugget
+    tau2 = float(np.exp(x[3]))
+    if not (math.isfinite(tau2) and tau2 > 0.0):
+        return None
+    return th, tau2
+
+
+def _start(theta0, nugget, fit_nugget):
+    x0 = list(np.log(np.asarray(theta0, dtype=np.float64)))
+    if fit_nugget:
+        x0.append(math.log(nugget))
+    return np.asarray(x0)
+
+
+def _estimate(r, nugget, fit_nugget) -> dict:
+    x = np.asarray(r["x"])
+    return dict(theta=tuple(float(v) for v in np.exp(x[:3])),
+                nugget=float(np.exp(x[3])) if fit_nugget else nugget,
+                loglik=-r["f"], evals=r["evals"], converged=r["converged"])
+
+
+def fit(ds, theta0, nugget: float, eps: float = 1e-7, rank: int = 0, fit_nugget: bool = False,
+        loglik_kw: dict = None, **kw) -> dict:
     """Maximum-likelihood estimate of theta for one hmlik.Dataset (with Z set);
-    returns dict(theta, loglik, evals, converged)."""
-    gen = nelder_mead(np.log(np.asarray(theta0, dtype=np.float64)), **kw)
+    returns dict(theta, nugget, loglik, evals, converged).  With fit_nugget the
+    nugget tau^2 is a fourth parameter, searched on log tau^2 from `nugget`
+    (the paper treats it as fixed; its Section 6 names the extension).
+    loglik_kw goes to Dataset.loglik (e.g. prec, refine_max_iter, refine_tol)."""
+    lk = loglik_kw or {}
+    gen = nelder_mead(_start(theta0, nugget, fit_nugget), **kw)
     x = next(gen)
     try:
         while True:
-            th = _theta(x)
-            x = gen.send(math.inf if th is None else _objective(ds.loglik(th, nugget, eps, rank)))
+            pt = _point(x, nugget, fit_nugget)
+            x = gen.send(math.inf if pt is None else _objective(ds.loglik(pt[0], pt[1], eps, rank, **lk)))
     except StopIteration as stop:
         r = stop.value
-    return dict(theta=tuple(np.exp(r["x"])), loglik=-r["f"], evals=r["evals"], converged=r["converged"])
+    return _estimate(r, nugget, fit_nugget)
 
 
 def fit_many(server, datasets: List, theta0s, nugget: float,
-             eps: float = 1e-7, rank: int = 0, **kw) -> List[dict]:
+             eps: float = 1e-7, rank: int = 0, fit_nugget: bool = False, **kw) -> List[dict]:
     """One search per hmlik.Dataset, advanced together through an
     hmlik.Server (give it a slot per dataset): each round submits the
     pending point of every unfinished search to the server and feeds back the
@@ -136,16 +169,16 @@ def fit_many(server, datasets: List, theta0s, nugget: float,
     estimates equal those of separate `fit` calls."""
     gens, pending, out = [], [], [None] * len(datasets)
     for th in theta0s:
-        g = nelder_mead(np.log(np.asarray(th, dtype=np.float64)), **kw)
+        g = nelder_mead(_start(th, nugget, fit_nugget), **kw)
         gens.append(g)
         pending.append(next(g))
     live = list(range(len(datasets)))
     while live:
         tickets = {}
         for i in live:
-            th = _theta(pending[i])
-            if th is not None:
-                tickets[i] = server.submit(datasets[i], th, nugget, eps, rank)
+            pt = _point(pending[i], nugget, fit_nugget)
+            if pt is not None:
+                tickets[i] = server.submit(datasets[i], pt[0], pt[1], eps, rank)
         still = []
         for i in live:
             f = _objective(server.poll(tickets[i], wait=True)) if i in tickets else math.inf
@@ -153,8 +186,6 @@ def fit_many(server, datasets: List, theta0s, nugget: float,
                 pending[i] = gens[i].send(f)
                 still.append(i)
             except StopIteration as stop:
-                r = stop.value
-                out[i] = dict(theta=tuple(np.exp(r["x"])), loglik=-r["f"], evals=r["evals"],
-                              converged=r["converged"])
+                out[i] = _estimate(stop.value, nugget, fit_nugget)
         live = still
     return out

@@ -80,6 +80,7 @@ def test_null_handles_are_argument_errors():
     out = ctypes.c_void_p()
     opts = hmlik.hm_tree_opts(64, 2.0)
     assert lib.hm_dataset_create(None, z, 2, 2, ctypes.byref(opts), 0, ctypes.byref(out)) == hmlik.HM_ERR_ARG
+    assert lib.hm_exact_block(None, 0, 1, 0, 1, z, 1, 0) == hmlik.HM_ERR_ARG
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

@@ -60,3 +60,25 @@ def test_fit_many_equals_separate_fits():
             assert a["theta"] == b["theta"] and a["loglik"] == b["loglik"] and a["evals"] == b["evals"]
     finally:
         ctx.close()
+
+
+def test_mle_fitted_nugget_matches_dense_oracle():
+    # the nugget as a fourth parameter: the same search on the dense likelihood
+    # (eq. 1) with tau^2 free, data drawn with a nugget of 0.05
+    from paper_1709_04419_amd import hmlik, mle
+    n, tau2 = 300, 0.05
+    P = wl.uniform_square(n, 53)
+    Z = dense_factor(P, THETA_TRUE, tau2) @ wl.standard_normal(n, 1, 54)
+    ref = mle.minimise(lambda x: -float(dense_loglik(P, Z, tuple(np.exp(x[:3])), float(np.exp(x[3])))[0][0]),
+                       np.log(list(THETA0) + [0.1]), **KW)
+    ctx = hmlik.Context(0)
+    try:
+        ds = hmlik.Dataset(ctx, P, 32, 2.0)
+        ds.set_z(Z)
+        g = mle.fit(ds, THETA0, 0.1, eps=1e-10, fit_nugget=True, **KW)
+    finally:
+        ctx.close()
+    assert g["converged"] and ref["f"] < np.inf
+    l_at_g = float(dense_loglik(P, Z, g["theta"], g["nugget"])[0][0])
+    assert abs(l_at_g - (-ref["f"])) <= 1e-6 * abs(ref["f"])
+    np.testing.assert_allclose(list(g["theta"]) + [g["nugget"]], np.exp(ref["x"]), rtol=5e-2)

@@ -48,3 +48,16 @@ def test_generator_counts_evaluations():
         r = stop.value
     assert r["evals"] == n
     assert n <= 25 + 2          # a shrink may overrun the budget by at most d - 1 points
+
+
+def test_fitted_nugget_point_mapping():
+    from paper_1709_04419_amd.mle import _point, _start
+    x = _start((1.0, 0.1, 0.5), 0.05, True)
+    assert x.shape == (4,)
+    th, tau2 = _point(x, 0.05, True)
+    np.testing.assert_allclose(th, (1.0, 0.1, 0.5), rtol=1e-15)
+    assert abs(tau2 - 0.05) <= 1e-16
+    # a fixed nugget passes through; nu above 50 or an overflowing nugget is rejected
+    assert _point(_start((1.0, 0.1, 0.5), 0.05, False), 0.05, False)[1] == 0.05
+    assert _point(np.array([0.0, 0.0, math.log(60.0), 0.0]), 0.0, True) is None
+    assert _point(np.array([0.0, 0.0, 0.0, 1e4]), 0.0, True) is None
