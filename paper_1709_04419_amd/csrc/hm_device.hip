@@ -221,7 +221,19 @@ __global__ void __launch_bounds__(NT) k_assemble_dense(DevData D) {
 
 // ------------------------------------------------------------------ QR / SVD
 
+// Term instances of the current task, resolved (factor pointers, leading
+// dimensions, rank and the instance's rectangle), a chunk at a time in LDS.
+#define TM_CHUNK 24
+struct TermMeta {
+  const double* X;
+  const double* Y;
+  int64_t ldx, ldy, xr0, yr0;
+  int32_t lr0, lc0, mx, ny, r, dd;
+};
+
 struct Smem {
+  TermMeta tm[TM_CHUNK];
+  int32_t tm_begin, tm_n;  // instance range held in tm (tm_begin = -1: none)
   double red[NW];
   int64_t redi[NW];
   double tau_x[2 * K_MAX];
@@ -2178,32 +2190,54 @@ __device__ __forceinline__ void tile_xyT_f32(Tile& T, double sign, const double*
 
 // Subtracts a leaf's restricted update terms, in order, from the tm x tn tile
 // at (ti0, tj0) of the block (FP64 matrix instructions, factors read from
-// global memory).
+// global memory).  The instances are resolved TM_CHUNK at a time into LDS by
+// one thread each (instance, term, rank and factor offsets are a chain of
+// dependent loads), and a chunk stays there for the next tile of the same task.
 __device__ void apply_terms(const DevData& D, const Task& tk, int ti0, int tj0, int tm, int tn, Tile& T, Smem& S) {
   const int tid = threadIdx.x;
-  for (int32_t ii = 0; ii < tk.ninst; ++ii) {
-    const TermInst in = D.insts[tk.inst_begin + ii];
-    // the term's rectangle, clipped to the tile (block coordinates)
-    const int r0 = in.lr0 > ti0 ? in.lr0 : ti0;
-    const int r1 = (in.lr0 + in.mx < ti0 + tm) ? in.lr0 + in.mx : ti0 + tm;
-    const int c0 = in.lc0 > tj0 ? in.lc0 : tj0;
-    const int c1 = (in.lc0 + in.ny < tj0 + tn) ? in.lc0 + in.ny : tj0 + tn;
-    if (r0 >= r1 || c0 >= c1) continue;
-    const TermDef t = D.terms[in.term];
-    const int r = term_rank(D, t);
-    if (r == 0) continue;
-    const double *X, *Y;
-    int64_t ldx, ldy;
-    term_factors(D, t, X, ldx, Y, ldy);
-    if (tid == 0) S.flops += 2.0 * (r1 - r0) * (c1 - c0) * r;
-    // products of dense leaves stay FP64; products with low-rank factors are
-    // FP32 in the mixed form
-    if (D.mixed && t.kind != TK_DD)
-      tile_xyT_f32(T, -1.0, X, ldx, in.xr0 + (r0 - in.lr0), Y, ldy, in.yr0 + (c0 - in.lc0), r, r0 - ti0, r1 - ti0,
-                   c0 - tj0, c1 - tj0);
-    else
-      tile_xyT(T, -1.0, X, ldx, in.xr0 + (r0 - in.lr0), Y, ldy, in.yr0 + (c0 - in.lc0), r, r0 - ti0, r1 - ti0,
-               c0 - tj0, c1 - tj0);
+  for (int32_t c0 = 0; c0 < tk.ninst; c0 += TM_CHUNK) {
+    const int nc = (tk.ninst - c0 < TM_CHUNK) ? tk.ninst - c0 : TM_CHUNK;
+    if (!(S.tm_begin == tk.inst_begin + c0 && S.tm_n == nc)) {
+      __syncthreads();   // the previous chunk's readers are done
+      if (tid < nc) {
+        const TermInst in = D.insts[tk.inst_begin + c0 + tid];
+        const TermDef t = D.terms[in.term];
+        TermMeta mt;
+        term_factors(D, t, mt.X, mt.ldx, mt.Y, mt.ldy);
+        mt.r = term_rank(D, t);
+        mt.dd = t.kind == TK_DD;
+        mt.xr0 = in.xr0;
+        mt.yr0 = in.yr0;
+        mt.lr0 = in.lr0;
+        mt.lc0 = in.lc0;
+        mt.mx = in.mx;
+        mt.ny = in.ny;
+        S.tm[tid] = mt;
+      }
+      if (tid == 0) {
+        S.tm_begin = tk.inst_begin + c0;
+        S.tm_n = nc;
+      }
+      __syncthreads();
+    }
+    for (int q = 0; q < nc; ++q) {
+      const TermMeta& mt = S.tm[q];
+      // the term's rectangle, clipped to the tile (block coordinates)
+      const int r0 = mt.lr0 > ti0 ? mt.lr0 : ti0;
+      const int r1 = (mt.lr0 + mt.mx < ti0 + tm) ? mt.lr0 + mt.mx : ti0 + tm;
+      const int cc0 = mt.lc0 > tj0 ? mt.lc0 : tj0;
+      const int cc1 = (mt.lc0 + mt.ny < tj0 + tn) ? mt.lc0 + mt.ny : tj0 + tn;
+      if (r0 >= r1 || cc0 >= cc1 || mt.r == 0) continue;
+      if (tid == 0) S.flops += 2.0 * (r1 - r0) * (cc1 - cc0) * mt.r;
+      // products of dense leaves stay FP64; products with low-rank factors are
+      // FP32 in the mixed form
+      if (D.mixed && !mt.dd)
+        tile_xyT_f32(T, -1.0, mt.X, mt.ldx, mt.xr0 + (r0 - mt.lr0), mt.Y, mt.ldy, mt.yr0 + (cc0 - mt.lc0), mt.r,
+                     r0 - ti0, r1 - ti0, cc0 - tj0, cc1 - tj0);
+      else
+        tile_xyT(T, -1.0, mt.X, mt.ldx, mt.xr0 + (r0 - mt.lr0), mt.Y, mt.ldy, mt.yr0 + (cc0 - mt.lc0), mt.r,
+                 r0 - ti0, r1 - ti0, cc0 - tj0, cc1 - tj0);
+    }
   }
 }
 
@@ -2491,6 +2525,7 @@ __device__ void task_ts_b(const DevData& D, const Task& tk, double* slot, double
     }
     return;
   }
+  int64_t c0 = (tid == 0) ? clk() : 0;
   const int gx = ts_nblk(bk.m), gy = ts_nblk(bk.n);
   const int64_t mx = (int64_t)gx * p, my = (int64_t)gy * p;
   double* Xs = slot;                     // stacked R factors of the U side (mx x p)
@@ -2513,6 +2548,7 @@ __device__ void task_ts_b(const DevData& D, const Task& tk, double* slot, double
   __syncthreads();
   qr_any(Xs, mx, p, mx, S.tau_x, lds, LDS_FACTOR, S);
   qr_any(Ys, my, p, my, S.tau_y, lds, LDS_FACTOR, S);
+  if (tid == 0) { const int64_t c1 = clk(); S.ph[0] += c1 - c0; c0 = c1; }
   // core M = Rx Ry^T (p x p), in LDS
   const int ldm = (int)odd_ld(p);
   double* M = lds;
@@ -2530,8 +2566,10 @@ __device__ void task_ts_b(const DevData& D, const Task& tk, double* slot, double
   const int k = wg_svd_explicit(D, M, p, p, ldm, Wx, mx, mx, Wy, my, my, work, lds + ldm * p,
                                 LDS_FACTOR - ldm * p, S);
   __syncthreads();
+  if (tid == 0) { const int64_t c1 = clk(); S.ph[1] += c1 - c0; c0 = c1; }
   wg_apply_q(Xs, mx, p, mx, S.tau_x, Wx, k, mx, S);
   wg_apply_q(Ys, my, p, my, S.tau_y, Wy, k, my, S);
+  if (tid == 0) S.ph[2] += clk() - c0;
   if (tid == 0) {
     D.ts_app[2 * b] = k;
     D.ts_app[2 * b + 1] = p;
@@ -2629,10 +2667,22 @@ __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn,
 // among themselves, and all their predecessors belong to earlier levels,
 // completed by earlier launches.  Work-group w takes tasks order[t0 + w],
 // order[t0 + w + gridDim.x], ... of the level; it uses workspace slot w.
+// The term-metadata cache of apply_terms starts empty in every launch (LDS
+// holds no defined value at kernel start); within a launch a task's instance
+// range identifies its chunks (ranges of different tasks are disjoint).
+__device__ __forceinline__ void term_cache_init(Smem& S) {
+  if (threadIdx.x == 0) {
+    S.tm_begin = -1;
+    S.tm_n = 0;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
   double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  term_cache_init(S);
   for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) run_task(D, D.order[q], slot, dyn, S);
 }
 
@@ -2650,6 +2700,7 @@ __global__ void __launch_bounds__(NT) k_level_tasks(DevData D, const Task* tasks
   extern __shared__ double dyn[];
   __shared__ Smem S;
   double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  term_cache_init(S);
   for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) {
     const Task tk = tasks[q];
     dispatch(D, tk, -1, slot, dyn, S);
