@@ -129,6 +129,21 @@ print(json.dumps(out))
                       f"({t2:.2f} s); value at n={n_full} extrapolated by the measured growth t ~ n^{alpha:.2f}"}
 
 
+def full_size_oracle_seconds(n: int, eps: float) -> dict | None:
+    """The oracle's own time for one full-size evaluation, recorded when the
+    stored full-size values were written (tests/golden/make_fullsize.py, on the
+    machine that ran it, one process): a measured check of the extrapolation."""
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "fullsize.json")) as f:
+            rec = json.load(f).get(f"basin{n // 1000}k_eps{eps:g}".replace("e-0", "e-"))
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("n") != n or "oracle_seconds" not in rec:
+        return None
+    return {"n": n, "seconds": rec["oracle_seconds"], "evals_per_s": 1.0 / rec["oracle_seconds"],
+            "measured_by": "tests/golden/make_fullsize.py (build host, one process)"}
+
+
 def oracle_error(n: int, eps: float, r) -> dict | None:
     """Relative differences to the oracle's FP64 values for this workload,
     stored by tests/golden/make_fullsize.py (None when there are none)."""
@@ -145,9 +160,11 @@ def oracle_error(n: int, eps: float, r) -> dict | None:
     return out
 
 
-def traffic_per_launch(n: int):
-    """HBM bytes per k_level launch from the committed counter summary, or None
-    when there is none for this workload or the kernel source has changed."""
+def traffic_per_launch(n: int, launches: int):
+    """HBM bytes per k_level launch: the committed counter summary's bytes per
+    factorisation (calibrated FETCH_SIZE + WRITE_SIZE summed over its
+    dispatches) over this schedule's launches; None when there is no summary
+    for this workload or the kernel source has changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -155,9 +172,9 @@ def traffic_per_launch(n: int):
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha or rec.get("n") != n:
+    if rec.get("kernel_source_sha256") != sha or rec.get("n") != n or "hbm_bytes_per_factorisation" not in rec:
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec["hbm_bytes_per_factorisation"] / launches
 
 
 def main():
@@ -229,7 +246,7 @@ def main():
     warm = min(args.warmup, 1)
     if not args.no_tune:
         s = time.perf_counter()
-        ds.tune_schedule(THETA, NUGGET, eps, 0)
+        ds.tune_schedule(THETA, NUGGET, eps, 0, prec=pk.get("prec", hmlik.HM_FP64))
         t_tune = time.perf_counter() - s
         warm = 1
         log(f"warm-up: schedule tuned from one timed evaluation, {t_tune:.2f} s")
@@ -270,7 +287,7 @@ def main():
         del src, dst
 
     flops = ds.factor_flops()
-    launches = info["nlevels"]
+    launches = ds.info()["nlevels"]      # after tuning: the schedule the steps ran
     t_fac = float(np.mean(fac))
     avg_launch = t_fac / launches
     achieved = flops / launches / avg_launch / 1e12
@@ -297,8 +314,9 @@ def main():
                                  f"recompression, refinement of C~^-1 Z (at most {args.refine_max_iter} steps, "
                                  f"tol {args.refine_tol:g})") if mixed else "fp64",
                    "blocks": info["nblocks"], "tasks": info["ntasks"], "levels": launches,
+                   "levels_longest_path": info["nlevels"],
                    "schedule": "longest-path levels" if args.no_tune else
-                               "levels re-balanced from one timed evaluation (untimed, before the steps)"},
+                               "levels rebuilt from one timed evaluation (untimed, before the steps)"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "phases_ms": {"assemble": float(np.mean(asm)) * 1e3, "factor": t_fac * 1e3,
                       "solve": float(np.mean(sol)) * 1e3, "dataset_setup_host": t_setup * 1e3,
@@ -311,14 +329,30 @@ def main():
         "bytes_C": int(r["bytes_C"][0]), "bytes_L": int(r["bytes_L"][0]), "max_rank": int(r["max_rank"][0]),
         "vs_oracle": oracle_error(n, eps, r),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_per_launch(n),
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_per_launch(n, launches),
                      "kernel": "k_level (H-Cholesky task executor, one launch per dependency level)",
                      "launches": launches, "avg_launch_ms": avg_launch * 1e3,
                      "flops_per_launch": flops / launches},
     }
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
-        out["cpu_baseline"] = cpu_baseline(n, eps)
+        cb = cpu_baseline(n, eps)
+        # the device on the largest sample (same points, Z, theta, eps): a
+        # like-for-like ratio beside the extrapolated full-size value
+        n_s = cb["measured"][-1]["n"]
+        ds_s = hmlik.Dataset(ctx, wl.basin_clusters(n_s, 31), LEAF, ETA)
+        ds_s.set_z(wl.standard_normal(n_s, 1, 32))
+        ds_s.loglik(THETA, NUGGET, eps, 0, **pk)
+        s = time.perf_counter()
+        ds_s.loglik(THETA, NUGGET, eps, 0, **pk)
+        t_dev = time.perf_counter() - s
+        ds_s.close()
+        cb["device_same_n"] = {"n": n_s, "seconds": t_dev,
+                               "oracle_over_device": cb["measured"][-1]["seconds"] / t_dev}
+        ref = full_size_oracle_seconds(n, eps)
+        if ref is not None:
+            cb["full_size_reference"] = ref
+        out["cpu_baseline"] = cb
     ds.close()
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -417,6 +417,10 @@ void hm_dataset_destroy(hm_dataset* ds) {
   if (ds->store) (void)hipFree(ds->store);
   for (int i = 0; i < 4; ++i)
     if (ds->ev[i]) (void)hipEventDestroy(ds->ev[i]);
+  for (hipEvent_t e : ds->mev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t x : ds->xs)
+    if (x) (void)hipStreamDestroy(x);
   ds->ctx->datasets.erase(ds);
   delete ds;
 }
@@ -682,6 +686,46 @@ static hm_status finish_factor(hm_dataset* ds) {
   return decode_factor_status(ds, key);
 }
 
+// Work-groups and workspace slots of each stream of the stream program
+// (disjoint slot ranges within the context's NSLOTS).
+static const int32_t MS_GRID[MS_STREAMS] = {256, 128, 64, 64};
+static const int32_t MS_SLOT_BASE[MS_STREAMS] = {0, 256, 384, 448};
+static_assert(MS_STREAMS == 4 && 448 + 64 <= NSLOTS, "stream slot ranges");
+
+// Issues the factorisation's stream program: the extra streams first wait for
+// the work already on st (the assembly), each launch waits for its events and
+// records its own, and st finally waits for the extra streams' last launches.
+static hipError_t launch_stream_program(hm_dataset* ds, const DevData& D, hipStream_t st) {
+  const StreamProgram& g = ds->ms;
+  hipEvent_t* fork = &ds->mev[g.nevents];
+  DevData Dm = D;
+  Dm.order = ds->d_morder;
+  hipStream_t sx[MS_STREAMS] = {st, ds->xs[0], ds->xs[1], ds->xs[2]};
+  hipError_t e = hipEventRecord(fork[0], st);
+  for (int s = 1; s < MS_STREAMS && e == hipSuccess; ++s) e = hipStreamWaitEvent(sx[s], fork[0], 0);
+  // HMLIK_PROGRESS=<launches>: synchronise every <launches> launches and
+  // report progress on stderr (long factorisations; costs a sync per chunk)
+  size_t chunk = 0;
+  if (const char* v = getenv("HMLIK_PROGRESS")) chunk = (size_t)std::max(1, atoi(v));
+  for (size_t k = 0; k < g.launches.size() && e == hipSuccess; ++k) {
+    if (chunk && k > 0 && k % chunk == 0) {
+      for (int s = 0; s < MS_STREAMS && e == hipSuccess; ++s) e = hipStreamSynchronize(sx[s]);
+      fprintf(stderr, "hmlik factor: launch %zu of %zu (streams)\n", k, g.launches.size());
+    }
+    const MSLaunch& M = g.launches[k];
+    for (int32_t w = 0; w < M.nwait && e == hipSuccess; ++w)
+      e = hipStreamWaitEvent(sx[M.stream], ds->mev[g.waits[M.wait_begin + w]], 0);
+    if (e == hipSuccess)
+      e = launch_factor_range(Dm, M.t0, M.t1, MS_GRID[M.stream], MS_SLOT_BASE[M.stream], sx[M.stream]);
+    if (e == hipSuccess && M.rec >= 0) e = hipEventRecord(ds->mev[M.rec], sx[M.stream]);
+  }
+  for (int s = 1; s < MS_STREAMS && e == hipSuccess; ++s) {
+    e = hipEventRecord(fork[s], sx[s]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, fork[s], 0);
+  }
+  return e;
+}
+
 hm_status hm_factor(hm_dataset* ds) {
   if (!ds || !ds->assembled) return HM_ERR_ARG;
   if (busy(ds->ctx)) return HM_ERR_BUSY;
@@ -690,7 +734,9 @@ hm_status hm_factor(hm_dataset* ds) {
   DevData& D = ds->D;
   hipStream_t st = ds->ctx->stream;
   HIPTRY(hipEventRecord(ds->ev[1], st));
-  {
+  if (ds->ms_valid) {
+    HIPTRY(launch_stream_program(ds, D, st));
+  } else {
     const int32_t nlev = (int32_t)ds->level_begin.size() - 1;
     // HMLIK_PROGRESS=<levels>: synchronise every <levels> levels and report
     // progress on stderr (for long factorisations; costs a sync per chunk)
@@ -914,13 +960,38 @@ hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_appro
   std::vector<double> dur(nt);
   for (int32_t t = 0; t < nt; ++t) dur[t] = (double)(tt[7 * (size_t)t + 1] - tt[7 * (size_t)t]);
   std::vector<int32_t> order, level_begin;
+  StreamProgram prog;
+  const bool multi = !getenv("HMLIK_SINGLE_STREAM");
   try {
     schedule_by_durations(ds->plan, dur, order, level_begin);
+    if (multi) {
+      // timing records are in s_memrealtime ticks (100 MHz): 6 us per launch
+      build_stream_program(ds->tree, ds->plan, dur, 600.0, prog);
+    }
   } catch (const std::exception&) {
     return HM_ERR_INTERNAL;
   }
   ds->level_begin = level_begin;
   ds->order = order;
+  ds->ms_valid = false;
+  if (multi) {
+    if (!ds->d_morder) {
+      void* q = nullptr;
+      TRY(dev_alloc(ds, sizeof(int32_t) * (size_t)nt, &q));
+      ds->d_morder = (int32_t*)q;
+    }
+    HIPTRY(hipMemcpy(ds->d_morder, prog.order.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+    for (int s = 0; s < MS_STREAMS - 1; ++s)
+      if (!ds->xs[s]) HIPTRY(hipStreamCreateWithFlags(&ds->xs[s], hipStreamNonBlocking));
+    const size_t nev = (size_t)prog.nevents + MS_STREAMS;
+    while (ds->mev.size() < nev) {
+      hipEvent_t e = nullptr;
+      HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ds->mev.push_back(e);
+    }
+    ds->ms = std::move(prog);
+    ds->ms_valid = true;
+  }
   HIPTRY(hipMemcpy(ds->d_order, ds->order.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
   return HM_OK;
 }

@@ -107,6 +107,10 @@ hipError_t launch_eval_init(const DevData& D, hipStream_t st);
 // Launches levels [l0, l1) of the task DAG, one kernel per level.
 hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, int32_t l0, int32_t l1, int max_grid,
                                 hipStream_t st);
+// Tasks order[t0 .. t1) of D.order on at most max_grid work-groups that use
+// workspace slots slot_base .. slot_base + max_grid - 1.
+hipError_t launch_factor_range(const DevData& D, int32_t t0, int32_t t1, int max_grid, int32_t slot_base,
+                               hipStream_t st);
 // One level of several datasets' factorisations in one launch: Ds (device
 // array of nseg DevData), seg (device, 2 nseg ints: the level's task range per
 // dataset), total = the number of tasks over all of them.

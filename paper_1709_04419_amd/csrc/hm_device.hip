@@ -2666,7 +2666,9 @@ __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn,
 // Level-synchronous executor: the tasks of one level have no dependencies
 // among themselves, and all their predecessors belong to earlier levels,
 // completed by earlier launches.  Work-group w takes tasks order[t0 + w],
-// order[t0 + w + gridDim.x], ... of the level; it uses workspace slot w.
+// order[t0 + w + gridDim.x], ... of the level; it uses workspace slot
+// slot_base + w (launches that may run at the same time on different streams
+// use disjoint slot ranges).
 // The term-metadata cache of apply_terms starts empty in every launch (LDS
 // holds no defined value at kernel start); within a launch a task's instance
 // range identifies its chunks (ranges of different tasks are disjoint).
@@ -2678,10 +2680,10 @@ __device__ __forceinline__ void term_cache_init(Smem& S) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1) {
+__global__ void __launch_bounds__(NT) k_level(DevData D, int32_t t0, int32_t t1, int32_t slot_base) {
   extern __shared__ double dyn[];
   __shared__ Smem S;
-  double* slot = D.ws + (int64_t)blockIdx.x * D.ws_stride;
+  double* slot = D.ws + (int64_t)(slot_base + blockIdx.x) * D.ws_stride;
   term_cache_init(S);
   for (int32_t q = t0 + blockIdx.x; q < t1; q += gridDim.x) run_task(D, D.order[q], slot, dyn, S);
 }
@@ -2962,8 +2964,22 @@ hipError_t launch_factor_levels(const DevData& D, const int32_t* level_begin, in
   for (int32_t l = l0; l < l1; ++l) {
     const int32_t t0 = level_begin[l], t1 = level_begin[l + 1];
     const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
-    if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1);
+    if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1, 0);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_range(const DevData& D, int32_t t0, int32_t t1, int max_grid, int32_t slot_base,
+                               hipStream_t st) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_level, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_FACTOR * sizeof(double));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int g = (t1 - t0) < max_grid ? (t1 - t0) : max_grid;
+  if (g > 0) hipLaunchKernelGGL(k_level, dim3(g), dim3(NT), LDS_FACTOR * sizeof(double), st, D, t0, t1, slot_base);
   return hipGetLastError();
 }
 

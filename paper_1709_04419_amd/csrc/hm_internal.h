@@ -88,6 +88,13 @@ struct hm_dataset {
   std::vector<int32_t> order;         // execution order (task ids), level by level
   int32_t* d_order = nullptr;
   int64_t* tt_buf = nullptr;          // per-task timing records (allocated on first use)
+  // factorisation on several streams (built by hm_tune_schedule): the program,
+  // its task order on the device, the extra streams and the events
+  bool ms_valid = false;
+  hm::StreamProgram ms;
+  int32_t* d_morder = nullptr;
+  hipStream_t xs[hm::MS_STREAMS - 1] = {};
+  std::vector<hipEvent_t> mev;        // ms.nevents, then MS_STREAMS (fork / join)
 };
 
 namespace hm_int {

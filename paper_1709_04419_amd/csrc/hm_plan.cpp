@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <queue>
 #include <set>
 #include <stdexcept>
 
@@ -935,6 +936,240 @@ void schedule_by_durations(const Plan& p, const std::vector<double>& dur, std::v
           by_tail.insert({tail[s2], s2});
         }
       }
+  }
+}
+
+}  // namespace hm
+
+namespace hm {
+
+// The stream program is built by simulating the execution with the measured
+// durations: a stream of levels (0 and 1) forms its next level, whenever it is
+// free, from the ready tasks of its class by the rule of schedule_by_durations
+// (a level lasts as long as its longest task, or its total work over 256 CUs if
+// that is more); a wave stream takes, whenever it is free, every ready task of
+// its class.  A task counts as finished when its launch ends (the event
+// granularity).  Launches are then issued in order of simulated start.
+void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double ovh,
+                          StreamProgram& out) {
+  const int32_t nt = (int32_t)p.tasks.size();
+  if ((int32_t)dur.size() != nt) throw std::logic_error("one duration per task");
+  std::vector<int8_t> cls(nt, 0);
+  for (int32_t i = 0; i < nt; ++i) {
+    const Task& tk = p.tasks[i];
+    if (tk.kind == TASK_TS_A || tk.kind == TASK_TS_B || tk.kind == TASK_TS_C) {
+      cls[i] = 1;
+    } else if (tk.kind == TASK_LR) {
+      const Block& b = t.bk[tk.obj];
+      if (std::max(b.m, b.n) > MS_LONG_ROWS) cls[i] = 2;
+    }
+  }
+  std::vector<int32_t> sbeg(nt + 1, 0), succ(p.deps.size());
+  for (int32_t i = 0; i < nt; ++i)
+    for (int32_t q = 0; q < p.tasks[i].ndeps; ++q) ++sbeg[p.deps[p.tasks[i].dep_begin + q] + 1];
+  for (int32_t i = 0; i < nt; ++i) sbeg[i + 1] += sbeg[i];
+  {
+    std::vector<int32_t> fill(sbeg.begin(), sbeg.end() - 1);
+    for (int32_t i = 0; i < nt; ++i)
+      for (int32_t q = 0; q < p.tasks[i].ndeps; ++q) succ[fill[p.deps[p.tasks[i].dep_begin + q]]++] = i;
+  }
+  std::vector<double> d(nt), tail(nt, 0.0);
+  for (int32_t i = 0; i < nt; ++i) d[i] = std::max(0.0, dur[i]);
+  for (int32_t i = nt - 1; i >= 0; --i) {
+    double m = 0.0;
+    for (int32_t q = sbeg[i]; q < sbeg[i + 1]; ++q) m = std::max(m, tail[succ[q]]);
+    tail[i] = m + d[i];
+  }
+  struct Sim {
+    int8_t stream;
+    double start, end;
+    std::vector<int32_t> tasks;
+  };
+  std::vector<Sim> sims;
+  std::vector<int32_t> need(nt), launch_of(nt, -1);
+  std::set<std::pair<double, int32_t>> by_dur[2], by_tail[2];
+  std::vector<int32_t> waveq;
+  auto ready = [&](int32_t i) {
+    if (cls[i] == 2) {
+      waveq.push_back(i);
+    } else {
+      by_dur[cls[i]].insert({d[i], i});
+      by_tail[cls[i]].insert({tail[i], i});
+    }
+  };
+  for (int32_t i = 0; i < nt; ++i) {
+    need[i] = p.tasks[i].ndeps;
+    if (!need[i]) ready(i);
+  }
+  using Ev = std::pair<double, int32_t>;   // (end time, launch id)
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> ends;
+  double free_at[MS_STREAMS] = {0, 0, 0, 0};
+  double now = 0.0;
+  int32_t done = 0;
+  while (done < nt) {
+    while (!ends.empty() && ends.top().first <= now) {
+      const int32_t L = ends.top().second;
+      ends.pop();
+      for (int32_t i : sims[L].tasks) {
+        ++done;
+        for (int32_t q = sbeg[i]; q < sbeg[i + 1]; ++q)
+          if (--need[succ[q]] == 0) ready(succ[q]);
+      }
+    }
+    if (done == nt) break;
+    for (int a = 0; a < 2; ++a) {
+      if (free_at[a] > now || by_tail[a].empty()) continue;
+      const double tmax = by_tail[a].rbegin()->first;
+      double delta = d[by_tail[a].rbegin()->second];
+      for (bool grew = true; grew;) {
+        grew = false;
+        for (auto it = by_tail[a].rbegin(); it != by_tail[a].rend() && it->first > tmax - delta; ++it)
+          if (d[it->second] > delta) {
+            delta = d[it->second];
+            grew = true;
+          }
+      }
+      Sim L{(int8_t)a, now, 0.0, {}};
+      for (auto it = by_tail[a].rbegin(); it != by_tail[a].rend() && it->first > tmax - delta; ++it)
+        L.tasks.push_back(it->second);
+      for (auto it = by_dur[a].begin(); it != by_dur[a].end() && it->first <= delta; ++it) L.tasks.push_back(it->second);
+      std::sort(L.tasks.begin(), L.tasks.end());
+      L.tasks.erase(std::unique(L.tasks.begin(), L.tasks.end()), L.tasks.end());
+      double work = 0.0;
+      for (int32_t i : L.tasks) {
+        by_dur[a].erase({d[i], i});
+        by_tail[a].erase({tail[i], i});
+        work += d[i];
+      }
+      L.end = now + std::max(delta, work / 256.0) + ovh;
+      free_at[a] = L.end;
+      ends.push({L.end, (int32_t)sims.size()});
+      sims.push_back(std::move(L));
+    }
+    for (int s = 2; s < MS_STREAMS && !waveq.empty(); ++s) {
+      if (free_at[s] > now) continue;
+      Sim L{(int8_t)s, now, 0.0, {}};
+      double mx = 0.0, work = 0.0;
+      for (int32_t i : waveq) {
+        mx = std::max(mx, d[i]);
+        work += d[i];
+      }
+      L.tasks.swap(waveq);
+      waveq.clear();
+      L.end = now + std::max(mx, work / 64.0) + ovh;
+      free_at[s] = L.end;
+      ends.push({L.end, (int32_t)sims.size()});
+      sims.push_back(std::move(L));
+    }
+    if (ends.empty()) throw std::logic_error("stream program: no task can start (dependency cycle)");
+    now = std::max(now, ends.top().first);
+  }
+  // issue order: by simulated start (ties: creation order)
+  std::vector<int32_t> ord(sims.size());
+  for (size_t i = 0; i < sims.size(); ++i) ord[i] = (int32_t)i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return sims[a].start < sims[b].start; });
+  std::vector<int32_t> pos_of(sims.size());
+  for (size_t k = 0; k < ord.size(); ++k) pos_of[ord[k]] = (int32_t)k;
+  for (size_t L = 0; L < sims.size(); ++L)
+    for (int32_t i : sims[L].tasks) launch_of[i] = pos_of[L];
+  out = StreamProgram{};
+  out.order.reserve(nt);
+  out.launches.resize(ord.size());
+  std::vector<int32_t> rec_of(ord.size(), -1);
+  // last launch (issue position) of stream s2 that stream s already waits for
+  int32_t waited[MS_STREAMS][MS_STREAMS];
+  for (auto& row : waited)
+    for (int32_t& v : row) v = -1;
+  for (size_t k = 0; k < ord.size(); ++k) {
+    Sim& L = sims[ord[k]];
+    MSLaunch& M = out.launches[k];
+    M.stream = L.stream;
+    M.rec = -1;
+    // longer tasks first (round-robin over the launch's work-groups)
+    std::stable_sort(L.tasks.begin(), L.tasks.end(), [&](int32_t a, int32_t b) { return d[a] > d[b]; });
+    M.t0 = (int32_t)out.order.size();
+    for (int32_t i : L.tasks) out.order.push_back(i);
+    M.t1 = (int32_t)out.order.size();
+    // per other stream, the latest launch this one depends on
+    int32_t need_from[MS_STREAMS] = {-1, -1, -1, -1};
+    for (int32_t i : L.tasks)
+      for (int32_t q = 0; q < p.tasks[i].ndeps; ++q) {
+        const int32_t u = p.deps[p.tasks[i].dep_begin + q];
+        const int32_t lu = launch_of[u];
+        const int su = out.launches[lu].stream;
+        if (lu >= (int32_t)k) throw std::logic_error("stream program: dependency issued later");
+        if (su != M.stream) need_from[su] = std::max(need_from[su], lu);
+      }
+    M.wait_begin = (int32_t)out.waits.size();
+    M.nwait = 0;
+    for (int s2 = 0; s2 < MS_STREAMS; ++s2) {
+      const int32_t lu = need_from[s2];
+      if (lu < 0 || lu <= waited[M.stream][s2]) continue;
+      if (rec_of[lu] < 0) {
+        rec_of[lu] = out.nevents++;
+        out.launches[lu].rec = rec_of[lu];
+      }
+      out.waits.push_back(rec_of[lu]);
+      ++M.nwait;
+      waited[M.stream][s2] = lu;
+    }
+  }
+  double end = 0.0;
+  for (const Sim& L : sims) end = std::max(end, L.end);
+  out.modelled_seconds = end;
+  validate_stream_program(p, out);
+}
+
+void validate_stream_program(const Plan& p, const StreamProgram& g) {
+  auto fail = [](const char* what) { throw std::logic_error(what); };
+  const int32_t nt = (int32_t)p.tasks.size();
+  if ((int32_t)g.order.size() != nt) fail("stream program: order is not a permutation");
+  std::vector<int32_t> launch_of(nt, -1);
+  for (size_t k = 0; k < g.launches.size(); ++k) {
+    const MSLaunch& M = g.launches[k];
+    if (M.stream < 0 || M.stream >= MS_STREAMS || M.t0 < 0 || M.t1 < M.t0 || M.t1 > nt) fail("stream program: launch");
+    if (M.wait_begin < 0 || M.nwait < 0 || M.wait_begin + M.nwait > (int32_t)g.waits.size())
+      fail("stream program: wait range");
+    if (M.rec < -1 || M.rec >= g.nevents) fail("stream program: event");
+    for (int32_t q = M.t0; q < M.t1; ++q) {
+      const int32_t i = g.order[q];
+      if (i < 0 || i >= nt || launch_of[i] >= 0) fail("stream program: order is not a permutation");
+      launch_of[i] = (int32_t)k;
+    }
+  }
+  // event e -> launch that records it (each event recorded once)
+  std::vector<int32_t> rec_launch(g.nevents, -1);
+  for (size_t k = 0; k < g.launches.size(); ++k)
+    if (g.launches[k].rec >= 0) {
+      if (rec_launch[g.launches[k].rec] >= 0) fail("stream program: event recorded twice");
+      rec_launch[g.launches[k].rec] = (int32_t)k;
+    }
+  // covered[s][s2]: latest launch of stream s2 whose completion stream s has
+  // waited for, so far in issue order (waits carry over to later launches of s)
+  std::vector<int32_t> covered(MS_STREAMS * MS_STREAMS, -1);
+  for (size_t k = 0; k < g.launches.size(); ++k) {
+    const MSLaunch& M = g.launches[k];
+    for (int32_t w = 0; w < M.nwait; ++w) {
+      const int32_t e = g.waits[M.wait_begin + w];
+      const int32_t lr = rec_launch[e];
+      if (lr < 0 || lr >= (int32_t)k) fail("stream program: wait on an event not yet recorded");
+      const int s2 = g.launches[lr].stream;
+      int32_t& c = covered[M.stream * MS_STREAMS + s2];
+      c = std::max(c, lr);
+    }
+    for (int32_t q = M.t0; q < M.t1; ++q) {
+      const int32_t i = g.order[q];
+      for (int32_t r = 0; r < p.tasks[i].ndeps; ++r) {
+        const int32_t u = p.deps[p.tasks[i].dep_begin + r];
+        const int32_t lu = launch_of[u];
+        if (lu >= (int32_t)k) fail("stream program: dependency not in an earlier launch");
+        const int su = g.launches[lu].stream;
+        // same stream: in order; other stream: an awaited launch of that stream
+        // at or after the dependency's launch (launches of one stream complete in order)
+        if (su != M.stream && covered[M.stream * MS_STREAMS + su] < lu)
+          fail("stream program: cross-stream dependency without a wait");
+      }
+    }
   }
 }
 

@@ -210,4 +210,33 @@ void build_plan(const Tree& t, Plan& p);
 void schedule_by_durations(const Plan& p, const std::vector<double>& dur, std::vector<int32_t>& order,
                            std::vector<int32_t>& level_begin);
 
+// Factorisation on several streams.  Task classes: the big blocks' flush steps
+// (TASK_TS_*) on stream 1, low-rank flushes of blocks above MS_LONG_ROWS rows
+// or columns as waves on streams 2 .. MS_STREAMS - 1, every other task on
+// stream 0; streams 0 and 1 run levels built as in schedule_by_durations.  A
+// launch runs tasks order[t0 .. t1) on its stream; before it, its stream waits
+// for the events waits[wait_begin .. + nwait) (each recorded after an earlier
+// launch of another stream); after it, event rec (>= 0) is recorded.  The
+// launches are listed in the order the host issues them; every dependency of a
+// task is met by an earlier launch of its own stream or by such a wait.
+constexpr int MS_STREAMS = 4;
+constexpr int MS_LONG_ROWS = 64;
+struct MSLaunch {
+  int8_t stream;
+  int32_t t0, t1;
+  int32_t wait_begin, nwait;
+  int32_t rec;
+};
+struct StreamProgram {
+  std::vector<int32_t> order;
+  std::vector<MSLaunch> launches;
+  std::vector<int32_t> waits;
+  int32_t nevents = 0;
+  double modelled_seconds = 0;   // makespan of the simulation that built it
+};
+void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double launch_overhead,
+                          StreamProgram& out);
+// Throws std::logic_error if a dependency is not met as stated above.
+void validate_stream_program(const Plan& p, const StreamProgram& g);
+
 }  // namespace hm
