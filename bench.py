@@ -26,13 +26,16 @@ timed, fewer if the next one would overrun the run's wall budget
 actually timed, `steps_requested` the number asked for.
 
 roofline: the dominant kernel is the H-Cholesky executor k_level, launched once
-per dependency level of the task graph.  achieved = (algorithmic flops of one
-factorisation, counted by the device from the actual ranks) / (number of
-launches) / (average launch duration), where the launch duration is the
-factorisation time measured with HIP events on the library's stream divided
-by the number of launches; peak = MI355X FP64 vector rate.  traffic comes from
-the committed rocprofv3 counter summary for k_level when the kernel source is
-unchanged since the counters were taken, else null.
+per level of the schedule (with the tuned schedule: the launches of the
+four-stream program, which overlap in time).  achieved = (algorithmic flops of
+one factorisation, counted by the device from the actual ranks) / (number of
+launches) / (wall time per launch), where the wall time per launch is the
+factorisation time measured with HIP events on the library's stream (which
+joins the other three) divided by the number of launches -- that is, the
+factorisation's flop rate; peak = MI355X FP64 rate.  traffic comes from the
+committed rocprofv3 counter summary for k_level (HBM bytes per factorisation
+over the launches) when the kernel source is unchanged since the counters
+were taken, else null.
 
 cpu_baseline times the oracle (oracle/, one thread) at two sample sizes of the
 same workload (n = 3000 and 6000) and extrapolates to n with the growth
@@ -189,7 +192,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0)
-    ap.add_argument("--form", choices=("plain", "served", "batched", "stream", "mc"), default="plain")
+    ap.add_argument("--form", choices=("plain", "served", "batched", "stream", "mc", "accuracy"), default="plain")
+    ap.add_argument("--acc-m", type=int, default=129, help="accuracy form: grid side (n = m^2, eq. 3)")
     ap.add_argument("--mc-n", type=int, default=4000, help="mc form: locations")
     ap.add_argument("--mc-mixed-replicates", type=int, default=0,
                     help="mc form: mixed-precision fits for the first replicates only (0: all)")
@@ -220,6 +224,8 @@ def main():
         return stream(args)
     if args.form == "mc":
         return mc(args)
+    if args.form == "accuracy":
+        return accuracy(args)
 
     import numpy as np
     import torch
@@ -316,7 +322,7 @@ def main():
                    "blocks": info["nblocks"], "tasks": info["ntasks"], "levels": launches,
                    "levels_longest_path": info["nlevels"],
                    "schedule": "longest-path levels" if args.no_tune else
-                               "levels rebuilt from one timed evaluation (untimed, before the steps)"},
+                               "four-stream program built from one timed evaluation (untimed, before the steps)"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "phases_ms": {"assemble": float(np.mean(asm)) * 1e3, "factor": t_fac * 1e3,
                       "solve": float(np.mean(sol)) * 1e3, "dataset_setup_host": t_setup * 1e3,
@@ -330,7 +336,8 @@ def main():
         "vs_oracle": oracle_error(n, eps, r),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_per_launch(n, launches),
-                     "kernel": "k_level (H-Cholesky task executor, one launch per dependency level)",
+                     "kernel": "k_level (H-Cholesky task executor, one launch per level of the schedule)",
+                     "streams": 1 if args.no_tune else 4,
                      "launches": launches, "avg_launch_ms": avg_launch * 1e3,
                      "flops_per_launch": flops / launches},
     }
@@ -399,8 +406,18 @@ def batched(args):
             seq_res.append(ds.loglik(theta, nug, eps))
             log(f"replicate {r + 1}/{m} alone: n={ns[r]}, {seq_res[-1]['t_factor'][0]:.2f} s factor")
         seq = time.perf_counter() - t0
+    # one batched call per group of at most 16 replicates (all on the device at
+    # once); a group's factor storage is released before the next group, so
+    # any number of replicates fits in HBM
+    group = 16
     t0 = time.perf_counter()
-    res = hmlik.loglik_batch(ctx, dss, [theta] * m, [nug] * m, eps)
+    res = []
+    for g0 in range(0, m, group):
+        part = dss[g0:g0 + group]
+        res += hmlik.loglik_batch(ctx, part, [theta] * len(part), [nug] * len(part), eps)
+        for ds in part:
+            ds.release()
+        log(f"replicates {g0 + 1}..{g0 + len(part)} done, {time.perf_counter() - t0:.1f} s")
     wall = time.perf_counter() - t0
     fac = [float(r["t_factor"][0]) for r in res]
     flops = sum(ds.factor_flops() for ds in dss)
@@ -425,6 +442,7 @@ def batched(args):
                    "eps": eps, "leaf_size": LEAF, "eta": ETA, "slots": min(16, m),
                    "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]), "schedule": "longest-path levels"},
         "batch_wall_s": wall,
+        "batch_calls": (m + group - 1) // group,
         "sequential_wall_s": seq,
         "bitwise_equal_to_sequential": (None if seq is None else
                                         all(np.array_equal(a["loglik"], b["loglik"]) for a, b in zip(res, seq_res))),
@@ -456,6 +474,40 @@ def nm_trace(seed: int, length: int):
         out.append(tuple(float(v) for v in np.exp(x)))
         x = gen.send(float(np.sum(((x - centre) / scale) ** 2)))
     return out
+
+
+def accuracy(args):
+    """Accuracy diagnostics in the style of Table 2 (Section 2.4): the perturbed
+    grid of eq. 3 (n = m^2), exponential covariance (nu = 0.5) at two length
+    scales, a list of eps: log-det error, KLD, ||I - C~^{-1} C||_2 (10 power
+    steps) and storage, per (ell, eps)."""
+    from paper_1709_04419_amd import diagnostics, hmlik
+    from paper_1709_04419_amd import workloads as wl
+
+    m = args.acc_m
+    n = m * m
+    P = wl.perturbed_grid(m, 7)
+    ctx = hmlik.Context(0)
+    rows = []
+    try:
+        ds = hmlik.Dataset(ctx, P, LEAF, ETA)
+        ds.set_z(wl.standard_normal(n, 1, 8))
+        for ell in (0.0334, 0.2337):
+            theta = (1.0, ell, 0.5)
+            t0 = time.perf_counter()
+            for r in diagnostics.sweep(ds, theta, 0.0, eps_list=(1e-3, 1e-5, 1e-7, 1e-9)):
+                r["ell"] = ell
+                rows.append(r)
+                log(f"accuracy: ell {ell} eps {r['eps']:g}: " + (
+                    f"logdet rel err {r['logdet_rel_err']:.2e}, KLD {r['kld']:.3e}, inverse error {r['inv_err']:.2e}, "
+                    f"max rank {r['max_rank']}" if r["status"] == 0 else f"status {r['status']}"))
+            log(f"accuracy: ell {ell} done in {time.perf_counter() - t0:.1f} s")
+        ds.close()
+    finally:
+        ctx.close()
+    print(json.dumps({"metric": "H-matrix accuracy diagnostics (Section 2.4, Table 2 style)", "form": "accuracy",
+                      "data": "synthetic", "n": n, "points": f"perturbed grid (eq. 3), {m} x {m}, seed 7",
+                      "nugget": 0.0, "leaf_size": LEAF, "eta": ETA, "rows": rows}), flush=True)
 
 
 def mc(args):

@@ -43,7 +43,8 @@ typedef enum {
   HM_ERR_ARG = 1,       /* invalid argument (null pointer, size, non-finite value, theta <= 0) */
   HM_ERR_NOT_SPD = 2,   /* a pivot of the H-Cholesky was <= 0 (the paper's breakdown at coarse
                            accuracy, Tables 6 and 7); outputs are NaN, fail_block/fail_pivot set */
-  HM_ERR_OOM = 3,       /* device allocation failed */
+  HM_ERR_OOM = 3,       /* device allocation failed, or (hm_dataset_create) the task graph exceeds the
+                           schedule's 32-bit offsets (about 1.8e9 dependencies at n = 2,000,000) */
   HM_ERR_DEVICE = 4,    /* a HIP runtime call failed */
   HM_ERR_INTERNAL = 5,  /* an internal invariant failed (planner error on unusual input) */
   HM_ERR_CANCELLED = 6, /* the request was cancelled before it finished */
@@ -195,8 +196,10 @@ hm_status hm_loglik_batch(hm_ctx *ctx, int32_t m, hm_dataset *const *ds, const h
                           const hm_approx *approx, hm_result *out);
 
 /* Introspection: sizes of the trees and of the factorisation's task graph.
- * nlevels is the number of dependency levels of that graph, which is also the
- * number of executor kernel launches per factorisation.  Any pointer may be
+ * nlevels is the number of executor kernel launches per factorisation of the
+ * schedule in use: the dependency levels of the graph (longest path, or as
+ * rebuilt by hm_tune_schedule), or the launches of the four-stream program
+ * that hm_tune_schedule builds (those overlap in time).  Any pointer may be
  * NULL (that value is not written). */
 hm_status hm_dataset_info(const hm_dataset *ds, int64_t *n, int64_t *nclusters, int64_t *nblocks,
                           int64_t *ntasks, int64_t *nlevels);

@@ -361,6 +361,9 @@ hm_status hm_dataset_create(hm_ctx* ctx, const double* coords_in, int64_t n, int
   } catch (const std::bad_alloc&) {
     delete ds;
     return HM_ERR_OOM;
+  } catch (const std::length_error&) {
+    delete ds;              // the task graph outgrows the schedule's 32-bit offsets
+    return HM_ERR_OOM;
   } catch (const std::exception&) {
     delete ds;
     return HM_ERR_INTERNAL;
@@ -1003,7 +1006,7 @@ hm_status hm_dataset_info(const hm_dataset* ds, int64_t* n, int64_t* nclusters, 
   if (nclusters) *nclusters = (int64_t)ds->tree.cl.size();
   if (nblocks) *nblocks = (int64_t)ds->tree.bk.size();
   if (ntasks) *ntasks = (int64_t)ds->plan.tasks.size();
-  if (nlevels) *nlevels = (int64_t)ds->level_begin.size() - 1;
+  if (nlevels) *nlevels = ds->ms_valid ? (int64_t)ds->ms.launches.size() : (int64_t)ds->level_begin.size() - 1;
   return HM_OK;
 }
 

@@ -25,7 +25,10 @@
 #include "hm_plan.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <deque>
+#include <map>
 #include <queue>
 #include <set>
 #include <stdexcept>
@@ -216,6 +219,7 @@ struct Planner {
     t.diag = -1;
     t.a0 = a0;
     t.a1 = a1;
+    if (tasks.size() >= (size_t)INT32_MAX) throw std::length_error("task graph: more tasks than 32-bit ids");
     tasks.push_back(t);
     tdeps.push_back(std::move(deps));
     return (int32_t)tasks.size() - 1;
@@ -374,6 +378,7 @@ struct Planner {
       d.A = A;
       d.B = Bb;
       std::vector<int32_t> deps;
+      if (P.terms.size() >= (size_t)INT32_MAX) throw std::length_error("task graph: more terms than 32-bit ids");
       int32_t tid = (int32_t)P.terms.size();
       if (ka == BK_LR) {
         d.kind = TK_LRA;
@@ -396,8 +401,6 @@ struct Planner {
       d.buf = -1;
       term_tasks.emplace_back();
       if (d.rows > 0) {
-        d.buf = P.term_pool;
-        P.term_pool += d.rows * K_MAX;
         // rows of the computed factor = rows of the H-block applied
         const int32_t hrow = (d.kind == TK_LRA) ? B(Bb).row : B(A).row;
         if (d.rows > TERM_SPLIT) {
@@ -478,6 +481,75 @@ struct Planner {
       for (int q = 0; q < g; ++q) prevC.push_back(new_task(TASK_TS_C, bid, cd, i, q));
     }
     return prevC;
+  }
+
+  // Term buffers by liveness.  A computed term factor is written by its
+  // producer tasks and read while the leaves that hold its instances are
+  // flushed; every such read happens before final_task of that leaf (the
+  // flush task, or a task that depends on it).  Sweeping the program order, a
+  // term's buffer is released after the last of those final tasks and given
+  // to a later term of the same row count whose producers are at least
+  // TERM_REUSE_SLACK longest-path levels later than every one of them; the
+  // new producers then depend on those final tasks, so no schedule can
+  // overwrite a factor that is still to be read.
+  void share_term_buffers() {
+    constexpr int32_t TERM_REUSE_SLACK = 8;
+    const int32_t nt = (int32_t)tasks.size(), nterm = (int32_t)P.terms.size();
+    std::vector<int32_t> lev(nt, 0);
+    for (int32_t i = 0; i < nt; ++i)
+      for (int32_t d : tdeps[i]) lev[i] = std::max(lev[i], lev[d] + 1);
+    std::vector<std::vector<int32_t>> cons(nterm);
+    for (size_t b = 0; b < leaf_insts.size(); ++b)
+      for (const TermInst& in : leaf_insts[b])
+        if (P.terms[in.term].rows > 0) cons[in.term].push_back(final_task[b]);
+    std::vector<int32_t> first(nterm, -1), last(nterm, -1), conslev(nterm, 0);
+    std::vector<std::vector<int32_t>> at_first(nt + 1), at_free(nt + 1);
+    for (int32_t k = 0; k < nterm; ++k) {
+      if (P.terms[k].rows <= 0 || term_tasks[k].empty()) continue;
+      auto& c = cons[k];
+      std::sort(c.begin(), c.end());
+      c.erase(std::unique(c.begin(), c.end()), c.end());
+      first[k] = *std::min_element(term_tasks[k].begin(), term_tasks[k].end());
+      last[k] = *std::max_element(term_tasks[k].begin(), term_tasks[k].end());
+      for (int32_t q : c) {
+        if (q < 0) throw std::logic_error("term consumer without a final task");
+        last[k] = std::max(last[k], q);
+        conslev[k] = std::max(conslev[k], lev[q]);
+      }
+      at_first[first[k]].push_back(k);
+      at_free[last[k] + 1].push_back(k);
+    }
+    struct Slot {
+      int64_t off;
+      int32_t prev;   // term that held it last
+    };
+    std::map<int64_t, std::deque<Slot>> free_by_rows;
+    P.term_pool = 0;
+    for (int32_t i = 0; i <= nt; ++i) {
+      for (int32_t k : at_free[i]) free_by_rows[P.terms[k].rows].push_back(Slot{P.terms[k].buf, k});
+      if (i == nt) break;
+      for (int32_t k : at_first[i]) {
+        TermDef& d = P.terms[k];
+        int32_t plev = nt;
+        for (int32_t q : term_tasks[k]) plev = std::min(plev, lev[q]);
+        auto& fl = free_by_rows[d.rows];
+        bool got = false;
+        for (int probe = 0; probe < 8 && probe < (int)fl.size(); ++probe) {
+          const Slot sl = fl[probe];
+          if (conslev[sl.prev] + TERM_REUSE_SLACK >= plev) continue;
+          fl.erase(fl.begin() + probe);
+          d.buf = sl.off;
+          for (int32_t q : term_tasks[k])
+            for (int32_t c : cons[sl.prev]) tdeps[q].push_back(c);
+          got = true;
+          break;
+        }
+        if (!got) {
+          d.buf = P.term_pool;
+          P.term_pool += d.rows * K_MAX;
+        }
+      }
+    }
   }
 
   void htrsm(int32_t bid) {
@@ -641,6 +713,7 @@ struct Planner {
     final_task.assign(nb, -1);
     leaf_insts.assign(nb, {});
     hchol(0);
+    share_term_buffers();
     // levels (longest path) and ticket order
     const int32_t nt = (int32_t)tasks.size();
     std::vector<int32_t> level(nt, 0);
@@ -667,6 +740,9 @@ struct Planner {
       Task t = tasks[i];
       t.level = level[i];
       P.max_level = std::max(P.max_level, level[i]);
+      // dependency and instance lists are indexed with 32 bits on both sides
+      if (P.deps.size() + tdeps[i].size() > (size_t)INT32_MAX || P.insts.size() + leaf_insts.size() > (size_t)INT32_MAX)
+        throw std::length_error("task graph: more dependencies or instances than 32-bit offsets");
       t.dep_begin = (int32_t)P.deps.size();
       for (int32_t d : tdeps[i]) P.deps.push_back(rank[d]);
       t.ndeps = (int32_t)tdeps[i].size();
