@@ -198,6 +198,9 @@ def main():
     ap.add_argument("--mc-mixed-replicates", type=int, default=0,
                     help="mc form: mixed-precision fits for the first replicates only (0: all)")
     ap.add_argument("--mc-max-evals", type=int, default=300)
+    ap.add_argument("--mc-theta", type=str, default="1.0,0.7,0.9",
+                    help="mc form: true theta sigma2,ell,nu (default: Section 4's (ell, nu, sigma) = (0.7, 0.9, 1))")
+    ap.add_argument("--mc-nugget", type=float, default=1e-6)
     ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64",
                     help="plain form: FP64, or the mixed-precision form with refinement of C~^-1 Z")
     ap.add_argument("--refine-max-iter", type=int, default=10)
@@ -395,6 +398,7 @@ def batched(args):
         n_r = int(np.random.default_rng(4000 + r).integers(4000, 64001))
         ds = hmlik.Dataset(ctx, wl.uniform_square(n_r, 4000 + r), LEAF, ETA)
         ds.set_z(wl.standard_normal(n_r, 1, 4200 + r))
+        ds.release()                      # factor storage is attached on admission
         dss.append(ds)
         ns.append(n_r)
     log(f"{m} replicates, n from {min(ns)} to {max(ns)} (sum {sum(ns)})")
@@ -495,7 +499,7 @@ def accuracy(args):
         for ell in (0.0334, 0.2337):
             theta = (1.0, ell, 0.5)
             t0 = time.perf_counter()
-            for r in diagnostics.sweep(ds, theta, 0.0, eps_list=(1e-3, 1e-5, 1e-7, 1e-9)):
+            for r in diagnostics.sweep(ds, theta, 0.0, eps_list=(1e-3, 1e-5, 1e-7, 1e-9), log=log):
                 r["ell"] = ell
                 rows.append(r)
                 log(f"accuracy: ell {ell} eps {r['eps']:g}: " + (
@@ -518,7 +522,9 @@ def mc(args):
 
     ctx = hmlik.Context(0)
     try:
-        out = mc_study.run(ctx, args.mc_n, args.replicates, eps=args.eps, mixed=(args.prec == "mixed"),
+        th = tuple(float(v) for v in args.mc_theta.split(","))
+        out = mc_study.run(ctx, args.mc_n, args.replicates, theta_true=th, nugget=args.mc_nugget, eps=args.eps,
+                           mixed=(args.prec == "mixed"),
                            mixed_replicates=args.mc_mixed_replicates, max_evals=args.mc_max_evals,
                            refine_max_iter=args.refine_max_iter, refine_tol=args.refine_tol, log=log)
     finally:

@@ -282,7 +282,7 @@ const char* hm_status_string(hm_status s) {
     case HM_ERR_NOT_SPD: return "H-Cholesky breakdown: non-positive pivot";
     case HM_ERR_OOM: return "device out of memory";
     case HM_ERR_DEVICE: return "HIP runtime error";
-    case HM_ERR_INTERNAL: return "task executor aborted";
+    case HM_ERR_INTERNAL: return "internal invariant failed (planner or schedule)";
     case HM_ERR_CANCELLED: return "request cancelled";
     case HM_ERR_BUSY: return "a request server owns this context";
   }

@@ -1321,12 +1321,13 @@ __device__ int wg_svd_explicit(const DevData& D, double* A, int m, int n, int64_
     G[q + i * ldg] = (i <= q) ? A[i * si + (int64_t)pos[q] * sc] : 0.0;
   }
   __syncthreads();
-  // Explicit flushes with r well below n: QR of R^T = Q2 [R2; 0] first, and
-  // the Jacobi iteration on the r x r factor R2 (R2 J = X Sigma, so that
-  // R^T J = Q2 [X; 0] Sigma): the same rotations (R2 has the Gram matrix of
-  // R^T), on r rows instead of n.
+  // With r well below n: QR of R^T = Q2 [R2; 0] first, and the Jacobi
+  // iteration on the r x r factor R2 (R2 J = X Sigma, so that R^T J = Q2 [X; 0]
+  // Sigma): the same rotations (R2 has the Gram matrix of R^T), on r rows
+  // instead of n.  R2 and the reflectors go to gws (odd_ld(n) r doubles, within
+  // its stated size).
   const int ldm = (int)odd_ld(r);
-  const bool precond = (by_rows || a_spill) && n >= 2 * r && r >= 8 && (int64_t)ldm * r + odd_ld(n) <= lds_cap;
+  const bool precond = n >= 2 * r && r >= 8 && (int64_t)ldm * r + odd_ld(n) <= lds_cap;
   double* M = lds;
   double* Gq = G;
   if (precond) {

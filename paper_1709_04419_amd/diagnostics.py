@@ -27,7 +27,11 @@ import numpy as np
 from . import hmlik as H
 
 
-def exact_logdet(ds, chunk: int = 4096) -> float:
+def _quiet(msg: str) -> None:
+    pass
+
+
+def exact_logdet(ds, chunk: int = 4096, log=_quiet) -> float:
     """log|C| of the exact covariance at the dataset's last assembled theta."""
     import torch
     n = ds.n
@@ -35,12 +39,15 @@ def exact_logdet(ds, chunk: int = 4096) -> float:
     for j0 in range(0, n, chunk):
         nj = min(chunk, n - j0)
         C[:, j0:j0 + nj] = ds.exact_block(0, n, j0, nj, device=True)
+    log(f"diagnostics: exact covariance formed ({n} x {n}), dense Cholesky")
     L = torch.linalg.cholesky(C)
     del C
-    return float(2.0 * torch.sum(torch.log(torch.diagonal(L))).item())
+    v = float(2.0 * torch.sum(torch.log(torch.diagonal(L))).item())
+    log(f"diagnostics: log|C| = {v:.10g}")
+    return v
 
 
-def trace_inv_exact(ds, chunk: int = 64) -> float:
+def trace_inv_exact(ds, chunk: int = 64, log=_quiet) -> float:
     """tr(C~^{-1} C) = tr((L~ L~^T)^{-1} C), column chunk by column chunk."""
     import torch
     n = ds.n
@@ -50,11 +57,13 @@ def trace_inv_exact(ds, chunk: int = 64) -> float:
         Cj = ds.exact_block(0, n, j0, nj, device=True)          # C(:, j0:j0+nj)
         Y = ds.apply(H.HM_OP_SOLVE, Cj)                          # (L~ L~^T)^{-1} C(:, j0:j0+nj)
         tr += float(torch.sum(torch.diagonal(Y[j0:j0 + nj, :])).item())
+        if (j0 // chunk) % 64 == 63:
+            log(f"diagnostics: trace, {j0 + nj} of {n} columns")
     return tr
 
 
 def accuracy(ds, theta, nugget: float, eps: float = 0.0, rank: int = 0, power_iters: int = 10,
-             seed: int = 7, logdet_exact: float = None) -> Dict[str, float]:
+             seed: int = 7, logdet_exact: float = None, log=_quiet) -> Dict[str, float]:
     """Evaluates the H-likelihood at theta (eps or rank), then the diagnostics
     of the module docstring.  logdet_exact may be passed in when several
     accuracies are compared at one theta (it does not depend on eps)."""
@@ -63,8 +72,8 @@ def accuracy(ds, theta, nugget: float, eps: float = 0.0, rank: int = 0, power_it
         return dict(status=int(res["status"][0]), eps=eps, rank=rank)
     logdet_h = float(res["logdet"][0])
     if logdet_exact is None:
-        logdet_exact = exact_logdet(ds)
-    tr = trace_inv_exact(ds)
+        logdet_exact = exact_logdet(ds, log=log)
+    tr = trace_inv_exact(ds, log=log)
     n = ds.n
     kld = 0.5 * (tr - n + logdet_h - logdet_exact)
     x0 = np.random.default_rng(seed).standard_normal(n)
@@ -76,10 +85,10 @@ def accuracy(ds, theta, nugget: float, eps: float = 0.0, rank: int = 0, power_it
 
 
 def sweep(ds, theta, nugget: float, eps_list: Sequence[float] = (), ranks: Sequence[int] = (),
-          power_iters: int = 10) -> list:
+          power_iters: int = 10, log=_quiet) -> list:
     """Table 2 (accuracy eps) / Table 3 (fixed rank k) style sweep at one theta."""
     ds.loglik(theta, nugget, eps_list[0] if eps_list else 0.0, ranks[0] if ranks and not eps_list else 0)
-    ld = exact_logdet(ds)
-    rows = [accuracy(ds, theta, nugget, eps=e, power_iters=power_iters, logdet_exact=ld) for e in eps_list]
-    rows += [accuracy(ds, theta, nugget, rank=k, power_iters=power_iters, logdet_exact=ld) for k in ranks]
+    ld = exact_logdet(ds, log=log)
+    rows = [accuracy(ds, theta, nugget, eps=e, power_iters=power_iters, logdet_exact=ld, log=log) for e in eps_list]
+    rows += [accuracy(ds, theta, nugget, rank=k, power_iters=power_iters, logdet_exact=ld, log=log) for k in ranks]
     return rows

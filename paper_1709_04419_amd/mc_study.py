@@ -51,6 +51,24 @@ def simulate_replicates(ctx, points, replicates: int, theta_true, nugget: float,
         ds.close()
 
 
+class _Progress:
+    """A Dataset seen through its loglik calls, reporting every `every` calls
+    (a search of hundreds of evaluations prints while it runs)."""
+
+    def __init__(self, ds, label: str, log, every: int = 25):
+        self._ds, self._label, self._log, self._every = ds, label, log, every
+        self.calls = self.breakdowns = 0
+
+    def loglik(self, *a, **k):
+        r = self._ds.loglik(*a, **k)
+        self.calls += 1
+        if int(r["status"][0]) != 0:
+            self.breakdowns += 1
+        if self.calls % self._every == 0:
+            self._log(f"{self._label}: {self.calls} evaluations, {self.breakdowns} not SPD")
+        return r
+
+
 def run(ctx, n: int, replicates: int, theta_true=(1.0, 0.7, 0.9), nugget: float = 1e-6,
         eps: float = 1e-7, theta0=None, points: str = "uniform", seed: int = 101, leaf_size: int = 64,
         eta: float = 2.0, mixed: bool = True, mixed_replicates: int = 0, slots: int = 16,
@@ -75,7 +93,7 @@ def run(ctx, n: int, replicates: int, theta_true=(1.0, 0.7, 0.9), nugget: float 
             ds.set_z(Z[:, j])
         t0 = time.perf_counter()
         with H.Server(ctx, max_active=min(slots, replicates)) as sv:
-            fp64 = mle.fit_many(sv, dss, [th0] * replicates, nugget, eps=eps, **kw)
+            fp64 = mle.fit_many(sv, dss, [th0] * replicates, nugget, eps=eps, log=log, **kw)
         t_fp64 = time.perf_counter() - t0
         log(f"mc: FP64 fits of {replicates} replicates in {t_fp64:.1f} s "
             f"({sum(r['evals'] for r in fp64)} evaluations)")
@@ -86,7 +104,9 @@ def run(ctx, n: int, replicates: int, theta_true=(1.0, 0.7, 0.9), nugget: float 
             lk = dict(prec=H.HM_MIXED, refine_max_iter=refine_max_iter, refine_tol=refine_tol)
             t0 = time.perf_counter()
             for j in range(nm):
-                mix.append(mle.fit(dss[j], th0, nugget, eps=eps, loglik_kw=lk, **kw))
+                pr = _Progress(dss[j], f"mc: mixed fit {j + 1}/{nm}", log)
+                mix.append(mle.fit(pr, th0, nugget, eps=eps, loglik_kw=lk, **kw))
+                mix[-1]["breakdowns"] = pr.breakdowns
                 log(f"mc: mixed fit {j + 1}/{nm}: theta {tuple(round(v, 5) for v in mix[-1]['theta'])}")
             t_mixed = time.perf_counter() - t0
     finally:
@@ -96,8 +116,14 @@ def run(ctx, n: int, replicates: int, theta_true=(1.0, 0.7, 0.9), nugget: float 
                points=points, seed=seed, theta0=th0, seconds=dict(simulate=t_sim, fp64=t_fp64, mixed=t_mixed),
                fp64=[dict(theta=r["theta"], loglik=r["loglik"], evals=r["evals"], converged=r["converged"])
                      for r in fp64],
-               mixed=[dict(theta=r["theta"], loglik=r["loglik"], evals=r["evals"], converged=r["converged"])
-                      for r in mix])
+               mixed=[dict(theta=r["theta"], loglik=r["loglik"], evals=r["evals"], converged=r["converged"],
+                           breakdowns=r["breakdowns"]) for r in mix])
+    # mixed searches that never left a breakdown (every evaluation not SPD) have
+    # no estimate; the FP64-vs-mixed comparison is over the others
+    mix_ok = [(a, b) for a, b in zip(fp64, mix) if math.isfinite(b["loglik"])]
+    out["mixed_without_estimate"] = len(mix) - len(mix_ok)
+    mix = [b for _, b in mix_ok]
+    fp64_paired = [a for a, _ in mix_ok]
     out["summary"] = {}
     for name, fits in (("fp64", fp64), ("mixed", mix)):
         if fits:
@@ -105,7 +131,7 @@ def run(ctx, n: int, replicates: int, theta_true=(1.0, 0.7, 0.9), nugget: float 
             out["summary"][name] = {q: _quartiles([x[q] for x in qs]) for q in QUANTITIES}
     if mix:
         diffs = {q: [] for q in QUANTITIES}
-        for a, b in zip(fp64, mix):
+        for a, b in zip(fp64_paired, mix):
             qa, qb = _quantities(a["theta"]), _quantities(b["theta"])
             for q in QUANTITIES:
                 diffs[q].append(abs(qb[q] - qa[q]) / abs(qa[q]))

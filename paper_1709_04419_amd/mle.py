@@ -161,7 +161,7 @@ def fit(ds, theta0, nugget: float, eps: float = 1e-7, rank: int = 0, fit_nugget:
 
 
 def fit_many(server, datasets: List, theta0s, nugget: float,
-             eps: float = 1e-7, rank: int = 0, fit_nugget: bool = False, **kw) -> List[dict]:
+             eps: float = 1e-7, rank: int = 0, fit_nugget: bool = False, log=None, **kw) -> List[dict]:
     """One search per hmlik.Dataset, advanced together through an
     hmlik.Server (give it a slot per dataset): each round submits the
     pending point of every unfinished search to the server and feeds back the
@@ -173,7 +173,11 @@ def fit_many(server, datasets: List, theta0s, nugget: float,
         gens.append(g)
         pending.append(next(g))
     live = list(range(len(datasets)))
+    rounds = 0
     while live:
+        rounds += 1
+        if log is not None and rounds % 25 == 0:
+            log(f"fit_many: round {rounds}, {len(live)} searches running")
         tickets = {}
         for i in live:
             pt = _point(pending[i], nugget, fit_nugget)
