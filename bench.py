@@ -18,9 +18,10 @@ vector (the cost of an evaluation does not depend on Z).
 Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
 with the dataset (locations, trees, task schedule, Z) resident on the device
 before timing starts.  Warm-up is at most one evaluation: by default it is the
-evaluation of hm_tune_schedule, which times every task and re-balances the
-level schedule from those times (results are unchanged; --no-tune skips it and
-runs a plain warm-up evaluation instead).  Up to --steps evaluations are then
+evaluation of hm_tune_schedule, which times every task and builds from those
+times the four-stream program the timed steps run (results are unchanged;
+--no-tune skips it and runs a plain warm-up evaluation instead, and the steps
+keep the longest-path levels on one stream).  Up to --steps evaluations are then
 timed, fewer if the next one would overrun the run's wall budget
 (--deadline-s, counted from the start of the process); `steps` is the number
 actually timed, `steps_requested` the number asked for.
@@ -416,15 +417,18 @@ def batched(args):
     group = 16
     t0 = time.perf_counter()
     res = []
+    flops = 0.0
     for g0 in range(0, m, group):
         part = dss[g0:g0 + group]
         res += hmlik.loglik_batch(ctx, part, [theta] * len(part), [nug] * len(part), eps)
+        # flop counts are read while the factors are attached (released
+        # factors report none)
+        flops += sum(ds.factor_flops() for ds in part)
         for ds in part:
             ds.release()
         log(f"replicates {g0 + 1}..{g0 + len(part)} done, {time.perf_counter() - t0:.1f} s")
     wall = time.perf_counter() - t0
     fac = [float(r["t_factor"][0]) for r in res]
-    flops = sum(ds.factor_flops() for ds in dss)
     achieved = flops / wall / 1e12
     out = {
         "metric": METRIC,

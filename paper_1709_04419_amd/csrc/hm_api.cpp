@@ -196,11 +196,19 @@ hm_status build_device(hm_dataset* ds) {
   TRY(attach_store(ds));
   TRY(upload(ds, P.terms, const_cast<TermDef**>(&D.terms)));
   TRY(upload(ds, P.insts, const_cast<TermInst**>(&D.insts)));
-  TRY(upload(ds, P.tasks, const_cast<Task**>(&D.tasks)));
+  {
+    // the factor tasks, then the data solve's tasks that the stream program
+    // runs beside them (ids from ntasks on, no program index)
+    std::vector<Task> all(P.tasks);
+    all.insert(all.end(), P.ftasks.begin(), P.ftasks.end());
+    TRY(upload(ds, all, const_cast<Task**>(&D.tasks)));
+    std::vector<int32_t> prog(P.task_prog);
+    prog.resize(all.size(), -1);
+    TRY(upload(ds, prog, const_cast<int32_t**>(&D.task_prog)));
+  }
   TRY(upload(ds, ds->order, &ds->d_order));
   D.order = ds->d_order;
   TRY(upload(ds, P.deps, const_cast<int32_t**>(&D.deps)));
-  TRY(upload(ds, P.task_prog, const_cast<int32_t**>(&D.task_prog)));
   D.ntasks = (int32_t)P.tasks.size();
   TRY(dev_alloc(ds, 256, &p));
   D.fail_key = (unsigned long long*)p;
@@ -500,6 +508,7 @@ hm_status hm_dataset_set_z(hm_dataset* ds, const double* Z, int32_t r, int32_t o
     ds->zcap = r;
   }
   ds->r = r;
+  ds->fused_solved = false;
   return HM_OK;
 }
 
@@ -661,6 +670,7 @@ hm_status hm_assemble(hm_dataset* ds, const hm_theta* th, const hm_approx* ap) {
     ds->bytes_C = storage_bytes(ds, rk.data());
   }
   ds->assembled = true;
+  ds->fused_solved = false;
   ds->factored = false;
   return HM_OK;
 }
@@ -737,8 +747,16 @@ hm_status hm_factor(hm_dataset* ds) {
   DevData& D = ds->D;
   hipStream_t st = ds->ctx->stream;
   HIPTRY(hipEventRecord(ds->ev[1], st));
+  ds->fused_solved = false;
   if (ds->ms_valid) {
-    HIPTRY(launch_stream_program(ds, D, st));
+    // the program also runs the data's forward solve L~ v = Z (tree order, in
+    // place in the solve buffer) beside the factorisation's tail
+    DevData Dm = D;
+    Dm.W = ds->d_W;
+    Dm.r = ds->r;
+    HIPTRY(launch_permute(ds->d_Z, ds->d_perm, ds->tree.n, ds->r, ds->d_W, st));
+    HIPTRY(launch_stream_program(ds, Dm, st));
+    ds->fused_solved = true;
   } else {
     const int32_t nlev = (int32_t)ds->level_begin.size() - 1;
     // HMLIK_PROGRESS=<levels>: synchronise every <levels> levels and report
@@ -872,9 +890,17 @@ hm_status hm_solve(hm_dataset* ds, hm_result* out) {
     DevData Ds = D;
     Ds.W = ds->d_W;
     Ds.r = r;
-    HIPTRY(launch_solve(Ds, ds->d_Z, ds->d_perm, ds->plan.slevel_begin.data(),
-                        (int32_t)ds->plan.slevel_begin.size() - 1, NSLOTS, ds->d_diag_ids,
-                        (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, st));
+    if (ds->fused_solved) {
+      // v = L~^-1 Z is already in the solve buffer (the factorisation's
+      // program ran the solve): only the sums remain
+      HIPTRY(launch_solve_reduce(Ds, ds->d_diag_ids, (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, st));
+    } else {
+      HIPTRY(launch_solve(Ds, ds->d_Z, ds->d_perm, ds->plan.slevel_begin.data(),
+                          (int32_t)ds->plan.slevel_begin.size() - 1, NSLOTS, ds->d_diag_ids,
+                          (int32_t)ds->plan.diag_leaf_ids.size(), ds->d_out, st));
+    }
+    // the buffer is reused below (refinement) and by a later call
+    ds->fused_solved = false;
     HIPTRY(hipEventRecord(ds->ev[3], st));
     HIPTRY(hipEventSynchronize(ds->ev[3]));
     float ms = 0;
@@ -960,16 +986,33 @@ hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_appro
   if (s != HM_OK) return s;
   std::vector<int64_t> tt(7 * (size_t)nt);
   HIPTRY(hipMemcpy(tt.data(), ds->tt_buf, sizeof(int64_t) * tt.size(), hipMemcpyDeviceToHost));
-  std::vector<double> dur(nt);
-  for (int32_t t = 0; t < nt; ++t) dur[t] = (double)(tt[7 * (size_t)t + 1] - tt[7 * (size_t)t]);
+  // factor tasks: measured; the data solve's tasks (not timed in the run):
+  // the mean of the factor's tasks of the same kind, an over-estimate (those
+  // solve for many columns) that only orders the program
+  const int32_t nf = (int32_t)ds->plan.ftasks.size();
+  std::vector<double> dur(nt + (size_t)nf);
+  double ksum[2] = {0.0, 0.0};
+  int64_t kcnt[2] = {0, 0};
+  for (int32_t t = 0; t < nt; ++t) {
+    dur[t] = (double)(tt[7 * (size_t)t + 1] - tt[7 * (size_t)t]);
+    const int8_t k = ds->plan.tasks[t].kind;
+    if (k == TASK_SOLVE_SEQ || k == TASK_SOLVE_MV) {
+      ksum[k == TASK_SOLVE_MV] += dur[t];
+      ++kcnt[k == TASK_SOLVE_MV];
+    }
+  }
+  for (int32_t k = 0; k < nf; ++k) {
+    const int j = ds->plan.ftasks[k].kind == TASK_SOLVE_MV;
+    dur[nt + (size_t)k] = kcnt[j] ? ksum[j] / (double)kcnt[j] : 1000.0;
+  }
   std::vector<int32_t> order, level_begin;
   StreamProgram prog;
   const bool multi = !getenv("HMLIK_SINGLE_STREAM");
   try {
-    schedule_by_durations(ds->plan, dur, order, level_begin);
+    schedule_by_durations(ds->plan, std::vector<double>(dur.begin(), dur.begin() + nt), order, level_begin);
     if (multi) {
       // timing records are in s_memrealtime ticks (100 MHz): 6 us per launch
-      build_stream_program(ds->tree, ds->plan, dur, 600.0, prog);
+      build_stream_program(ds->tree, ds->plan, dur, 600.0, true, prog);
     }
   } catch (const std::exception&) {
     return HM_ERR_INTERNAL;
@@ -978,12 +1021,14 @@ hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_appro
   ds->order = order;
   ds->ms_valid = false;
   if (multi) {
+    const size_t no = prog.order.size();   // factor and data-solve tasks
+    if (no != (size_t)nt + (size_t)nf) return HM_ERR_INTERNAL;
     if (!ds->d_morder) {
       void* q = nullptr;
-      TRY(dev_alloc(ds, sizeof(int32_t) * (size_t)nt, &q));
+      TRY(dev_alloc(ds, sizeof(int32_t) * no, &q));
       ds->d_morder = (int32_t*)q;
     }
-    HIPTRY(hipMemcpy(ds->d_morder, prog.order.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+    HIPTRY(hipMemcpy(ds->d_morder, prog.order.data(), sizeof(int32_t) * no, hipMemcpyHostToDevice));
     for (int s = 0; s < MS_STREAMS - 1; ++s)
       if (!ds->xs[s]) HIPTRY(hipStreamCreateWithFlags(&ds->xs[s], hipStreamNonBlocking));
     const size_t nev = (size_t)prog.nevents + MS_STREAMS;

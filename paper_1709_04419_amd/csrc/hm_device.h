@@ -141,6 +141,9 @@ hipError_t launch_permute(const double* Z, const int64_t* perm, int64_t n, int r
 hipError_t launch_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z, hipStream_t st);
 // Forward solve L v = Z (Z permuted into W, then the solve task levels
 // slevel_begin[0 .. nslev]), log-determinant and v^T v into out.
+// log-det and v^T v sums of an already solved W (the data solve ran inside
+// the factorisation's stream program).
+hipError_t launch_solve_reduce(const DevData& D, const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st);
 hipError_t launch_solve(const DevData& D, const double* Z, const int64_t* perm, const int32_t* slevel_begin,
                         int32_t nslev, int max_grid, const int32_t* diag_ids, int32_t ndiag, double* out,
                         hipStream_t st);

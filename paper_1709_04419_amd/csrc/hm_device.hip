@@ -2653,15 +2653,18 @@ __device__ void run_task(const DevData& D, int32_t t, double* slot, double* dyn,
   const int32_t prog = D.task_prog[t];
   int64_t ts = 0;
   if (threadIdx.x == 0) { S.flops = 0.0; S.ph[0] = S.ph[1] = S.ph[2] = S.ph[3] = S.ph[4] = 0; }
-  if (D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
+  // per-task records exist for the factorisation's tasks only (ids below
+  // D.ntasks; the stream program's data-solve tasks follow them)
+  const bool rec = t < D.ntasks;
+  if (rec && D.task_times && threadIdx.x == 0) ts = (int64_t)__builtin_amdgcn_s_memrealtime();
   dispatch(D, tk, prog, slot, dyn, S);
   __syncthreads();
-  if (D.task_times && threadIdx.x == 0) {
+  if (rec && D.task_times && threadIdx.x == 0) {
     D.task_times[7 * t] = ts;
     D.task_times[7 * t + 1] = (int64_t)__builtin_amdgcn_s_memrealtime();
     for (int q = 0; q < 5; ++q) D.task_times[7 * t + 2 + q] = S.ph[q];
   }
-  if (D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
+  if (rec && D.task_flops && threadIdx.x == 0) D.task_flops[t] = S.flops;
 }
 
 // Level-synchronous executor: the tasks of one level have no dependencies
@@ -3046,6 +3049,11 @@ hipError_t launch_permute(const double* Z, const int64_t* perm, int64_t n, int r
 
 hipError_t launch_unpermute(const double* W, const int64_t* perm, int64_t n, int r, double* Z, hipStream_t st) {
   hipLaunchKernelGGL(k_unpermute, dim3(1024), dim3(NT), 0, st, W, perm, n, r, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_reduce(const DevData& D, const int32_t* diag_ids, int32_t ndiag, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, st, D, diag_ids, ndiag, D.W, D.r, out);
   return hipGetLastError();
 }
 

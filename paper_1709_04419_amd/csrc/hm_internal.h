@@ -95,6 +95,13 @@ struct hm_dataset {
   int32_t* d_morder = nullptr;
   hipStream_t xs[hm::MS_STREAMS - 1] = {};
   std::vector<hipEvent_t> mev;        // ms.nevents, then MS_STREAMS (fork / join)
+  // the program also runs the data's forward solve (tasks plan.ftasks after the
+  // factor tasks; combined task and program-index arrays on the device), and
+  // whether the last factorisation did so for the current data
+  bool ms_fused = false;
+  hm::Task* d_ctasks = nullptr;
+  int32_t* d_cprog = nullptr;
+  bool fused_solved = false;
 };
 
 namespace hm_int {

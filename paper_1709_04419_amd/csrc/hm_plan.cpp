@@ -209,10 +209,15 @@ struct Planner {
     for (int32_t i = leaf_rank[b]; i < leaf_rank[sub_end[b]]; ++i) out.push_back(P.sub_leaves[i]);
   }
 
+  // set while the fused data solve is emitted: negative dependencies then
+  // name factor tasks (-1 - id) rather than unfinished blocks
+  bool factor_deps_coded = false;
+
   int32_t new_task(int8_t kind, int32_t obj, std::vector<int32_t> deps, int32_t a0 = 0, int32_t a1 = 0) {
     std::sort(deps.begin(), deps.end());
     deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
-    if (!deps.empty() && deps.front() < 0) throw std::logic_error("dependency on an unfinished block");
+    if (!deps.empty() && deps.front() < 0 && !factor_deps_coded)
+      throw std::logic_error("dependency on an unfinished block");
     Task t{};
     t.kind = kind;
     t.obj = obj;
@@ -764,6 +769,41 @@ struct Planner {
     }
     P.prog_obj.resize(nt);
     for (int32_t i = 0; i < nt; ++i) P.prog_obj[i] = tasks[i].obj;
+    // the data's forward solve again, now depending on the factor tasks whose
+    // blocks it reads: final_task is re-coded as -1 - (task id) while it is
+    // emitted, so those dependencies are told apart from the solve's own
+    {
+      const std::vector<int32_t> saved = final_task;
+      // (a block without a final task decodes out of range, which the
+      // validation rejects)
+      for (int32_t& f : final_task) f = f >= 0 ? -1 - rank[f] : INT32_MIN;
+      tasks.clear();
+      tdeps.clear();
+      factor_deps_coded = true;
+      emit_solve(-1, 0, {}, true);
+      factor_deps_coded = false;
+      final_task = saved;
+      const int32_t nf = (int32_t)tasks.size();
+      P.ftasks.clear();
+      P.fdeps.clear();
+      for (int32_t i = 0; i < nf; ++i) {
+        Task t = tasks[i];
+        t.level = 0;
+        if (P.fdeps.size() + tdeps[i].size() > (size_t)INT32_MAX)
+          throw std::length_error("task graph: more dependencies than 32-bit offsets");
+        t.dep_begin = (int32_t)P.fdeps.size();
+        t.ndeps = (int32_t)tdeps[i].size();
+        for (int32_t d : tdeps[i]) {
+          if (d < 0) {
+            P.fdeps.push_back(-1 - d);
+          } else {
+            if (d >= i) throw std::logic_error("data solve dependency not earlier in program order");
+            P.fdeps.push_back(nt + d);
+          }
+        }
+        P.ftasks.push_back(t);
+      }
+    }
     // solve programs for every cluster
     const int32_t nc = (int32_t)T.cl.size();
     P.sop_begin.assign(nc + 1, 0);
@@ -910,6 +950,18 @@ static void validate(const Tree& T, const Plan& P) {
       }
     }
   }
+  // the data solve beside the factorisation: solve tasks on the data, each
+  // dependency a factor task or an earlier task of this list
+  for (size_t k = 0; k < P.ftasks.size(); ++k) {
+    const Task& t = P.ftasks[k];
+    if (t.obj != -1 || (t.kind != TASK_SOLVE_SEQ && t.kind != TASK_SOLVE_MV)) fail("fused solve task kind");
+    check_solve_task(T, t, fail);
+    if (t.dep_begin < 0 || t.ndeps < 0 || (size_t)t.dep_begin + t.ndeps > P.fdeps.size()) fail("fused solve deps");
+    for (int32_t q = 0; q < t.ndeps; ++q) {
+      const int32_t d = P.fdeps[t.dep_begin + q];
+      if (d < 0 || d >= nt + (int64_t)k) fail("fused solve dependency");
+    }
+  }
   int64_t covered = 0;
   for (int32_t q : P.apply_chunks) {
     if (q < 0 || q >= (int32_t)T.cl.size() || T.cl[q].begin != covered) fail("operator chunks");
@@ -1027,11 +1079,15 @@ namespace hm {
 // its class.  A task counts as finished when its launch ends (the event
 // granularity).  Launches are then issued in order of simulated start.
 void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double ovh,
-                          StreamProgram& out) {
-  const int32_t nt = (int32_t)p.tasks.size();
+                          bool fused, StreamProgram& out) {
+  const int32_t nfac = (int32_t)p.tasks.size();
+  const int32_t nt = nfac + (fused ? (int32_t)p.ftasks.size() : 0);
   if ((int32_t)dur.size() != nt) throw std::logic_error("one duration per task");
+  auto task = [&](int32_t i) -> const Task& { return i < nfac ? p.tasks[i] : p.ftasks[i - nfac]; };
+  auto dep = [&](int32_t i, int32_t q) { return i < nfac ? p.deps[p.tasks[i].dep_begin + q]
+                                                       : p.fdeps[p.ftasks[i - nfac].dep_begin + q]; };
   std::vector<int8_t> cls(nt, 0);
-  for (int32_t i = 0; i < nt; ++i) {
+  for (int32_t i = 0; i < nfac; ++i) {
     const Task& tk = p.tasks[i];
     if (tk.kind == TASK_TS_A || tk.kind == TASK_TS_B || tk.kind == TASK_TS_C) {
       cls[i] = 1;
@@ -1040,14 +1096,15 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
       if (std::max(b.m, b.n) > MS_LONG_ROWS) cls[i] = 2;
     }
   }
-  std::vector<int32_t> sbeg(nt + 1, 0), succ(p.deps.size());
+  std::vector<int32_t> sbeg(nt + 1, 0);
   for (int32_t i = 0; i < nt; ++i)
-    for (int32_t q = 0; q < p.tasks[i].ndeps; ++q) ++sbeg[p.deps[p.tasks[i].dep_begin + q] + 1];
+    for (int32_t q = 0; q < task(i).ndeps; ++q) ++sbeg[dep(i, q) + 1];
   for (int32_t i = 0; i < nt; ++i) sbeg[i + 1] += sbeg[i];
+  std::vector<int32_t> succ(sbeg[nt]);
   {
     std::vector<int32_t> fill(sbeg.begin(), sbeg.end() - 1);
     for (int32_t i = 0; i < nt; ++i)
-      for (int32_t q = 0; q < p.tasks[i].ndeps; ++q) succ[fill[p.deps[p.tasks[i].dep_begin + q]]++] = i;
+      for (int32_t q = 0; q < task(i).ndeps; ++q) succ[fill[dep(i, q)]++] = i;
   }
   std::vector<double> d(nt), tail(nt, 0.0);
   for (int32_t i = 0; i < nt; ++i) d[i] = std::max(0.0, dur[i]);
@@ -1074,7 +1131,7 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
     }
   };
   for (int32_t i = 0; i < nt; ++i) {
-    need[i] = p.tasks[i].ndeps;
+    need[i] = task(i).ndeps;
     if (!need[i]) ready(i);
   }
   using Ev = std::pair<double, int32_t>;   // (end time, launch id)
@@ -1169,8 +1226,8 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
     // per other stream, the latest launch this one depends on
     int32_t need_from[MS_STREAMS] = {-1, -1, -1, -1};
     for (int32_t i : L.tasks)
-      for (int32_t q = 0; q < p.tasks[i].ndeps; ++q) {
-        const int32_t u = p.deps[p.tasks[i].dep_begin + q];
+      for (int32_t q = 0; q < task(i).ndeps; ++q) {
+        const int32_t u = dep(i, q);
         const int32_t lu = launch_of[u];
         const int su = out.launches[lu].stream;
         if (lu >= (int32_t)k) throw std::logic_error("stream program: dependency issued later");
@@ -1193,12 +1250,16 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
   double end = 0.0;
   for (const Sim& L : sims) end = std::max(end, L.end);
   out.modelled_seconds = end;
-  validate_stream_program(p, out);
+  validate_stream_program(p, out, fused);
 }
 
-void validate_stream_program(const Plan& p, const StreamProgram& g) {
+void validate_stream_program(const Plan& p, const StreamProgram& g, bool fused) {
   auto fail = [](const char* what) { throw std::logic_error(what); };
-  const int32_t nt = (int32_t)p.tasks.size();
+  const int32_t nfac = (int32_t)p.tasks.size();
+  const int32_t nt = nfac + (fused ? (int32_t)p.ftasks.size() : 0);
+  auto task = [&](int32_t i) -> const Task& { return i < nfac ? p.tasks[i] : p.ftasks[i - nfac]; };
+  auto dep = [&](int32_t i, int32_t q) { return i < nfac ? p.deps[p.tasks[i].dep_begin + q]
+                                                       : p.fdeps[p.ftasks[i - nfac].dep_begin + q]; };
   if ((int32_t)g.order.size() != nt) fail("stream program: order is not a permutation");
   std::vector<int32_t> launch_of(nt, -1);
   for (size_t k = 0; k < g.launches.size(); ++k) {
@@ -1235,8 +1296,8 @@ void validate_stream_program(const Plan& p, const StreamProgram& g) {
     }
     for (int32_t q = M.t0; q < M.t1; ++q) {
       const int32_t i = g.order[q];
-      for (int32_t r = 0; r < p.tasks[i].ndeps; ++r) {
-        const int32_t u = p.deps[p.tasks[i].dep_begin + r];
+      for (int32_t r = 0; r < task(i).ndeps; ++r) {
+        const int32_t u = dep(i, r);
         const int32_t lu = launch_of[u];
         if (lu >= (int32_t)k) fail("stream program: dependency not in an earlier launch");
         const int su = g.launches[lu].stream;

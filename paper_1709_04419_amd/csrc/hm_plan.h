@@ -155,6 +155,11 @@ struct Tree {
 };
 
 struct Plan {
+  // the forward solve of the data as tasks that depend on the factor tasks they
+  // read (ids: factor tasks 0 .. tasks.size()-1, then these from tasks.size()),
+  // in program order; run inside the stream program, beside the factorisation
+  std::vector<Task> ftasks;
+  std::vector<int32_t> fdeps;
   // storage
   std::vector<int64_t> dense_off;   // block id -> offset (doubles) in dense pool, -1 otherwise
   std::vector<int64_t> lr_off;      // block id -> offset of U (m x cap), then V (n x cap), cap = lr_cap
@@ -234,9 +239,12 @@ struct StreamProgram {
   int32_t nevents = 0;
   double modelled_seconds = 0;   // makespan of the simulation that built it
 };
+// Tasks of the program: the factorisation's (p.tasks) and, when fused, the
+// data solve's (p.ftasks, ids from p.tasks.size(); they run on stream 0); dur
+// holds one duration per task of the program.
 void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double launch_overhead,
-                          StreamProgram& out);
+                          bool fused, StreamProgram& out);
 // Throws std::logic_error if a dependency is not met as stated above.
-void validate_stream_program(const Plan& p, const StreamProgram& g);
+void validate_stream_program(const Plan& p, const StreamProgram& g, bool fused);
 
 }  // namespace hm

@@ -493,6 +493,7 @@ hm_status hm_server_submit(hm_server* sv, hm_dataset* ds, const hm_theta* theta,
   q->ap = *approx;
   q->r = ds->r;
   q->t_submit = Clock::now();
+  ds->fused_solved = false;   // the served solve overwrites the solve buffer
   std::lock_guard<std::mutex> lk(sv->mu);
   if (sv->failed != HM_OK || sv->stop) {
     delete q;

@@ -193,3 +193,30 @@ def fit_many(server, datasets: List, theta0s, nugget: float,
                 out[i] = _estimate(stop.value, nugget, fit_nugget)
         live = still
     return out
+
+
+def gradient(ds, theta, nugget: float, eps: float = 1e-7, rank: int = 0, h: float = 1e-4,
+             fit_nugget: bool = False, loglik_kw: dict = None) -> np.ndarray:
+    """Gradient of L~ (summed over the columns of Z) with respect to log theta
+    (and log tau^2 with fit_nugget), by central differences of step h in the
+    log parameters: 2 d evaluations of the device likelihood.  The paper names
+    the gradient as an extension (Section 6) without giving a method; this is
+    the plain numerical one (truncation error O(h^2), rounding error about
+    |L~| u / h, and the H-approximation error of L~ divided by h)."""
+    lk = loglik_kw or {}
+    x0 = _start(theta, nugget, fit_nugget)
+    g = np.empty_like(x0)
+    for i in range(x0.size):
+        vals = []
+        for sgn in (1.0, -1.0):
+            x = x0.copy()
+            x[i] += sgn * h
+            pt = _point(x, nugget, fit_nugget)
+            if pt is None:
+                raise ValueError("gradient: a difference point is outside the parameter domain")
+            r = ds.loglik(pt[0], pt[1], eps, rank, **lk)
+            if int(r["status"][0]) != 0:
+                raise ValueError("gradient: the factorisation broke down at a difference point")
+            vals.append(float(np.sum(r["loglik"])))
+        g[i] = (vals[0] - vals[1]) / (2.0 * h)
+    return g

@@ -4,7 +4,9 @@ instructions with FP32 accumulation, dense leaves / log-determinant /
 recompressions in FP64, and C~^{-1} Z refined iteratively in FP64.
 
   * the refinement converges: the relative residual ||Z - C~ x|| / ||Z|| of
-    every column reaches refine_tol within refine_max_iter corrections;
+    every column reaches refine_tol (or the FP64 rounding floor of the
+    residual, u ||C|| ||x|| / ||Z||, where that is larger) within
+    refine_max_iter corrections;
   * the error against the FP64 oracle (the dense likelihood, eq. 1) respects
     Theorem 1 (Section 3.2) with eps_inv = ||I - (L~ L~^T)^{-1} C||_2 of the
     mixed factor, computed densely here;
@@ -57,7 +59,12 @@ def test_mixed_against_fp64_and_theorem1(H, ctx, case):
     assert int(f["status"][0]) == 0 and int(m["status"][0]) == 0
     for k in ("loglik", "logdet", "quadform", "refine_quad", "refine_resid"):
         assert np.array_equal(m[k], m2[k])
-    assert m["refine_resid"][0] <= 1e-13 and 1 <= int(m["refine_iters"][0]) <= 20
+    # the residual Z - C~ x is formed in FP64: below u ||C|| ||x|| / ||Z|| it is
+    # rounding (a dense LAPACK solve of the smooth uniform4000 case leaves
+    # 7.8e-13), so the target is refine_tol or that floor, whichever is larger
+    x = np.linalg.solve(C, Z)
+    floor = np.finfo(np.float64).eps * np.linalg.norm(C, 2) * np.linalg.norm(x) / np.linalg.norm(Z)
+    assert m["refine_resid"][0] <= max(1e-13, floor) and 1 <= int(m["refine_iters"][0]) <= 20
     d_logdet = abs(m["logdet"][0] - f["logdet"][0]) / abs(f["logdet"][0])
     d_ll = abs(m["loglik"][0] - f["loglik"][0]) / abs(f["loglik"][0])
     d_quad = abs(m["refine_quad"][0] - f["quadform"][0]) / abs(f["quadform"][0])

@@ -82,3 +82,31 @@ def test_mle_fitted_nugget_matches_dense_oracle():
     l_at_g = float(dense_loglik(P, Z, g["theta"], g["nugget"])[0][0])
     assert abs(l_at_g - (-ref["f"])) <= 1e-6 * abs(ref["f"])
     np.testing.assert_allclose(list(g["theta"]) + [g["nugget"]], np.exp(ref["x"]), rtol=5e-2)
+
+
+def test_gradient_matches_dense_oracle():
+    # central differences in log theta of the device likelihood against the same
+    # differences of the dense likelihood (eq. 1); and near the maximiser the
+    # gradient vanishes to the differencing error
+    from paper_1709_04419_amd import hmlik, mle
+    P, Z = _data(300, 51)
+    ctx = hmlik.Context(0)
+    try:
+        ds = hmlik.Dataset(ctx, P, 32, 2.0)
+        ds.set_z(Z)
+        g = mle.gradient(ds, THETA0, NUGGET, eps=1e-10, h=1e-4)
+        fit = mle.fit(ds, THETA0, NUGGET, eps=1e-10, **KW)
+        g_at = mle.gradient(ds, fit["theta"], NUGGET, eps=1e-10, h=1e-4)
+    finally:
+        ctx.close()
+    ref = np.empty(3)
+    for i in range(3):
+        v = []
+        for s in (1.0, -1.0):
+            x = np.log(np.asarray(THETA0))
+            x[i] += s * 1e-4
+            v.append(float(dense_loglik(P, Z, tuple(np.exp(x)), NUGGET)[0][0]))
+        ref[i] = (v[0] - v[1]) / 2e-4
+    # the H-approximation error of L~ at eps 1e-10 (about 1e-7 here) enters divided by 2h
+    np.testing.assert_allclose(g, ref, rtol=1e-4, atol=5e-3)
+    assert np.max(np.abs(g_at)) <= 1e-2 * np.max(np.abs(g))

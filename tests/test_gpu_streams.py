@@ -3,7 +3,13 @@ stream program: the big blocks' flush steps, the long low-rank flushes and the
 rest on their own streams, cross-stream dependencies as events).  Every task
 runs on the same inputs as in the level schedule, so the evaluation is
 bitwise equal before and after tuning, with and without the extra streams,
-and over repeated evaluations; and it still agrees with the oracle."""
+and over repeated evaluations; and it still agrees with the oracle.
+
+The stream program also runs the data's forward solve beside the
+factorisation (hm_solve then only sums); the solve tasks and their order of
+accumulation are those of the separate solve, so the results stay bitwise
+equal, also for several columns, in the mixed form, for data replaced after
+the factorisation and for a second solve of the same factor."""
 import os
 
 import numpy as np
@@ -48,3 +54,53 @@ def test_stream_program_is_bitwise_equal(n, leaf):
     if n <= 3000:
         ref = h_loglik(P, Z, THETA, NUGGET, n_min=leaf, eta=2.0, eps=EPS)
         assert abs(base[0] - float(ref["loglik"][0])) <= 1e-10 * abs(float(ref["loglik"][0]))
+
+
+def test_fused_solve_edge_cases():
+    from paper_1709_04419_amd import hmlik
+    n, leaf = 6000, 64
+    P = wl.basin_clusters(n, 43)
+    Z3 = wl.standard_normal(n, 3, 44)
+    Z1 = wl.standard_normal(n, 1, 45)
+    ctx = hmlik.Context(0)
+    try:
+        ref = hmlik.Dataset(ctx, P, leaf, 2.0)   # never tuned: separate solve
+        ds = hmlik.Dataset(ctx, P, leaf, 2.0)
+        ds.set_z(Z1)
+        ds.tune_schedule(THETA, NUGGET, EPS)
+        assert ds.info()["nlevels"] > 0
+
+        def both(Z, **kw):
+            ref.set_z(Z)
+            ds.set_z(Z)
+            a = ref.loglik(THETA, NUGGET, EPS, **kw)
+            b = ds.loglik(THETA, NUGGET, EPS, **kw)
+            return a, b
+
+        # several columns
+        a, b = both(Z3)
+        for k in ("loglik", "logdet", "quadform"):
+            assert np.array_equal(a[k], b[k]), k
+        # mixed form: the refinement reuses the solve buffer after the sums
+        a, b = both(Z1, prec=hmlik.HM_MIXED, refine_max_iter=8, refine_tol=1e-12)
+        assert int(a["status"][0]) == int(b["status"][0])
+        if int(a["status"][0]) == 0:
+            for k in ("loglik", "logdet", "quadform"):
+                assert np.array_equal(a[k], b[k]), k
+        # data replaced between factorisation and solve: the solve runs again
+        ds.set_z(Z3)
+        ref.set_z(Z3)
+        ds.assemble(THETA, NUGGET, EPS)
+        ref.assemble(THETA, NUGGET, EPS)
+        assert ds.factor() == 0 and ref.factor() == 0
+        ds.set_z(Z1)
+        ref.set_z(Z1)
+        s1, r1 = ds.solve(), ref.solve()
+        # and a second solve of the same factor and data
+        s2, r2 = ds.solve(), ref.solve()
+        for k in ("loglik", "logdet", "quadform"):
+            assert np.array_equal(s1[k], r1[k]), k
+            assert np.array_equal(s2[k], r2[k]), k
+            assert np.array_equal(s1[k], s2[k]), k
+    finally:
+        ctx.close()

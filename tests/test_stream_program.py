@@ -1,9 +1,11 @@
 """CPU checks of the multi-stream factorisation schedule (hm_plan.cpp:
 build_stream_program / validate_stream_program), compiled into a small host
 harness: for the task graph of a real point set and seeded random durations,
-the program covers every task once, every dependency is met by an earlier
+with and without the data's forward solve beside the factorisation, the
+program covers every task once, every dependency is met by an earlier
 launch of the same stream or by a wait on an event recorded after it, and the
-validator rejects programs with a wait removed or two launches swapped."""
+validator rejects programs with a wait removed, two launches swapped or a
+data-solve task moved ahead of the factor tasks it reads."""
 import json
 import os
 import shutil
@@ -24,43 +26,64 @@ HARNESS = r"""
 #include <stdexcept>
 #include <vector>
 using namespace hm;
-static bool rejects(const Plan& p, const StreamProgram& g) {
-  try { validate_stream_program(p, g); } catch (const std::logic_error&) { return true; }
+static bool rejects(const Plan& p, const StreamProgram& g, bool fused) {
+  try { validate_stream_program(p, g, fused); } catch (const std::logic_error&) { return true; }
   return false;
 }
 int main(int argc, char** argv) {
   FILE* f = fopen(argv[1], "rb");
   long n = atol(argv[2]);
   int leaf = atoi(argv[3]);
+  const bool fused = atoi(argv[5]) != 0;
   std::vector<double> P(2 * n);
   if (fread(P.data(), 8, 2 * n, f) != (size_t)(2 * n)) return 1;
   fclose(f);
   Tree t; build_tree(P.data(), n, leaf, 2.0, t);
   Plan p; build_plan(t, p);
-  const int nt = (int)p.tasks.size();
+  const int nfac = (int)p.tasks.size();
+  const int nt = nfac + (fused ? (int)p.ftasks.size() : 0);
   std::mt19937_64 rng(atoi(argv[4]));
   std::exponential_distribution<double> ex(1.0);
   std::vector<double> dur(nt);
   for (int i = 0; i < nt; ++i) dur[i] = 100.0 * ex(rng);
   StreamProgram g;
-  build_stream_program(t, p, dur, 1.0, g);
-  int per[MS_STREAMS] = {0}, waits_total = 0, dropped_ok = 0, dropped_tried = 0;
-  for (auto& L : g.launches) { per[L.stream]++; waits_total += L.nwait; }
+  build_stream_program(t, p, dur, 1.0, fused, g);
+  int per[MS_STREAMS] = {0}, waits_total = 0, dropped_ok = 0, dropped_tried = 0, fused_launches = 0;
+  for (auto& L : g.launches) {
+    per[L.stream]++;
+    waits_total += L.nwait;
+    for (int32_t q = L.t0; q < L.t1; ++q)
+      if (g.order[q] >= nfac) { fused_launches += 1; break; }
+  }
   for (size_t k = 0; k < g.launches.size() && dropped_tried < 20; ++k)
     if (g.launches[k].nwait > 0) {
       StreamProgram b = g; b.launches[k].nwait -= 1; ++dropped_tried;
-      dropped_ok += rejects(p, b);
+      dropped_ok += rejects(p, b, fused);
     }
   // swap two adjacent launches of one stream that depend on each other
   int swapped_rejected = -1;
   for (size_t k = 0; k + 1 < g.launches.size() && swapped_rejected < 0; ++k) {
     StreamProgram b = g;
     std::swap(b.launches[k], b.launches[k + 1]);
-    if (rejects(p, b)) swapped_rejected = 1;
+    if (rejects(p, b, fused)) swapped_rejected = 1;
   }
-  printf("{\"tasks\": %d, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d], \"waits\": %d, \"events\": %d, "
-         "\"dropped_tried\": %d, \"dropped_rejected\": %d, \"swap_rejected\": %d}\n", nt, g.launches.size(),
-         per[0], per[1], per[2], per[3], waits_total, g.nevents, dropped_tried, dropped_ok, swapped_rejected);
+  // the first data-solve task moved ahead of every factor task: its factor
+  // dependencies are then unmet
+  int early_rejected = -1;
+  if (fused) {
+    StreamProgram b = g;
+    for (size_t q = 0; q < b.order.size(); ++q)
+      if (b.order[q] >= nfac) {
+        std::swap(b.order[0], b.order[q]);
+        break;
+      }
+    early_rejected = rejects(p, b, fused) ? 1 : 0;
+  }
+  printf("{\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d], "
+         "\"waits\": %d, \"events\": %d, \"dropped_tried\": %d, \"dropped_rejected\": %d, \"swap_rejected\": %d, "
+         "\"early_rejected\": %d, \"fused_launches\": %d}\n", nt, nfac, g.order.size(), g.launches.size(),
+         per[0], per[1], per[2], per[3], waits_total, g.nevents, dropped_tried, dropped_ok, swapped_rejected,
+         early_rejected, fused_launches);
   return 0;
 }
 """
@@ -79,17 +102,26 @@ def harness(tmp_path_factory):
     return d, exe
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("n,leaf,seed", [(3000, 32, 1), (12000, 64, 2)])
-def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed):
+def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed, fused):
     d, exe = harness
     pts = d / f"p{n}.bin"
     wl.basin_clusters(n, 41).astype(np.float64).tofile(pts)
-    out = subprocess.run([str(exe), str(pts), str(n), str(leaf), str(seed)], capture_output=True, text=True,
-                         timeout=600, check=True)
+    out = subprocess.run([str(exe), str(pts), str(n), str(leaf), str(seed), str(int(fused))], capture_output=True,
+                         text=True, timeout=600, check=True)
     r = json.loads(out.stdout.strip().splitlines()[-1])
+    assert r["order"] == r["tasks"]
     assert sum(r["per_stream"]) == r["launches"]
     assert r["per_stream"][0] > 0 and r["per_stream"][2] + r["per_stream"][3] > 0
     assert r["waits"] > 0 and r["events"] > 0
     # every wait the builder emits is needed: removing any one breaks a dependency
     assert r["dropped_tried"] > 0 and r["dropped_rejected"] == r["dropped_tried"]
     assert r["swap_rejected"] == 1
+    if fused:
+        # the data solve's tasks are in the program, in launches of their own
+        # or beside factor tasks, and may not run before the blocks they read
+        assert r["tasks"] > r["factor_tasks"] and r["fused_launches"] > 0
+        assert r["early_rejected"] == 1
+    else:
+        assert r["tasks"] == r["factor_tasks"] and r["fused_launches"] == 0
