@@ -158,26 +158,37 @@ hm_status hm_dataset_set_z(hm_dataset *ds, const double *Z, int32_t r, int32_t o
 hm_status hm_assemble(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx);
 
 /* H-Cholesky of the assembled matrix, in place (Sect. 3.2).  Returns
- * HM_ERR_NOT_SPD on a non-positive pivot (the factor then holds NaNs). */
+ * HM_ERR_NOT_SPD on a non-positive pivot (the factor then holds NaNs).  On a
+ * dataset with a stream program (hm_tune_schedule) the program also runs the
+ * forward solve L~ v = Z of the current Z beside the factorisation. */
 hm_status hm_factor(hm_dataset *ds);
 
 /* Forward solve L~ v = Z, log-determinant and eq. (4) for every column of Z;
- * out has r entries. */
+ * out has r entries.  If the last hm_factor already solved for the current Z
+ * (and no hm_dataset_set_z, hm_assemble or earlier hm_solve came between),
+ * only the sums remain; the results are bitwise the same either way. */
 hm_status hm_solve(hm_dataset *ds, hm_result *out);
 
 /* hm_assemble + hm_factor + hm_solve. out has r entries. */
 hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx, hm_result *out);
 
-/* Schedule tuning: runs one evaluation at theta (assembly and factorisation,
- * with per-task timing), then rebuilds the factorisation's levels from the
- * timed durations: each level is led by the ready task with the longest timed
- * chain to the end, takes every ready task that would lengthen the schedule if
- * deferred, and every other ready task no longer than the level already is;
- * longer tasks run first within a level.  Later factorisations of the dataset,
- * at any theta, use the new assignment; they run the same tasks on the same
- * inputs, so results are bitwise unchanged.  Returns the evaluation's status
- * (on HM_ERR_NOT_SPD the schedule is left as it was).  Allocates the timing
- * records on first use. */
+/* Schedule tuning (Z must be set): runs one evaluation at theta (assembly and
+ * factorisation, with per-task timing), then rebuilds the factorisation's
+ * levels from the timed durations: each level is led by the ready task with the
+ * longest timed chain to the end, takes every ready task that would lengthen
+ * the schedule if deferred, and every other ready task no longer than the
+ * level already is; longer tasks run first within a level.  From the same
+ * durations it builds a stream program that later factorisations run instead:
+ * the big blocks' flush steps, the long low-rank flushes and the other tasks
+ * (with the data's forward solve) on streams of their own, ordered by events.
+ * Six streams if the HIP runtime has at least 7 hardware queues
+ * (GPU_MAX_HW_QUEUES, read when HIP initialises: streams sharing a queue run
+ * one after the other), else four; the environment variable HMLIK_STREAMS = 1,
+ * 4 or 6 overrides (1: the levels on the context's stream only).  Later
+ * factorisations of the dataset, at any theta, use the new schedule; they run
+ * the same tasks on the same inputs, so results are bitwise unchanged.
+ * Returns the evaluation's status (on HM_ERR_NOT_SPD the schedule is left as
+ * it was).  Allocates the timing records on first use. */
 hm_status hm_tune_schedule(hm_dataset *ds, const hm_theta *theta, const hm_approx *approx);
 
 /* Batched evaluation of eq. (4) (Monte-Carlo replicates, several theta on
@@ -198,8 +209,8 @@ hm_status hm_loglik_batch(hm_ctx *ctx, int32_t m, hm_dataset *const *ds, const h
 /* Introspection: sizes of the trees and of the factorisation's task graph.
  * nlevels is the number of executor kernel launches per factorisation of the
  * schedule in use: the dependency levels of the graph (longest path, or as
- * rebuilt by hm_tune_schedule), or the launches of the four-stream program
- * that hm_tune_schedule builds (those overlap in time).  Any pointer may be
+ * rebuilt by hm_tune_schedule), or the launches of the stream program that
+ * hm_tune_schedule builds (those overlap in time).  Any pointer may be
  * NULL (that value is not written). */
 hm_status hm_dataset_info(const hm_dataset *ds, int64_t *n, int64_t *nclusters, int64_t *nblocks,
                           int64_t *ntasks, int64_t *nlevels);

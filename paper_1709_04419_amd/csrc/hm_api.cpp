@@ -700,10 +700,33 @@ static hm_status finish_factor(hm_dataset* ds) {
 }
 
 // Work-groups and workspace slots of each stream of the stream program
-// (disjoint slot ranges within the context's NSLOTS).
-static const int32_t MS_GRID[MS_STREAMS] = {256, 128, 64, 64};
-static const int32_t MS_SLOT_BASE[MS_STREAMS] = {0, 256, 384, 448};
-static_assert(MS_STREAMS == 4 && 448 + 64 <= NSLOTS, "stream slot ranges");
+// (disjoint slot ranges within the context's NSLOTS).  Four streams: the
+// general levels 256, the big-block flush steps 128, the two wave streams 64
+// each.  Six: streams 0 and 4 (general levels) 128 each, 1 and 5 (flush
+// steps) and 2, 3 (waves) 64 each.
+static const int32_t MS_GRID4[4] = {256, 128, 64, 64};
+static const int32_t MS_SLOT_BASE4[4] = {0, 256, 384, 448};
+static const int32_t MS_GRID6[MS_STREAMS] = {128, 64, 64, 64, 128, 64};
+static const int32_t MS_SLOT_BASE6[MS_STREAMS] = {0, 128, 192, 256, 320, 448};
+static_assert(MS_STREAMS == 6 && 448 + 64 <= NSLOTS, "stream slot ranges");
+
+// Streams of the program hm_tune_schedule builds: HMLIK_STREAMS (1, 4 or 6)
+// if set; otherwise six when the HIP runtime was given enough hardware queues
+// for them (GPU_MAX_HW_QUEUES >= 7: one per stream and one for the default
+// stream; streams that share a hardware queue run their work in issue order,
+// which costs more than the extra streams gain), else four.  1: the
+// level-synchronous schedule on the caller's stream.
+static int program_streams() {
+  if (const char* v = getenv("HMLIK_SINGLE_STREAM")) {
+    if (*v) return 1;
+  }
+  if (const char* v = getenv("HMLIK_STREAMS")) {
+    const int k = atoi(v);
+    if (k == 1 || k == 4 || k == MS_STREAMS) return k;
+  }
+  const char* q = getenv("GPU_MAX_HW_QUEUES");
+  return (q && atoi(q) >= MS_STREAMS + 1) ? MS_STREAMS : 4;
+}
 
 // Issues the factorisation's stream program: the extra streams first wait for
 // the work already on st (the assembly), each launch waits for its events and
@@ -713,26 +736,31 @@ static hipError_t launch_stream_program(hm_dataset* ds, const DevData& D, hipStr
   hipEvent_t* fork = &ds->mev[g.nevents];
   DevData Dm = D;
   Dm.order = ds->d_morder;
-  hipStream_t sx[MS_STREAMS] = {st, ds->xs[0], ds->xs[1], ds->xs[2]};
+  const int ns = g.nstreams;
+  const int32_t* grid = ns == MS_STREAMS ? MS_GRID6 : MS_GRID4;
+  const int32_t* slot = ns == MS_STREAMS ? MS_SLOT_BASE6 : MS_SLOT_BASE4;
+  hipStream_t sx[MS_STREAMS];
+  sx[0] = st;
+  for (int s = 1; s < ns; ++s) sx[s] = ds->xs[s - 1];
   hipError_t e = hipEventRecord(fork[0], st);
-  for (int s = 1; s < MS_STREAMS && e == hipSuccess; ++s) e = hipStreamWaitEvent(sx[s], fork[0], 0);
+  for (int s = 1; s < ns && e == hipSuccess; ++s) e = hipStreamWaitEvent(sx[s], fork[0], 0);
   // HMLIK_PROGRESS=<launches>: synchronise every <launches> launches and
   // report progress on stderr (long factorisations; costs a sync per chunk)
   size_t chunk = 0;
   if (const char* v = getenv("HMLIK_PROGRESS")) chunk = (size_t)std::max(1, atoi(v));
   for (size_t k = 0; k < g.launches.size() && e == hipSuccess; ++k) {
     if (chunk && k > 0 && k % chunk == 0) {
-      for (int s = 0; s < MS_STREAMS && e == hipSuccess; ++s) e = hipStreamSynchronize(sx[s]);
+      for (int s = 0; s < ns && e == hipSuccess; ++s) e = hipStreamSynchronize(sx[s]);
       fprintf(stderr, "hmlik factor: launch %zu of %zu (streams)\n", k, g.launches.size());
     }
     const MSLaunch& M = g.launches[k];
     for (int32_t w = 0; w < M.nwait && e == hipSuccess; ++w)
       e = hipStreamWaitEvent(sx[M.stream], ds->mev[g.waits[M.wait_begin + w]], 0);
     if (e == hipSuccess)
-      e = launch_factor_range(Dm, M.t0, M.t1, MS_GRID[M.stream], MS_SLOT_BASE[M.stream], sx[M.stream]);
+      e = launch_factor_range(Dm, M.t0, M.t1, grid[M.stream], slot[M.stream], sx[M.stream]);
     if (e == hipSuccess && M.rec >= 0) e = hipEventRecord(ds->mev[M.rec], sx[M.stream]);
   }
-  for (int s = 1; s < MS_STREAMS && e == hipSuccess; ++s) {
+  for (int s = 1; s < ns && e == hipSuccess; ++s) {
     e = hipEventRecord(fork[s], sx[s]);
     if (e == hipSuccess) e = hipStreamWaitEvent(st, fork[s], 0);
   }
@@ -1007,12 +1035,13 @@ hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_appro
   }
   std::vector<int32_t> order, level_begin;
   StreamProgram prog;
-  const bool multi = !getenv("HMLIK_SINGLE_STREAM");
+  const int nstreams = program_streams();
+  const bool multi = nstreams > 1;
   try {
     schedule_by_durations(ds->plan, std::vector<double>(dur.begin(), dur.begin() + nt), order, level_begin);
     if (multi) {
       // timing records are in s_memrealtime ticks (100 MHz): 6 us per launch
-      build_stream_program(ds->tree, ds->plan, dur, 600.0, true, prog);
+      build_stream_program(ds->tree, ds->plan, dur, 600.0, true, nstreams, prog);
     }
   } catch (const std::exception&) {
     return HM_ERR_INTERNAL;
@@ -1029,7 +1058,7 @@ hm_status hm_tune_schedule(hm_dataset* ds, const hm_theta* theta, const hm_appro
       ds->d_morder = (int32_t*)q;
     }
     HIPTRY(hipMemcpy(ds->d_morder, prog.order.data(), sizeof(int32_t) * no, hipMemcpyHostToDevice));
-    for (int s = 0; s < MS_STREAMS - 1; ++s)
+    for (int s = 0; s < nstreams - 1; ++s)
       if (!ds->xs[s]) HIPTRY(hipStreamCreateWithFlags(&ds->xs[s], hipStreamNonBlocking));
     const size_t nev = (size_t)prog.nevents + MS_STREAMS;
     while (ds->mev.size() < nev) {

@@ -1079,7 +1079,8 @@ namespace hm {
 // its class.  A task counts as finished when its launch ends (the event
 // granularity).  Launches are then issued in order of simulated start.
 void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double ovh,
-                          bool fused, StreamProgram& out) {
+                          bool fused, int nstreams, StreamProgram& out) {
+  if (nstreams != 4 && nstreams != MS_STREAMS) throw std::logic_error("stream program: 4 or MS_STREAMS streams");
   const int32_t nfac = (int32_t)p.tasks.size();
   const int32_t nt = nfac + (fused ? (int32_t)p.ftasks.size() : 0);
   if ((int32_t)dur.size() != nt) throw std::logic_error("one duration per task");
@@ -1136,7 +1137,7 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
   }
   using Ev = std::pair<double, int32_t>;   // (end time, launch id)
   std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> ends;
-  double free_at[MS_STREAMS] = {0, 0, 0, 0};
+  double free_at[MS_STREAMS] = {};
   double now = 0.0;
   int32_t done = 0;
   while (done < nt) {
@@ -1150,8 +1151,9 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
       }
     }
     if (done == nt) break;
-    for (int a = 0; a < 2; ++a) {
-      if (free_at[a] > now || by_tail[a].empty()) continue;
+    for (int sa = 0; sa < nstreams; ++sa) {
+      const int a = MS_STREAM_CLASS[sa];
+      if (a > 1 || free_at[sa] > now || by_tail[a].empty()) continue;
       const double tmax = by_tail[a].rbegin()->first;
       double delta = d[by_tail[a].rbegin()->second];
       for (bool grew = true; grew;) {
@@ -1162,7 +1164,7 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
             grew = true;
           }
       }
-      Sim L{(int8_t)a, now, 0.0, {}};
+      Sim L{(int8_t)sa, now, 0.0, {}};
       for (auto it = by_tail[a].rbegin(); it != by_tail[a].rend() && it->first > tmax - delta; ++it)
         L.tasks.push_back(it->second);
       for (auto it = by_dur[a].begin(); it != by_dur[a].end() && it->first <= delta; ++it) L.tasks.push_back(it->second);
@@ -1175,12 +1177,12 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
         work += d[i];
       }
       L.end = now + std::max(delta, work / 256.0) + ovh;
-      free_at[a] = L.end;
+      free_at[sa] = L.end;
       ends.push({L.end, (int32_t)sims.size()});
       sims.push_back(std::move(L));
     }
-    for (int s = 2; s < MS_STREAMS && !waveq.empty(); ++s) {
-      if (free_at[s] > now) continue;
+    for (int s = 0; s < nstreams && !waveq.empty(); ++s) {
+      if (MS_STREAM_CLASS[s] != 2 || free_at[s] > now) continue;
       Sim L{(int8_t)s, now, 0.0, {}};
       double mx = 0.0, work = 0.0;
       for (int32_t i : waveq) {
@@ -1206,6 +1208,7 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
   for (size_t L = 0; L < sims.size(); ++L)
     for (int32_t i : sims[L].tasks) launch_of[i] = pos_of[L];
   out = StreamProgram{};
+  out.nstreams = nstreams;
   out.order.reserve(nt);
   out.launches.resize(ord.size());
   std::vector<int32_t> rec_of(ord.size(), -1);
@@ -1224,7 +1227,8 @@ void build_stream_program(const Tree& t, const Plan& p, const std::vector<double
     for (int32_t i : L.tasks) out.order.push_back(i);
     M.t1 = (int32_t)out.order.size();
     // per other stream, the latest launch this one depends on
-    int32_t need_from[MS_STREAMS] = {-1, -1, -1, -1};
+    int32_t need_from[MS_STREAMS];
+    for (int32_t& v : need_from) v = -1;
     for (int32_t i : L.tasks)
       for (int32_t q = 0; q < task(i).ndeps; ++q) {
         const int32_t u = dep(i, q);
@@ -1261,10 +1265,11 @@ void validate_stream_program(const Plan& p, const StreamProgram& g, bool fused) 
   auto dep = [&](int32_t i, int32_t q) { return i < nfac ? p.deps[p.tasks[i].dep_begin + q]
                                                        : p.fdeps[p.ftasks[i - nfac].dep_begin + q]; };
   if ((int32_t)g.order.size() != nt) fail("stream program: order is not a permutation");
+  if (g.nstreams < 1 || g.nstreams > MS_STREAMS) fail("stream program: stream count");
   std::vector<int32_t> launch_of(nt, -1);
   for (size_t k = 0; k < g.launches.size(); ++k) {
     const MSLaunch& M = g.launches[k];
-    if (M.stream < 0 || M.stream >= MS_STREAMS || M.t0 < 0 || M.t1 < M.t0 || M.t1 > nt) fail("stream program: launch");
+    if (M.stream < 0 || M.stream >= g.nstreams || M.t0 < 0 || M.t1 < M.t0 || M.t1 > nt) fail("stream program: launch");
     if (M.wait_begin < 0 || M.nwait < 0 || M.wait_begin + M.nwait > (int32_t)g.waits.size())
       fail("stream program: wait range");
     if (M.rec < -1 || M.rec >= g.nevents) fail("stream program: event");

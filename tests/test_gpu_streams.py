@@ -1,6 +1,7 @@
 """GPU test of the factorisation on several streams (hm_tune_schedule builds a
 stream program: the big blocks' flush steps, the long low-rank flushes and the
-rest on their own streams, cross-stream dependencies as events).  Every task
+rest on their own streams, cross-stream dependencies as events; four or six
+streams, forced here with HMLIK_STREAMS whatever the hardware queues).  Every task
 runs on the same inputs as in the level schedule, so the evaluation is
 bitwise equal before and after tuning, with and without the extra streams,
 and over repeated evaluations; and it still agrees with the oracle.
@@ -43,8 +44,14 @@ def test_stream_program_is_bitwise_equal(n, leaf):
         finally:
             del os.environ["HMLIK_SINGLE_STREAM"]
         single = _vals(ds.loglik(THETA, NUGGET, EPS))
-        ds.tune_schedule(THETA, NUGGET, EPS)
-        multi = [_vals(ds.loglik(THETA, NUGGET, EPS)) for _ in range(3)]
+        multi = []
+        for k in ("4", "6"):
+            os.environ["HMLIK_STREAMS"] = k
+            try:
+                ds.tune_schedule(THETA, NUGGET, EPS)
+            finally:
+                del os.environ["HMLIK_STREAMS"]
+            multi += [_vals(ds.loglik(THETA, NUGGET, EPS)) for _ in range(3)]
     finally:
         ctx.close()
     assert base[3] == 0
@@ -67,7 +74,11 @@ def test_fused_solve_edge_cases():
         ref = hmlik.Dataset(ctx, P, leaf, 2.0)   # never tuned: separate solve
         ds = hmlik.Dataset(ctx, P, leaf, 2.0)
         ds.set_z(Z1)
-        ds.tune_schedule(THETA, NUGGET, EPS)
+        os.environ["HMLIK_STREAMS"] = "6"
+        try:
+            ds.tune_schedule(THETA, NUGGET, EPS)
+        finally:
+            del os.environ["HMLIK_STREAMS"]
         assert ds.info()["nlevels"] > 0
 
         def both(Z, **kw):

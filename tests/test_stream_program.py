@@ -35,6 +35,7 @@ int main(int argc, char** argv) {
   long n = atol(argv[2]);
   int leaf = atoi(argv[3]);
   const bool fused = atoi(argv[5]) != 0;
+  const int nstreams = atoi(argv[6]);
   std::vector<double> P(2 * n);
   if (fread(P.data(), 8, 2 * n, f) != (size_t)(2 * n)) return 1;
   fclose(f);
@@ -47,8 +48,8 @@ int main(int argc, char** argv) {
   std::vector<double> dur(nt);
   for (int i = 0; i < nt; ++i) dur[i] = 100.0 * ex(rng);
   StreamProgram g;
-  build_stream_program(t, p, dur, 1.0, fused, g);
-  int per[MS_STREAMS] = {0}, waits_total = 0, dropped_ok = 0, dropped_tried = 0, fused_launches = 0;
+  build_stream_program(t, p, dur, 1.0, fused, nstreams, g);
+  int per[MS_STREAMS] = {}, waits_total = 0, dropped_ok = 0, dropped_tried = 0, fused_launches = 0;
   for (auto& L : g.launches) {
     per[L.stream]++;
     waits_total += L.nwait;
@@ -79,11 +80,11 @@ int main(int argc, char** argv) {
       }
     early_rejected = rejects(p, b, fused) ? 1 : 0;
   }
-  printf("{\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d], "
+  printf("{\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d, %d, %d], "
          "\"waits\": %d, \"events\": %d, \"dropped_tried\": %d, \"dropped_rejected\": %d, \"swap_rejected\": %d, "
          "\"early_rejected\": %d, \"fused_launches\": %d}\n", nt, nfac, g.order.size(), g.launches.size(),
-         per[0], per[1], per[2], per[3], waits_total, g.nevents, dropped_tried, dropped_ok, swapped_rejected,
-         early_rejected, fused_launches);
+         per[0], per[1], per[2], per[3], per[4], per[5], waits_total, g.nevents, dropped_tried, dropped_ok,
+         swapped_rejected, early_rejected, fused_launches);
   return 0;
 }
 """
@@ -102,18 +103,25 @@ def harness(tmp_path_factory):
     return d, exe
 
 
+@pytest.mark.parametrize("nstreams", [4, 6])
 @pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("n,leaf,seed", [(3000, 32, 1), (12000, 64, 2)])
-def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed, fused):
+def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed, fused, nstreams):
     d, exe = harness
     pts = d / f"p{n}.bin"
     wl.basin_clusters(n, 41).astype(np.float64).tofile(pts)
-    out = subprocess.run([str(exe), str(pts), str(n), str(leaf), str(seed), str(int(fused))], capture_output=True,
-                         text=True, timeout=600, check=True)
+    out = subprocess.run([str(exe), str(pts), str(n), str(leaf), str(seed), str(int(fused)), str(nstreams)],
+                         capture_output=True, text=True, timeout=600, check=True)
     r = json.loads(out.stdout.strip().splitlines()[-1])
     assert r["order"] == r["tasks"]
     assert sum(r["per_stream"]) == r["launches"]
-    assert r["per_stream"][0] > 0 and r["per_stream"][2] + r["per_stream"][3] > 0
+    # general levels (0, and 4 of six), flush steps (1, and 5 of six), waves (2, 3)
+    ps = r["per_stream"]
+    assert ps[0] > 0 and ps[2] + ps[3] > 0
+    if nstreams == 4:
+        assert ps[4] == 0 and ps[5] == 0
+    else:
+        assert ps[4] > 0
     assert r["waits"] > 0 and r["events"] > 0
     # every wait the builder emits is needed: removing any one breaks a dependency
     assert r["dropped_tried"] > 0 and r["dropped_rejected"] == r["dropped_tried"]
