@@ -21,11 +21,68 @@ CSRC = os.path.join(ROOT, "paper_1709_04419_amd", "csrc")
 
 HARNESS = r"""
 #include "hm_plan.h"
+#include <algorithm>
 #include <cstdio>
 #include <random>
 #include <stdexcept>
 #include <vector>
 using namespace hm;
+// Leaf blocks a data-solve task reads: those of its cluster's solve program
+// (SOLVE_SEQ), or the leaves of the product's block a0 that meet the rows of
+// its row chunk, cluster a1 (SOLVE_MV).
+static void blocks_read(const Tree& t, const Plan& p, const Task& tk, std::vector<int32_t>& out) {
+  out.clear();
+  int64_t lo = 0, hi = t.n;
+  auto leaves = [&](int32_t b) {
+    for (int32_t i = p.sub_begin[b]; i < p.sub_end[b]; ++i) {
+      const Block& l = t.bk[p.sub_leaves[i]];
+      if (l.r0 < hi && l.r0 + l.m > lo) out.push_back(p.sub_leaves[i]);
+    }
+  };
+  if (tk.kind == TASK_SOLVE_SEQ) {
+    for (int32_t q = p.sop_begin[tk.a0]; q < p.sop_begin[tk.a0 + 1]; ++q) leaves(p.sops[q].blk);
+  } else {
+    lo = t.cl[tk.a1].begin;
+    hi = t.cl[tk.a1].end;
+    leaves(tk.a0);
+  }
+}
+// (fused task, block read) pairs whose last factor writer is not among the
+// task's ancestors; with factor_deps false the data solve's dependencies on
+// factor tasks are ignored (a control: the check must then find pairs).
+static long unmet_reads(const Tree& tr, const Plan& p, bool factor_deps) {
+  const int32_t nfac = (int32_t)p.tasks.size(), nf = (int32_t)p.ftasks.size();
+  // last writer of every block: the highest-ticket factor task that finishes
+  // or rewrites it (tasks writing one block are ordered by dependencies)
+  std::vector<int32_t> last(p.sub_begin.size(), -1);
+  for (int32_t i = 0; i < nfac; ++i) {
+    const Task& t = p.tasks[i];
+    if (t.kind == TASK_TERM || t.kind == TASK_TERM_ROWS || t.obj < 0) continue;
+    last[t.obj] = std::max(last[t.obj], i);
+  }
+  long unmet = 0;
+  std::vector<int32_t> reads, stack;
+  std::vector<char> seen(nfac + nf);
+  for (int32_t k = 0; k < nf; ++k) {
+    std::fill(seen.begin(), seen.end(), 0);
+    stack.assign(1, nfac + k);
+    while (!stack.empty()) {
+      const int32_t i = stack.back();
+      stack.pop_back();
+      const Task& t = i < nfac ? p.tasks[i] : p.ftasks[i - nfac];
+      for (int32_t q = 0; q < t.ndeps; ++q) {
+        const int32_t d = i < nfac ? p.deps[t.dep_begin + q] : p.fdeps[t.dep_begin + q];
+        if (i >= nfac && d < nfac && !factor_deps) continue;
+        if (!seen[d]) { seen[d] = 1; stack.push_back(d); }
+      }
+    }
+    blocks_read(tr, p, p.ftasks[k], reads);
+    for (int32_t b : reads)
+      if (last[b] >= 0 && !seen[last[b]]) ++unmet;
+  }
+  return unmet;
+}
+
 static bool rejects(const Plan& p, const StreamProgram& g, bool fused) {
   try { validate_stream_program(p, g, fused); } catch (const std::logic_error&) { return true; }
   return false;
@@ -80,7 +137,9 @@ int main(int argc, char** argv) {
       }
     early_rejected = rejects(p, b, fused) ? 1 : 0;
   }
-  printf("{\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d, %d, %d], "
+  const long unmet = fused ? unmet_reads(t, p, true) : -1, unmet_control = fused ? unmet_reads(t, p, false) : -1;
+  printf("{\"unmet_reads\": %ld, \"unmet_reads_control\": %ld, ", unmet, unmet_control);
+  printf("\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d, %d, %d], "
          "\"waits\": %d, \"events\": %d, \"dropped_tried\": %d, \"dropped_rejected\": %d, \"swap_rejected\": %d, "
          "\"early_rejected\": %d, \"fused_launches\": %d}\n", nt, nfac, g.order.size(), g.launches.size(),
          per[0], per[1], per[2], per[3], per[4], per[5], waits_total, g.nevents, dropped_tried, dropped_ok,
@@ -131,5 +190,9 @@ def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed, fused
         # or beside factor tasks, and may not run before the blocks they read
         assert r["tasks"] > r["factor_tasks"] and r["fused_launches"] > 0
         assert r["early_rejected"] == 1
+        # every block a data-solve task reads is finished by a factor task
+        # among its ancestors (and the check is not vacuous: without the
+        # factor dependencies it finds unmet reads)
+        assert r["unmet_reads"] == 0 and r["unmet_reads_control"] > 0
     else:
         assert r["tasks"] == r["factor_tasks"] and r["fused_launches"] == 0
