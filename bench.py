@@ -19,8 +19,8 @@ Prints one JSON line on stdout (progress goes to stderr).  `value` is evals/s
 with the dataset (locations, trees, task schedule, Z) resident on the device
 before timing starts.  Warm-up is at most one evaluation: by default it is the
 evaluation of hm_tune_schedule, which times every task and builds from those
-times the stream program the timed steps run (six streams: the bench gives
-the HIP runtime 8 hardware queues; results are unchanged;
+times the stream program the timed steps run (eight streams: the bench gives
+the HIP runtime 10 hardware queues; results are unchanged;
 --no-tune skips it and runs a plain warm-up evaluation instead, and the steps
 keep the longest-path levels on one stream).  Up to --steps evaluations are then
 timed, fewer if the next one would overrun the run's wall budget
@@ -232,10 +232,10 @@ def main():
     if args.form == "accuracy":
         return accuracy(args)
 
-    # the tuned factorisation runs on six streams (hm_tune_schedule): one
+    # the tuned factorisation runs on eight streams (hm_tune_schedule): one
     # hardware queue each, plus the default stream's
-    hwq = raise_hw_queues(7)
-    nstreams = 1 if args.no_tune else (6 if hwq >= 7 else 4)   # as hm_tune_schedule chooses
+    hwq = raise_hw_queues(9)
+    nstreams = 1 if args.no_tune else (8 if hwq >= 9 else 6 if hwq >= 7 else 4)   # as hm_tune_schedule chooses
     import numpy as np
     import torch
 

@@ -181,10 +181,10 @@ hm_status hm_loglik(hm_dataset *ds, const hm_theta *theta, const hm_approx *appr
  * durations it builds a stream program that later factorisations run instead:
  * the big blocks' flush steps, the long low-rank flushes and the other tasks
  * (with the data's forward solve) on streams of their own, ordered by events.
- * Six streams if the HIP runtime has at least 7 hardware queues
- * (GPU_MAX_HW_QUEUES, read when HIP initialises: streams sharing a queue run
- * one after the other), else four; the environment variable HMLIK_STREAMS = 1,
- * 4 or 6 overrides (1: the levels on the context's stream only).  Later
+ * Eight streams if the HIP runtime has at least 9 hardware queues, six from 7,
+ * else four (GPU_MAX_HW_QUEUES, read when HIP initialises: streams sharing a
+ * queue run one after the other); the environment variable HMLIK_STREAMS = 1,
+ * 4, 6 or 8 overrides (1: the levels on the context's stream only).  Later
  * factorisations of the dataset, at any theta, use the new schedule; they run
  * the same tasks on the same inputs, so results are bitwise unchanged.
  * Returns the evaluation's status (on HM_ERR_NOT_SPD the schedule is left as

@@ -703,18 +703,21 @@ static hm_status finish_factor(hm_dataset* ds) {
 // (disjoint slot ranges within the context's NSLOTS).  Four streams: the
 // general levels 256, the big-block flush steps 128, the two wave streams 64
 // each.  Six: streams 0 and 4 (general levels) 128 each, 1 and 5 (flush
-// steps) and 2, 3 (waves) 64 each.
+// steps) and 2, 3 (waves) 64 each.  Eight: streams 0, 4, 6 (general levels)
+// 80 each, 1, 5, 7 (flush steps) 48 each, 2, 3 (waves) 64 each.
 static const int32_t MS_GRID4[4] = {256, 128, 64, 64};
 static const int32_t MS_SLOT_BASE4[4] = {0, 256, 384, 448};
-static const int32_t MS_GRID6[MS_STREAMS] = {128, 64, 64, 64, 128, 64};
-static const int32_t MS_SLOT_BASE6[MS_STREAMS] = {0, 128, 192, 256, 320, 448};
-static_assert(MS_STREAMS == 6 && 448 + 64 <= NSLOTS, "stream slot ranges");
+static const int32_t MS_GRID6[6] = {128, 64, 64, 64, 128, 64};
+static const int32_t MS_SLOT_BASE6[6] = {0, 128, 192, 256, 320, 448};
+static const int32_t MS_GRID8[8] = {80, 48, 64, 64, 80, 48, 80, 48};
+static const int32_t MS_SLOT_BASE8[8] = {0, 80, 128, 192, 256, 336, 384, 464};
+static_assert(MS_STREAMS == 8 && 448 + 64 <= NSLOTS && 464 + 48 <= NSLOTS, "stream slot ranges");
 
-// Streams of the program hm_tune_schedule builds: HMLIK_STREAMS (1, 4 or 6)
-// if set; otherwise six when the HIP runtime was given enough hardware queues
-// for them (GPU_MAX_HW_QUEUES >= 7: one per stream and one for the default
-// stream; streams that share a hardware queue run their work in issue order,
-// which costs more than the extra streams gain), else four.  1: the
+// Streams of the program hm_tune_schedule builds: HMLIK_STREAMS (1, 4, 6 or
+// 8) if set; otherwise as many as the HIP runtime has hardware queues for
+// (GPU_MAX_HW_QUEUES: one per stream and one for the default stream; streams
+// that share a hardware queue run their work in issue order, which costs more
+// than the extra streams gain): 8 from 9 queues, 6 from 7, else 4.  1: the
 // level-synchronous schedule on the caller's stream.
 static int program_streams() {
   if (const char* v = getenv("HMLIK_SINGLE_STREAM")) {
@@ -722,10 +725,11 @@ static int program_streams() {
   }
   if (const char* v = getenv("HMLIK_STREAMS")) {
     const int k = atoi(v);
-    if (k == 1 || k == 4 || k == MS_STREAMS) return k;
+    if (k == 1 || k == 4 || k == 6 || k == 8) return k;
   }
   const char* q = getenv("GPU_MAX_HW_QUEUES");
-  return (q && atoi(q) >= MS_STREAMS + 1) ? MS_STREAMS : 4;
+  const int hwq = q ? atoi(q) : 4;
+  return hwq >= 9 ? 8 : hwq >= 7 ? 6 : 4;
 }
 
 // Issues the factorisation's stream program: the extra streams first wait for
@@ -737,8 +741,8 @@ static hipError_t launch_stream_program(hm_dataset* ds, const DevData& D, hipStr
   DevData Dm = D;
   Dm.order = ds->d_morder;
   const int ns = g.nstreams;
-  const int32_t* grid = ns == MS_STREAMS ? MS_GRID6 : MS_GRID4;
-  const int32_t* slot = ns == MS_STREAMS ? MS_SLOT_BASE6 : MS_SLOT_BASE4;
+  const int32_t* grid = ns == 8 ? MS_GRID8 : ns == 6 ? MS_GRID6 : MS_GRID4;
+  const int32_t* slot = ns == 8 ? MS_SLOT_BASE8 : ns == 6 ? MS_SLOT_BASE6 : MS_SLOT_BASE4;
   hipStream_t sx[MS_STREAMS];
   sx[0] = st;
   for (int s = 1; s < ns; ++s) sx[s] = ds->xs[s - 1];

@@ -1080,7 +1080,7 @@ namespace hm {
 // granularity).  Launches are then issued in order of simulated start.
 void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double ovh,
                           bool fused, int nstreams, StreamProgram& out) {
-  if (nstreams != 4 && nstreams != MS_STREAMS) throw std::logic_error("stream program: 4 or MS_STREAMS streams");
+  if (nstreams != 4 && nstreams != 6 && nstreams != 8) throw std::logic_error("stream program: 4, 6 or 8 streams");
   const int32_t nfac = (int32_t)p.tasks.size();
   const int32_t nt = nfac + (fused ? (int32_t)p.ftasks.size() : 0);
   if ((int32_t)dur.size() != nt) throw std::logic_error("one duration per task");

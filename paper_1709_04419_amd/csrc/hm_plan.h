@@ -218,21 +218,22 @@ void schedule_by_durations(const Plan& p, const std::vector<double>& dur, std::v
 // Factorisation on several streams.  Task classes: (0) every task not named
 // below, (1) the big blocks' flush steps (TASK_TS_*), (2) low-rank flushes of
 // blocks above MS_LONG_ROWS rows or columns.  MS_STREAM_CLASS gives each
-// stream its class: classes 0 and 1 have two streams each, running levels built
-// as in schedule_by_durations (a free stream of the class takes the most
-// critical ready tasks and every ready task no longer than the longest of
-// them, so the second stream picks up what the first left while it is busy);
+// stream its class: classes 0 and 1 run levels built as in
+// schedule_by_durations (a free stream of the class takes the most critical
+// ready tasks and every ready task no longer than the longest of them, so a
+// further stream of the class picks up what the first left while it is busy);
 // class 2 runs waves (a free stream takes every ready task) on two streams.
-// A program uses the first nstreams of these streams, 4 (one stream each for
-// classes 0 and 1) or MS_STREAMS.  Stream 0 is the caller's.  A launch runs
+// A program uses the first nstreams of these streams: 4 (one stream each for
+// classes 0 and 1), 6 (two each) or MS_STREAMS = 8 (three each).  Stream 0 is
+// the caller's.  A launch runs
 // tasks order[t0 .. t1) on its stream;
 // before it, its stream waits for the events waits[wait_begin .. + nwait)
 // (each recorded after an earlier launch of another stream); after it, event
 // rec (>= 0) is recorded.  The launches are listed in the order the host issues
 // them; every dependency of a task is met by an earlier launch of its own
 // stream or by such a wait.
-constexpr int MS_STREAMS = 6;
-constexpr int8_t MS_STREAM_CLASS[MS_STREAMS] = {0, 1, 2, 2, 0, 1};
+constexpr int MS_STREAMS = 8;
+constexpr int8_t MS_STREAM_CLASS[MS_STREAMS] = {0, 1, 2, 2, 0, 1, 0, 1};
 constexpr int MS_LONG_ROWS = 128;
 struct MSLaunch {
   int8_t stream;

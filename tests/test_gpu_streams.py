@@ -1,7 +1,7 @@
 """GPU test of the factorisation on several streams (hm_tune_schedule builds a
 stream program: the big blocks' flush steps, the long low-rank flushes and the
-rest on their own streams, cross-stream dependencies as events; four or six
-streams, forced here with HMLIK_STREAMS whatever the hardware queues).  Every task
+rest on their own streams, cross-stream dependencies as events; four, six or
+eight streams, forced here with HMLIK_STREAMS whatever the hardware queues).  Every task
 runs on the same inputs as in the level schedule, so the evaluation is
 bitwise equal before and after tuning, with and without the extra streams,
 and over repeated evaluations; and it still agrees with the oracle.
@@ -45,7 +45,7 @@ def test_stream_program_is_bitwise_equal(n, leaf):
             del os.environ["HMLIK_SINGLE_STREAM"]
         single = _vals(ds.loglik(THETA, NUGGET, EPS))
         multi = []
-        for k in ("4", "6"):
+        for k in ("4", "6", "8"):
             os.environ["HMLIK_STREAMS"] = k
             try:
                 ds.tune_schedule(THETA, NUGGET, EPS)
@@ -74,7 +74,7 @@ def test_fused_solve_edge_cases():
         ref = hmlik.Dataset(ctx, P, leaf, 2.0)   # never tuned: separate solve
         ds = hmlik.Dataset(ctx, P, leaf, 2.0)
         ds.set_z(Z1)
-        os.environ["HMLIK_STREAMS"] = "6"
+        os.environ["HMLIK_STREAMS"] = "8"
         try:
             ds.tune_schedule(THETA, NUGGET, EPS)
         finally:

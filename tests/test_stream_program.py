@@ -139,10 +139,10 @@ int main(int argc, char** argv) {
   }
   const long unmet = fused ? unmet_reads(t, p, true) : -1, unmet_control = fused ? unmet_reads(t, p, false) : -1;
   printf("{\"unmet_reads\": %ld, \"unmet_reads_control\": %ld, ", unmet, unmet_control);
-  printf("\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d, %d, %d], "
+  printf("\"tasks\": %d, \"factor_tasks\": %d, \"order\": %zu, \"launches\": %zu, \"per_stream\": [%d, %d, %d, %d, %d, %d, %d, %d], "
          "\"waits\": %d, \"events\": %d, \"dropped_tried\": %d, \"dropped_rejected\": %d, \"swap_rejected\": %d, "
          "\"early_rejected\": %d, \"fused_launches\": %d}\n", nt, nfac, g.order.size(), g.launches.size(),
-         per[0], per[1], per[2], per[3], per[4], per[5], waits_total, g.nevents, dropped_tried, dropped_ok,
+         per[0], per[1], per[2], per[3], per[4], per[5], per[6], per[7], waits_total, g.nevents, dropped_tried, dropped_ok,
          swapped_rejected, early_rejected, fused_launches);
   return 0;
 }
@@ -162,7 +162,7 @@ def harness(tmp_path_factory):
     return d, exe
 
 
-@pytest.mark.parametrize("nstreams", [4, 6])
+@pytest.mark.parametrize("nstreams", [4, 6, 8])
 @pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("n,leaf,seed", [(3000, 32, 1), (12000, 64, 2)])
 def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed, fused, nstreams):
@@ -174,12 +174,12 @@ def test_stream_program_valid_and_validator_strict(harness, n, leaf, seed, fused
     r = json.loads(out.stdout.strip().splitlines()[-1])
     assert r["order"] == r["tasks"]
     assert sum(r["per_stream"]) == r["launches"]
-    # general levels (0, and 4 of six), flush steps (1, and 5 of six), waves (2, 3)
+    # general levels (0, 4, 6), flush steps (1, 5, 7), waves (2, 3); a program
+    # uses the first nstreams streams
     ps = r["per_stream"]
     assert ps[0] > 0 and ps[2] + ps[3] > 0
-    if nstreams == 4:
-        assert ps[4] == 0 and ps[5] == 0
-    else:
+    assert all(v == 0 for v in ps[nstreams:])
+    if nstreams > 4:
         assert ps[4] > 0
     assert r["waits"] > 0 and r["events"] > 0
     # every wait the builder emits is needed: removing any one breaks a dependency
