@@ -250,7 +250,7 @@ struct StreamProgram {
   double modelled_seconds = 0;   // makespan of the simulation that built it
 };
 // Tasks of the program: the factorisation's (p.tasks) and, when fused, the
-// data solve's (p.ftasks, ids from p.tasks.size(); they run on stream 0); dur
+// data solve's (p.ftasks, ids from p.tasks.size(); class 0, the general tasks); dur
 // holds one duration per task of the program.
 void build_stream_program(const Tree& t, const Plan& p, const std::vector<double>& dur, double launch_overhead,
                           bool fused, int nstreams, StreamProgram& out);
