@@ -705,13 +705,26 @@ static hm_status finish_factor(hm_dataset* ds) {
 // each.  Six: streams 0 and 4 (general levels) 128 each, 1 and 5 (flush
 // steps) and 2, 3 (waves) 64 each.  Eight: streams 0, 4, 6 (general levels)
 // 80 each, 1, 5, 7 (flush steps) 48 each, 2, 3 (waves) 64 each.
-static const int32_t MS_GRID4[4] = {256, 128, 64, 64};
-static const int32_t MS_SLOT_BASE4[4] = {0, 256, 384, 448};
-static const int32_t MS_GRID6[6] = {128, 64, 64, 64, 128, 64};
-static const int32_t MS_SLOT_BASE6[6] = {0, 128, 192, 256, 320, 448};
-static const int32_t MS_GRID8[8] = {80, 48, 64, 64, 80, 48, 80, 48};
-static const int32_t MS_SLOT_BASE8[8] = {0, 80, 128, 192, 256, 336, 384, 464};
-static_assert(MS_STREAMS == 8 && 448 + 64 <= NSLOTS && 464 + 48 <= NSLOTS, "stream slot ranges");
+static constexpr int32_t MS_GRID4[4] = {256, 128, 64, 64};
+static constexpr int32_t MS_SLOT_BASE4[4] = {0, 256, 384, 448};
+static constexpr int32_t MS_GRID6[6] = {128, 64, 64, 64, 128, 64};
+static constexpr int32_t MS_SLOT_BASE6[6] = {0, 128, 192, 256, 320, 448};
+static constexpr int32_t MS_GRID8[8] = {80, 48, 64, 64, 80, 48, 80, 48};
+static constexpr int32_t MS_SLOT_BASE8[8] = {0, 80, 128, 192, 256, 336, 384, 464};
+// every stream's slot range [base, base + grid) inside the NSLOTS slots and
+// disjoint from every other stream's
+static constexpr bool slot_ranges_ok(const int32_t* grid, const int32_t* base, int ns) {
+  for (int a = 0; a < ns; ++a) {
+    if (grid[a] < 1 || base[a] < 0 || base[a] + grid[a] > NSLOTS) return false;
+    for (int b = 0; b < ns; ++b)
+      if (a != b && base[a] < base[b] + grid[b] && base[b] < base[a] + grid[a]) return false;
+  }
+  return true;
+}
+static_assert(MS_STREAMS == 8, "stream tables for 4, 6 and 8 streams");
+static_assert(slot_ranges_ok(MS_GRID4, MS_SLOT_BASE4, 4) && slot_ranges_ok(MS_GRID6, MS_SLOT_BASE6, 6) &&
+                  slot_ranges_ok(MS_GRID8, MS_SLOT_BASE8, 8),
+              "stream slot ranges");
 
 // Streams of the program hm_tune_schedule builds: HMLIK_STREAMS (1, 4, 6 or
 // 8) if set; otherwise as many as the HIP runtime has hardware queues for
