@@ -12,7 +12,14 @@ the task graph of real point sets:
   * distinct buffers do not overlap, and sharing happens (the check is not
     vacuous);
   * a control: with the sharing dependencies ignored the same check finds
-    write-after-read hazards.
+    write-after-read hazards;
+  * read after write on the factor's blocks: every block a task reads (the
+    factors of its update terms, the diagonal leaf of a triangular solve, the
+    L blocks of a solve program, the blocks of a term product) is finished by
+    its last writer among the task's ancestors; a control without the term
+    products' dependencies finds reads that would race;
+  * the data's forward solve: any two of its tasks whose rows of W conflict
+    (one writes rows the other reads or writes) are ordered by dependencies.
 Compiled into a small host harness (g++)."""
 import json
 import os
@@ -120,6 +127,127 @@ int main(int argc, char** argv) {
   }
   long terms_with_buf = 0;
   for (const TermDef& d : p.terms) terms_with_buf += d.rows > 0;
+  // read after write on the factor's blocks: every block a task reads is
+  // finished (its last writer ran) before the task starts
+  const int32_t nb = (int32_t)t.bk.size();
+  std::vector<int32_t> last(nb, -1);
+  auto writes_block = [](int8_t kind) {
+    return kind == TASK_DIAG || kind == TASK_OFFD || kind == TASK_LR || kind == TASK_TS_A || kind == TASK_TS_B ||
+           kind == TASK_TS_C || kind == TASK_SOLVE_SEQ || kind == TASK_SOLVE_MV;
+  };
+  for (int32_t i = 0; i < nt; ++i)
+    if (writes_block(p.tasks[i].kind) && p.tasks[i].obj >= 0) last[p.tasks[i].obj] = i;
+  auto leaves_rows = [&](int32_t b, int64_t lo, int64_t hi, std::vector<int32_t>& out) {
+    for (int32_t q = p.sub_begin[b]; q < p.sub_end[b]; ++q) {
+      const Block& l = t.bk[p.sub_leaves[q]];
+      if (l.r0 < hi && l.r0 + l.m > lo) out.push_back(p.sub_leaves[q]);
+    }
+  };
+  auto inst_reads = [&](const TermInst& in, std::vector<int32_t>& out) {
+    const TermDef& d = p.terms[in.term];
+    if (d.kind == TK_LRA) out.push_back(d.A);
+    else if (d.kind == TK_LRB) out.push_back(d.B);
+    else { out.push_back(d.A); out.push_back(d.B); }
+  };
+  auto reads_of = [&](int32_t i, std::vector<int32_t>& out) {
+    out.clear();
+    const Task& k = p.tasks[i];
+    switch (k.kind) {
+      case TASK_TERM: case TASK_TERM_ROWS: {
+        const TermDef& d = p.terms[k.obj];
+        const int32_t lrb = d.kind == TK_LRA ? d.A : d.B, hb = d.kind == TK_LRA ? d.B : d.A;
+        int64_t lo = 0, hi = t.n;
+        if (k.kind == TASK_TERM_ROWS) { lo = t.cl[k.a1].begin; hi = t.cl[k.a1].end; }
+        out.push_back(lrb);
+        leaves_rows(hb, lo, hi, out);
+        break;
+      }
+      case TASK_DIAG: case TASK_OFFD: case TASK_LR:
+        for (int32_t q = 0; q < k.ninst; ++q) inst_reads(p.insts[k.inst_begin + q], out);
+        if (k.kind == TASK_OFFD) out.push_back(k.diag);
+        if (k.kind == TASK_LR && k.a0 == 1) leaves_rows(t.diag_of[k.diag], 0, t.n, out);
+        break;
+      case TASK_TS_A: case TASK_TS_B: case TASK_TS_C:
+        if (k.a0 >= 1 && k.a0 <= k.ninst) inst_reads(p.insts[k.inst_begin + k.a0 - 1], out);
+        break;
+      case TASK_SOLVE_SEQ:
+        for (int32_t q = p.sop_begin[k.a0]; q < p.sop_begin[k.a0 + 1]; ++q) leaves_rows(p.sops[q].blk, 0, t.n, out);
+        break;
+      case TASK_SOLVE_MV:
+        leaves_rows(k.a0, t.cl[k.a1].begin, t.cl[k.a1].end, out);
+        break;
+      default: break;
+    }
+  };
+  // ancestors again, optionally without the dependencies of the term products
+  // (the control: their reads of the factor blocks are then unordered)
+  auto block_raw = [&](bool term_deps, long& viol, long& checked) {
+    const size_t words = ((size_t)nt + 63) / 64;
+    std::vector<uint64_t> anc((size_t)nt * words, 0);
+    for (int32_t i = 0; i < nt; ++i) {
+      const Task& k = p.tasks[i];
+      if (!term_deps && (k.kind == TASK_TERM || k.kind == TASK_TERM_ROWS)) continue;
+      uint64_t* ai = &anc[(size_t)i * words];
+      for (int32_t q = 0; q < k.ndeps; ++q) {
+        const int32_t d = p.deps[k.dep_begin + q];
+        const uint64_t* ad = &anc[(size_t)d * words];
+        for (size_t w = 0; w < words; ++w) ai[w] |= ad[w];
+        ai[d / 64] |= 1ull << (d % 64);
+      }
+    }
+    viol = checked = 0;
+    std::vector<int32_t> rb;
+    for (int32_t i = 0; i < nt; ++i) {
+      reads_of(i, rb);
+      for (int32_t b : rb) {
+        if (b == p.tasks[i].obj || last[b] < 0) continue;
+        ++checked;
+        viol += !((anc[(size_t)i * words + last[b] / 64] >> (last[b] % 64)) & 1);
+      }
+    }
+  };
+  // the data solve (tasks on the rows of W): two tasks whose row ranges
+  // conflict (one writes what the other reads or writes) are ordered
+  const int32_t nf = (int32_t)p.ftasks.size();
+  std::vector<std::vector<uint64_t>> fanc(nf, std::vector<uint64_t>(((size_t)nf + 63) / 64, 0));
+  for (int32_t i = 0; i < nf; ++i) {
+    const Task& k = p.ftasks[i];
+    for (int32_t q = 0; q < k.ndeps; ++q) {
+      const int32_t d = p.fdeps[k.dep_begin + q] - nt;   // factor tasks: negative, skipped
+      if (d < 0) continue;
+      for (size_t w = 0; w < fanc[i].size(); ++w) fanc[i][w] |= fanc[d][w];
+      fanc[i][d / 64] |= 1ull << (d % 64);
+    }
+  }
+  auto wrange = [&](const Task& k, int64_t& w0, int64_t& w1, int64_t& r0, int64_t& r1) {
+    if (k.kind == TASK_SOLVE_SEQ) {
+      w0 = r0 = t.cl[k.a0].begin;
+      w1 = r1 = t.cl[k.a0].end;
+    } else {
+      w0 = t.cl[k.a1].begin;
+      w1 = t.cl[k.a1].end;
+      r0 = t.bk[k.a0].c0;
+      r1 = r0 + t.bk[k.a0].n;
+    }
+  };
+  long w_conflicts = 0, w_unordered = 0;
+  for (int32_t i = 0; i < nf; ++i)
+    for (int32_t j = i + 1; j < nf; ++j) {
+      int64_t wi0, wi1, ri0, ri1, wj0, wj1, rj0, rj1;
+      wrange(p.ftasks[i], wi0, wi1, ri0, ri1);
+      wrange(p.ftasks[j], wj0, wj1, rj0, rj1);
+      auto meet = [](int64_t a0, int64_t a1, int64_t b0, int64_t b1) { return a0 < b1 && b0 < a1; };
+      if (!(meet(wi0, wi1, wj0, wj1) || meet(wi0, wi1, rj0, rj1) || meet(wj0, wj1, ri0, ri1))) continue;
+      ++w_conflicts;
+      const bool ordered = ((fanc[j][i / 64] >> (i % 64)) & 1) || ((fanc[i][j / 64] >> (j % 64)) & 1);
+      w_unordered += !ordered;
+    }
+  printf("{\"solve_conflicts\": %ld, \"solve_unordered\": %ld}\n", w_conflicts, w_unordered);
+  long braw, bchecked, braw0, bchecked0;
+  block_raw(true, braw, bchecked);
+  block_raw(false, braw0, bchecked0);
+  printf("{\"block_reads_checked\": %ld, \"block_raw\": %ld, \"block_raw_without_term_deps\": %ld}\n", bchecked,
+         braw, braw0);
   printf("{\"tasks\": %d, \"terms_with_buffer\": %ld, \"buffers\": %zu, \"shared_pairs\": %ld, \"raw\": %ld, "
          "\"war\": %ld, \"overlaps\": %ld, \"war_without_sharing_deps\": %ld, \"pool_end\": %lld, "
          "\"term_pool\": %lld}\n", nt, terms_with_buf, ext.size(), pairs, raw, war, overlaps, war0,
@@ -149,7 +277,16 @@ def test_term_buffer_hazards(harness, n, leaf):
     wl.basin_clusters(n, 41).astype(np.float64).tofile(pts)
     out = subprocess.run([str(exe), str(pts), str(n), str(leaf)], capture_output=True, text=True, timeout=600,
                          check=True)
-    r = json.loads(out.stdout.strip().splitlines()[-1])
+    lines = out.stdout.strip().splitlines()
+    solve = json.loads(lines[-3])
+    # the data solve's tasks that touch the same rows of W are ordered
+    assert solve["solve_conflicts"] > 0 and solve["solve_unordered"] == 0
+    blocks = json.loads(lines[-2])
+    r = json.loads(lines[-1])
+    # every block read follows the block's last writer; the control (term
+    # products without their dependencies) finds reads that would not
+    assert blocks["block_reads_checked"] > 0 and blocks["block_raw"] == 0
+    assert blocks["block_raw_without_term_deps"] > 0
     assert r["raw"] == 0 and r["war"] == 0 and r["overlaps"] == 0
     assert r["shared_pairs"] > 0 and r["buffers"] < r["terms_with_buffer"]
     assert r["war_without_sharing_deps"] > 0
